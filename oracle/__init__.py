@@ -1,0 +1,132 @@
+"""Float64 CPU oracle for the time-varying LP filter (paper Sec. 3.2, Eqs. 6, 12, 13).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  The product
+library never loads it and shares no code with it.
+
+``lp_forward`` / ``lp_backward`` call the plain C routines in
+``tvlp_oracle.c`` (built with gcc -O2 -ffp-contract=off -fopenmp, no fast
+math).  Inputs are normally the same float32 arrays the GPU path reads; they
+are promoted exactly to float64 here (float64 inputs are taken as they are,
+for finite-difference checks) and results come back in float64.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tvlp_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+GCC_FLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+             "-shared", "-fPIC"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle in place; returns the library path."""
+    global _lib
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", *GCC_FLAGS, "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+        _lib = None
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        lib.oracle_lp_forward.argtypes = [I64, I64, ctypes.c_int, P, P, P, P, P]
+        lib.oracle_lp_forward.restype = None
+        lib.oracle_lp_backward.argtypes = [I64, I64, ctypes.c_int, P, P, P, P, P, P, P, P]
+        lib.oracle_lp_backward.restype = None
+        lib.oracle_num_threads.argtypes = []
+        lib.oracle_num_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _f64(x: np.ndarray) -> np.ndarray:
+    """Exact promotion of float32 (or pass-through of float64) to contiguous float64."""
+    if x.dtype not in (np.float32, np.float64):
+        raise TypeError(f"oracle inputs must be float32 or float64, got {x.dtype}")
+    return np.ascontiguousarray(x, dtype=np.float64)
+
+
+def _ptr(x: Optional[np.ndarray]):
+    return None if x is None else x.ctypes.data_as(ctypes.c_void_p)
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
+
+
+def lp_forward(e: np.ndarray, a: np.ndarray, zi: Optional[np.ndarray] = None):
+    """s = LP_a(e) in float64.  e [B,T], a [B,T,M] (f32 or f64), zi [B,M] = s(-1..-M).
+
+    Returns (s [B,T] f64, zf [B,M] f64 with zf[b, j-1] = s(T-j)).
+    """
+    e = _f64(e)
+    a = _f64(a)
+    B, T = e.shape
+    M = a.shape[2]
+    assert a.shape == (B, T, M)
+    zi64 = None if zi is None else np.ascontiguousarray(zi, dtype=np.float64).reshape(B, M)
+    s = np.empty((B, T), np.float64)
+    zf = np.empty((B, M), np.float64)
+    _load().oracle_lp_forward(B, T, M, _ptr(e), _ptr(a), _ptr(zi64), _ptr(s), _ptr(zf))
+    return s, zf
+
+
+def lp_backward(g: np.ndarray, a: np.ndarray, s: np.ndarray, zi: Optional[np.ndarray] = None,
+                need_grad_a: bool = True, need_grad_zi: bool = False):
+    """Adjoint of lp_forward in float64 (pull form of Eq. 12, then Eq. 13).
+
+    g [B,T] upstream gradient, a [B,T,M] (f32 or f64), s [B,T] f64 from lp_forward.
+    Returns (grad_e [B,T], grad_a [B,T,M] or None, grad_zi [B,M] or None), all f64.
+    """
+    g = _f64(g)
+    a = _f64(a)
+    B, T = g.shape
+    M = a.shape[2]
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    zi64 = None if zi is None else np.ascontiguousarray(zi, dtype=np.float64).reshape(B, M)
+    ge = np.empty((B, T), np.float64)
+    ga = np.empty((B, T, M), np.float64) if need_grad_a else None
+    gz = np.empty((B, M), np.float64) if need_grad_zi else None
+    _load().oracle_lp_backward(B, T, M, _ptr(g), _ptr(a), _ptr(zi64), _ptr(s), _ptr(ge),
+                               _ptr(ga), _ptr(gz), None)
+    return ge, ga, gz
+
+
+def lp_forward_varlen(e: np.ndarray, a: np.ndarray, offsets: np.ndarray):
+    """Packed variable-length batch: sequence b spans [offsets[b], offsets[b+1])."""
+    s = np.empty(e.shape, np.float64)
+    for b in range(len(offsets) - 1):
+        lo, hi = int(offsets[b]), int(offsets[b + 1])
+        if hi > lo:
+            s[lo:hi] = lp_forward(e[None, lo:hi], a[None, lo:hi])[0][0]
+    return s
+
+
+def lp_backward_varlen(g: np.ndarray, a: np.ndarray, s: np.ndarray, offsets: np.ndarray):
+    ge = np.empty(g.shape, np.float64)
+    ga = np.empty(a.shape, np.float64)
+    for b in range(len(offsets) - 1):
+        lo, hi = int(offsets[b]), int(offsets[b + 1])
+        if hi > lo:
+            r = lp_backward(g[None, lo:hi], a[None, lo:hi], s[None, lo:hi])
+            ge[lo:hi] = r[0][0]
+            ga[lo:hi] = r[1][0]
+    return ge, ga

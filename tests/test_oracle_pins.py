@@ -1,0 +1,93 @@
+"""The float64 oracle against what the paper and mathematics fix (CPU only)."""
+import numpy as np
+import pytest
+
+import oracle
+from tests import pins
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built_oracle():
+    oracle.build(force=False)
+
+
+@pytest.mark.parametrize("pin", pins.ALL_PINS, ids=lambda p: p.__name__)
+def test_oracle_pin(pin):
+    pin(oracle.lp_forward, oracle.lp_backward)
+
+
+# --------------------------------------------------------------------------
+# Planted mistakes: each plausible error in the oracle must fail some pin.
+# The mistakes are planted by wrapping the CPU oracle, never on a GPU.
+
+def _fwd_coef_time_shift(e, a, zi=None):
+    # uses a(t-1) for output t instead of a(t)
+    a2 = np.array(a, np.float64, copy=True)
+    a2[:, 1:] = a2[:, :-1].copy()
+    return oracle.lp_forward(e, a2, zi)
+
+
+def _fwd_dropped_last_tap(e, a, zi=None):
+    a2 = np.array(a, np.float64, copy=True)
+    a2[..., -1] = 0.0
+    return oracle.lp_forward(e, a2, zi)
+
+
+def _fwd_sign_flip(e, a, zi=None):
+    a2 = -np.array(a, np.float64)
+    z2 = None if zi is None else np.asarray(zi)
+    return oracle.lp_forward(e, a2, z2)
+
+
+def _fwd_reversed_taps(e, a, zi=None):
+    # a_i paired with s(t-(M+1-i)) — a transposed operand
+    return oracle.lp_forward(e, np.array(a, np.float64)[..., ::-1].copy(), zi)
+
+
+def _bwd_unshifted(g, a, s, zi=None, need_grad_a=True, need_grad_zi=False):
+    # adjoint that forgets the shift ahat_i(t) = a_i(t+i) and uses a_i(t)
+    a64 = np.array(a, np.float64)
+    ghat = oracle.lp_forward(np.array(g, np.float64)[:, ::-1].copy(), a64[:, ::-1].copy())[0][:, ::-1]
+    ge = ghat.copy()
+    B, T, M = a64.shape
+    ga = np.zeros((B, T, M))
+    for i in range(1, M + 1):
+        ga[:, i:, i - 1] = -ge[:, i:] * s[:, :-i] if i < T else 0.0
+    return ge, ga, (np.zeros((B, M)) if need_grad_zi else None)
+
+
+def _bwd_wrong_lag(g, a, s, zi=None, need_grad_a=True, need_grad_zi=False):
+    ge, ga, gz = oracle.lp_backward(g, a, s, zi, True, need_grad_zi)
+    B, T, M = ga.shape
+    ga2 = np.zeros_like(ga)
+    for i in range(1, M + 1):  # pairs ghat(t) with s(t-i+1)
+        ga2[:, i - 1:, i - 1] = -ge[:, i - 1:] * s[:, :T - i + 1]
+    return ge, ga2, gz
+
+
+def _bwd_grad_a_sign(g, a, s, zi=None, need_grad_a=True, need_grad_zi=False):
+    ge, ga, gz = oracle.lp_backward(g, a, s, zi, True, need_grad_zi)
+    return ge, -ga, gz
+
+
+MUTANTS = {
+    "coef_time_shift": (_fwd_coef_time_shift, oracle.lp_backward),
+    "dropped_last_tap": (_fwd_dropped_last_tap, oracle.lp_backward),
+    "sign_flip": (_fwd_sign_flip, oracle.lp_backward),
+    "reversed_taps": (_fwd_reversed_taps, oracle.lp_backward),
+    "bwd_unshifted": (oracle.lp_forward, _bwd_unshifted),
+    "grad_a_wrong_lag": (oracle.lp_forward, _bwd_wrong_lag),
+    "grad_a_sign": (oracle.lp_forward, _bwd_grad_a_sign),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_is_caught(name):
+    fwd, bwd = MUTANTS[name]
+    caught = []
+    for pin in pins.ALL_PINS:
+        try:
+            pin(fwd, bwd)
+        except (AssertionError, ValueError, IndexError, FloatingPointError):
+            caught.append(pin.__name__)
+    assert caught, f"no pin caught the planted mistake {name}"
