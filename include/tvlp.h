@@ -1,0 +1,140 @@
+/*
+ * tvlp.h — C ABI of the MI355X (gfx950) time-varying linear-prediction filter.
+ *
+ * The operation (paper Sec. 3.2, Eq. 6): for every sequence b,
+ *     s(t) = e(t) - sum_{i=1..M} a_i(t) s(t-i),      t = 0 .. T-1,
+ * with zero initial conditions s(t) = e(t) = 0 for t < 0 (Sec. 2.2), unless an
+ * initial state zi is given.  The coefficient row a(t) belongs to the output
+ * time t.  Its adjoint (Eqs. 12-13): with g(t) = dL/ds(t),
+ *     ghat(t) = g(t) - sum_{i=1..M} a_i(t+i) ghat(t+i),   ghat(t >= T) = 0,
+ *     dL/de(t) = ghat(t),      dL/da_i(t) = -ghat(t) s(t-i).
+ *
+ * Layout (all row-major, contiguous):
+ *   e, s, g, grad_e  float32 [B][T]        (packed [N] for the varlen calls)
+ *   a, grad_a        float32 [B][T][M]     (packed [N][M])
+ *   zi, zf, grad_zi  float64 [B][M]        zi[b][j-1] = s(-j), zf[b][j-1] = s(T-j)
+ *   offsets          int64   [B+1]         device array, offsets[0] = 0, non-decreasing
+ * Every pointer passed to lp_forward* / lp_backward* is a DEVICE pointer on the
+ * plan's device; `stream` is a hipStream_t (NULL = default stream).  Results
+ * are float32; all internal arithmetic (recursions, chunk transitions, carried
+ * states) is float64.
+ *
+ * Ownership: the caller owns every buffer it passes; the library never frees
+ * caller memory.  A plan owns a device workspace that grows on demand
+ * (lp_plan_reserve sizes it up front, which callers that capture launches into
+ * a hipGraph must do).  Calls are asynchronous on `stream`.
+ *
+ * Errors: every call returns an int status (LP_OK = 0, negative on error) and
+ * never throws.  lp_last_error() returns a thread-local message for the most
+ * recent failure.  Invalid arguments (B < 1, T < 1, M outside [1, 64], NULL
+ * required pointers, an unsupported order for the chunked kernels) give
+ * LP_EINVAL and launch nothing; device failures give LP_EDEVICE.  Non-finite
+ * inputs are not errors: they propagate through the recursion.
+ */
+#ifndef TVLP_H
+#define TVLP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lp_plan lp_plan;
+
+enum {
+    LP_OK = 0,
+    LP_PENDING = 1,
+    LP_EINVAL = -1,
+    LP_ENOMEM = -2,
+    LP_EDEVICE = -3,
+    LP_ENOTFOUND = -4,
+    LP_EBUDGET = -5
+};
+
+/* Plan flags. */
+enum {
+    LP_FLAG_NONE = 0
+};
+
+/* Library version string, e.g. "tvlp 0.1 gfx950". */
+const char *lp_version(void);
+
+/* Thread-local description of the last non-OK return on this thread. */
+const char *lp_last_error(void);
+
+/* Orders M for which the chunked kernels are compiled; returns the count and
+ * writes up to `cap` of them to `out` (which may be NULL). */
+int lp_supported_orders(int *out, int cap);
+
+/* Create a plan for filter order M on `device`.  The plan selects the chunk
+ * length L (a multiple of M, at least M) used by the chunked kernels. */
+int lp_plan_create(lp_plan **out, int device, int M, int flags);
+int lp_plan_destroy(lp_plan *p);
+
+/* Override / query the chunk length.  L must be a positive multiple of M. */
+int lp_plan_set_chunk(lp_plan *p, int L);
+int lp_plan_get_chunk(const lp_plan *p);
+
+/* Grow the plan's workspace for a batch of B sequences of length T (or, for
+ * varlen use, a total of N samples in B sequences: pass T = ceil(N / B) + L). */
+int lp_plan_reserve(lp_plan *p, int64_t B, int64_t T);
+
+/* Bytes of the `saved` buffer that lp_forward fills for lp_backward: the
+ * float64 chunk-entry states and chunk transition matrices (Sec. 3.2 method,
+ * chunked form; the backward recomputes s(t) per chunk from them). */
+size_t lp_saved_bytes(const lp_plan *p, int64_t B, int64_t T);
+size_t lp_saved_bytes_varlen(const lp_plan *p, int64_t B, int64_t N);
+
+/*
+ * Chunked forward (Eq. 6).  e [B,T], a [B,T,M] -> s [B,T].
+ * zi: optional [B,M] initial state (NULL = zero initial conditions).
+ * zf: optional [B,M] final state out.
+ * saved: optional, lp_saved_bytes(p,B,T) bytes, filled for lp_backward; when
+ *        NULL the plan's workspace holds the intermediates.
+ */
+int lp_forward(lp_plan *p, int64_t B, int64_t T,
+               const float *e, const float *a, const double *zi,
+               float *s, double *zf, void *saved, void *stream);
+
+/*
+ * Chunked adjoint (Eqs. 12-13).  g [B,T] = dL/ds; a, e, zi as given to the
+ * lp_forward call that filled `saved` (required).  s: the forward output, or
+ * NULL to recompute s(t) chunk by chunk from `saved`.  Outputs (each may be
+ * NULL if not wanted): grad_e [B,T], grad_a [B,T,M], grad_zi [B,M].
+ */
+int lp_backward(lp_plan *p, int64_t B, int64_t T,
+                const float *g, const float *a, const float *e, const double *zi,
+                const float *s, const void *saved,
+                float *grad_e, float *grad_a, double *grad_zi, void *stream);
+
+/* Variable-length batches: sequence b occupies samples [offsets[b], offsets[b+1])
+ * of the packed arrays e [N], a [N,M], s [N] (N = offsets[B]).  `offsets` is a
+ * device array; `N` must equal offsets[B].  Chunk boundaries are relative to
+ * each sequence's own start, so a sequence's result does not depend on what
+ * else is in the batch. */
+int lp_forward_varlen(lp_plan *p, int64_t B, const int64_t *offsets, int64_t N,
+                      const float *e, const float *a, const double *zi,
+                      float *s, double *zf, void *saved, void *stream);
+int lp_backward_varlen(lp_plan *p, int64_t B, const int64_t *offsets, int64_t N,
+                       const float *g, const float *a, const float *e, const double *zi,
+                       const float *s, const void *saved,
+                       float *grad_e, float *grad_a, double *grad_zi, void *stream);
+
+/*
+ * Sequential baseline: one GPU thread per sequence runs Eq. 6 (forward) and
+ * the adjoint of Eqs. 12-13 (backward, which reads the stored forward output
+ * s) straight through, float64 arithmetic, float32 I/O.  Same layouts as above.
+ */
+int lp_forward_plain(int M, int64_t B, int64_t T, const float *e, const float *a,
+                     const double *zi, float *s, double *zf, void *stream);
+int lp_backward_plain(int M, int64_t B, int64_t T, const float *g, const float *a,
+                      const double *zi, const float *s,
+                      float *grad_e, float *grad_a, double *grad_zi, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TVLP_H */

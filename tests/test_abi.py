@@ -1,0 +1,50 @@
+"""The C-ABI library loads and exports what include/tvlp.h declares (CPU only, no compute)."""
+import ctypes
+
+import pytest
+
+from paper_2406_05128_amd import _lib
+
+
+def test_library_exports_every_header_symbol():
+    lib = _lib.load()
+    declared = _lib.header_symbols()
+    assert "lp_forward" in declared and "lp_backward" in declared
+    missing = [n for n in declared if not hasattr(lib, n)]
+    assert not missing, missing
+    # the binding knows every declared call
+    assert set(declared) <= set(_lib.SIGNATURES), set(declared) - set(_lib.SIGNATURES)
+
+
+def test_version_and_orders():
+    assert "gfx950" in _lib.version()
+    orders = _lib.supported_orders()
+    for m in (1, 2, 16, 22, 32):
+        assert m in orders
+
+
+@pytest.mark.parametrize("M", [0, 65, -3])
+def test_plan_rejects_bad_order(M):
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    rc = lib.lp_plan_create(ctypes.byref(h), 0, M, 0)
+    assert rc == _lib.LP_EINVAL
+    assert "order" in _lib.last_error()
+
+
+def test_plan_rejects_uncompiled_order():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    assert lib.lp_plan_create(ctypes.byref(h), 0, 5, 0) == _lib.LP_EINVAL
+    assert "compiled" in _lib.last_error()
+
+
+def test_null_plan_and_bad_sizes_are_errors():
+    lib = _lib.load()
+    assert lib.lp_saved_bytes(None, 4, 100) == 0
+    assert lib.lp_forward(None, 1, 1, None, None, None, None, None, None, None) == _lib.LP_EINVAL
+    assert lib.lp_forward_plain(0, 1, 1, None, None, None, None, None, None) == _lib.LP_EINVAL
+    assert lib.lp_forward_plain(16, 0, 1, None, None, None, None, None, None) == _lib.LP_EINVAL
+    assert lib.lp_forward_plain(16, 1, 1, None, None, None, None, None, None) == _lib.LP_EINVAL
+    assert lib.lp_backward_plain(16, 1, 1, None, None, None, None, None, None, None, None) == _lib.LP_EINVAL
+    assert lib.lp_plan_destroy(None) == _lib.LP_OK
