@@ -77,6 +77,15 @@ int lp_plan_destroy(lp_plan *p);
 int lp_plan_set_chunk(lp_plan *p, int L);
 int lp_plan_get_chunk(const lp_plan *p);
 
+/* Per-kernel timing.  When on, every kernel the plan launches is bracketed by
+ * hipEvents recorded on the launch stream.  lp_plan_timings waits for the
+ * recorded events, adds their durations to per-kernel totals and writes up to
+ * `cap` entries: names (cap x name_len chars, NUL-terminated), total
+ * milliseconds and launch counts.  Returns the number of kernels seen. */
+int lp_plan_set_timing(lp_plan *p, int on);
+int lp_plan_timings(lp_plan *p, char *names, int name_len, double *ms, int64_t *launches, int cap);
+int lp_plan_reset_timings(lp_plan *p);
+
 /* Grow the plan's workspace for a batch of B sequences of length T (or, for
  * varlen use, a total of N samples in B sequences: pass T = ceil(N / B) + L). */
 int lp_plan_reserve(lp_plan *p, int64_t B, int64_t T);

@@ -9,9 +9,16 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
+#include <vector>
 
 using namespace tvlp;
+
+struct TimingRecord {
+    const char *name;
+    hipEvent_t start, stop;
+};
 
 struct lp_plan {
     int device;
@@ -20,6 +27,9 @@ struct lp_plan {
     int flags;
     void *ws;
     size_t ws_bytes;
+    bool timing;
+    std::vector<TimingRecord> pending;
+    std::map<std::string, std::pair<double, int64_t>> totals;  // name -> (ms, launches)
 };
 
 namespace {
@@ -40,6 +50,29 @@ int check_hip(hipError_t e, const char *what) {
     if (e == hipSuccess) return LP_OK;
     return fail(LP_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
+
+// Brackets kernel launches with hipEvents on their stream when the plan's
+// timing switch is on (events are read back by lp_plan_timings).
+struct Timer {
+    lp_plan *p;
+    hipStream_t st;
+    TimingRecord cur{};
+    void begin(const char *name) {
+        if (!p || !p->timing) return;
+        cur.name = name;
+        if (hipEventCreate(&cur.start) != hipSuccess || hipEventCreate(&cur.stop) != hipSuccess) {
+            cur.name = nullptr;
+            return;
+        }
+        (void)hipEventRecord(cur.start, st);
+    }
+    void end() {
+        if (!p || !p->timing || !cur.name) return;
+        (void)hipEventRecord(cur.stop, st);
+        p->pending.push_back(cur);
+        cur.name = nullptr;
+    }
+};
 
 // Restores the caller's current device on scope exit.
 struct DeviceGuard {
@@ -165,34 +198,49 @@ struct Ops {
 
     static void forward(const Seqs &S, int64_t nch, int64_t nseq, const float *e, const float *a,
                         const double *zi, float *s, double *zf, double *xs, double *phi, double *z,
-                        hipStream_t st) {
+                        hipStream_t st, Timer &tm) {
         if (nch <= 0) return;
+        tm.begin("fwd_basis");
         hipLaunchKernelGGL((k_fwd_basis<M, BS::LPC, BS::CPL>), dim3((unsigned)ceil_div(nch, CPW)), dim3(64), 0, st,
                            S, e, a, phi, z, nch);
+        tm.end();
+        tm.begin("fwd_chain");
         hipLaunchKernelGGL((k_fwd_chain<M>), dim3((unsigned)nseq), dim3(64), 0, st, S, phi, z, zi, xs);
+        tm.end();
+        tm.begin("fwd_emit");
         hipLaunchKernelGGL((k_fwd_emit<M>), dim3((unsigned)ceil_div(nch, 64)), dim3(64), 0, st, S, e, a, xs, s,
                            zf, nch);
+        tm.end();
     }
 
     static void backward(const Seqs &S, int64_t nch, int64_t nseq, const float *g, const float *a,
                          const float *e, const float *s_in, const double *xs, const double *phi, double *q,
-                         double *yend, float *sbuf, float *ge, float *ga, double *gzi, hipStream_t st) {
+                         double *yend, float *sbuf, float *ge, float *ga, double *gzi, hipStream_t st,
+                         Timer &tm) {
         if (nch <= 0) return;
+        tm.begin("bwd_zs");
         hipLaunchKernelGGL((k_bwd_zs<M>), dim3((unsigned)ceil_div(nch, 64)), dim3(64), 0, st, S, g, a, q, nch,
                            gzi ? 1 : 0);
+        tm.end();
+        tm.begin("bwd_chain");
         hipLaunchKernelGGL((k_bwd_chain<M>), dim3((unsigned)nseq), dim3(64), 0, st, S, phi, q, yend, gzi);
+        tm.end();
         const float *s = s_in;
         if (ga && !s) {
+            tm.begin("recompute_s");
             hipLaunchKernelGGL((k_recompute_s<M>), dim3((unsigned)ceil_div(nch, 64)), dim3(64), 0, st, S, e, a,
                                xs, sbuf, nch);
+            tm.end();
             s = sbuf;
         }
+        tm.begin("bwd_emit");
         if (ga)
             hipLaunchKernelGGL((k_bwd_emit<M, true>), dim3((unsigned)ceil_div(nch, 64)), dim3(64), 0, st, S, g,
                                a, s, xs, yend, ge, ga, nch);
         else if (ge)
             hipLaunchKernelGGL((k_bwd_emit<M, false>), dim3((unsigned)ceil_div(nch, 64)), dim3(64), 0, st, S, g,
                                a, s, xs, yend, ge, ga, nch);
+        tm.end();
     }
 
     static void plain_fwd(int64_t B, int64_t T, const float *e, const float *a, const double *zi, float *s,
@@ -271,8 +319,9 @@ int forward_impl(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, 
         S.cbase = cb;
     }
     (void)nsamp;
+    Timer tm{p, st};
     dispatch(M, [&](auto ops) {
-        decltype(ops)::forward(S, nch, B, e, a, zi, s, zf, xs, phi, (double *)(ws + w.z), st);
+        decltype(ops)::forward(S, nch, B, e, a, zi, s, zf, xs, phi, (double *)(ws + w.z), st, tm);
     });
     return check_hip(hipGetLastError(), "kernel launch (forward)");
 }
@@ -305,9 +354,10 @@ int backward_impl(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N,
         S.offsets = offsets;
         S.cbase = cb;
     }
+    Timer tm{p, st};
     dispatch(M, [&](auto ops) {
         decltype(ops)::backward(S, nch, B, g, a, e, s, xs, phi, (double *)(ws + w.q), (double *)(ws + w.yend),
-                                (float *)(ws + w.sbuf), ge, ga, gzi, st);
+                                (float *)(ws + w.sbuf), ge, ga, gzi, st, tm);
     });
     return check_hip(hipGetLastError(), "kernel launch (backward)");
 }
@@ -347,6 +397,10 @@ int lp_plan_create(lp_plan **out, int device, int M, int flags) {
 
 int lp_plan_destroy(lp_plan *p) {
     if (!p) return LP_OK;
+    for (auto &r : p->pending) {
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
+    }
     if (p->ws) {
         DeviceGuard dg(p->device);
         (void)hipDeviceSynchronize();
@@ -364,6 +418,48 @@ int lp_plan_set_chunk(lp_plan *p, int L) {
 }
 
 int lp_plan_get_chunk(const lp_plan *p) { return p ? p->L : 0; }
+
+int lp_plan_set_timing(lp_plan *p, int on) {
+    if (int r = check_plan(p)) return r;
+    p->timing = on != 0;
+    return LP_OK;
+}
+
+int lp_plan_timings(lp_plan *p, char *names, int name_len, double *ms, int64_t *launches, int cap) {
+    if (int r = check_plan(p)) return r;
+    DeviceGuard dg(p->device);
+    for (auto &r : p->pending) {
+        float t = 0.f;
+        if (hipEventSynchronize(r.stop) == hipSuccess && hipEventElapsedTime(&t, r.start, r.stop) == hipSuccess) {
+            auto &acc = p->totals[r.name];
+            acc.first += t;
+            acc.second += 1;
+        }
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
+    }
+    p->pending.clear();
+    int i = 0;
+    for (auto &kv : p->totals) {
+        if (i < cap) {
+            if (names && name_len > 0) {
+                std::strncpy(names + (size_t)i * name_len, kv.first.c_str(), (size_t)name_len - 1);
+                names[(size_t)i * name_len + name_len - 1] = 0;
+            }
+            if (ms) ms[i] = kv.second.first;
+            if (launches) launches[i] = kv.second.second;
+        }
+        ++i;
+    }
+    return i;
+}
+
+int lp_plan_reset_timings(lp_plan *p) {
+    if (int r = check_plan(p)) return r;
+    (void)lp_plan_timings(p, nullptr, 0, nullptr, nullptr, 0);
+    p->totals.clear();
+    return LP_OK;
+}
 
 int lp_plan_reserve(lp_plan *p, int64_t B, int64_t T) {
     if (int r = check_plan(p)) return r;

@@ -74,6 +74,30 @@ class Plan:
     def reserve(self, B: int, T: int):
         _lib.check(_lib.load().lp_plan_reserve(self._h, int(B), int(T)))
 
+    def set_timing(self, on: bool = True):
+        _lib.check(_lib.load().lp_plan_set_timing(self._h, 1 if on else 0))
+
+    def reset_timings(self):
+        _lib.check(_lib.load().lp_plan_reset_timings(self._h))
+
+    def timings(self) -> dict:
+        """{kernel name: (total ms, launches)} accumulated while timing was on (synchronises)."""
+        lib = _lib.load()
+        n = _lib.check(lib.lp_plan_timings(self._h, None, 0, None, None, 0))
+        if n == 0:
+            return {}
+        NL = 64
+        names = ctypes.create_string_buffer(n * NL)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        lib.lp_plan_timings(self._h, ctypes.cast(names, ctypes.c_void_p), NL, ctypes.cast(ms, ctypes.c_void_p),
+                            ctypes.cast(cnt, ctypes.c_void_p), n)
+        out = {}
+        for i in range(n):
+            nm = names.raw[i * NL:(i + 1) * NL].split(b"\0", 1)[0].decode()
+            out[nm] = (float(ms[i]), int(cnt[i]))
+        return out
+
     def saved_bytes(self, B: int, T: int) -> int:
         return int(_lib.load().lp_saved_bytes(self._h, int(B), int(T)))
 
@@ -82,8 +106,12 @@ class Plan:
 
     # ------------------------------------------------------------ uniform batches
     def forward(self, e: torch.Tensor, a: torch.Tensor, zi: Optional[torch.Tensor] = None,
-                want_zf: bool = False, save: bool = True, out: Optional[torch.Tensor] = None):
-        """s = LP_a(e).  Returns (s, zf or None, saved or None)."""
+                want_zf: bool = False, save: bool = True, out: Optional[torch.Tensor] = None,
+                saved_out: Optional[torch.Tensor] = None):
+        """s = LP_a(e).  Returns (s, zf or None, saved or None).
+
+        out / saved_out: optional preallocated output and saved-state buffers.
+        """
         _need(e, "e", torch.float32, 2)
         _need(a, "a", torch.float32, 3)
         B, T = e.shape
@@ -93,7 +121,12 @@ class Plan:
             _need(zi, "zi", torch.float64, 2)
         s = torch.empty_like(e) if out is None else out
         zf = torch.empty((B, self.M), dtype=torch.float64, device=e.device) if want_zf else None
-        saved = torch.empty(self.saved_bytes(B, T), dtype=torch.uint8, device=e.device) if save else None
+        if saved_out is not None:
+            if saved_out.numel() * saved_out.element_size() < self.saved_bytes(B, T):
+                raise ValueError("saved_out is smaller than saved_bytes(B, T)")
+            saved = saved_out
+        else:
+            saved = torch.empty(self.saved_bytes(B, T), dtype=torch.uint8, device=e.device) if save else None
         _lib.check(_lib.load().lp_forward(self._h, B, T, _ptr(e), _ptr(a), _ptr(zi), _ptr(s), _ptr(zf),
                                           _ptr(saved), _stream(e.device)))
         return s, zf, saved
