@@ -32,17 +32,21 @@ def log(*a):
 
 
 def kernel_bytes(name: str, B: int, T: int, M: int, L: int) -> float:
-    """Algorithmic HBM bytes of one launch of each kernel (float32 I/O per sample)."""
+    """Algorithmic HBM bytes of one launch of each kernel (float32 I/O per sample).
+
+    Only the bytes the operation itself must move are counted: the coefficient
+    row (4M), the per-sample scalars and outputs.  Chunk-state side arrays and
+    re-reads are overhead and excluded.
+    """
     n = B * T
     C = -(-T // L)
     n_full = B * (C - 1) * L  # samples in chunks that carry a transition
     row = 4 * M
     table = {
-        "fwd_basis": n_full * (4 + row),          # read e, a
+        "fwd_scan": n_full * (4 + row),           # read e, a (transition-carrying chunks)
         "fwd_emit": n * (4 + row + 4),            # read e, a; write s
-        "bwd_zs": n * (4 + row),                  # read g, a
-        "recompute_s": n * (4 + row + 4),         # read e, a; write s
-        "bwd_emit": n * (4 + row + 4 + 4 + row),  # read g, a, s; write grad_e, grad_a
+        "bwd_scan": n * (4 + row),                # read g, a
+        "bwd_emit": n * (4 + 4 + row + 4 + row),  # read g, e, a; write grad_e, grad_a
     }
     return float(table.get(name, 0.0))
 
@@ -53,11 +57,10 @@ def kernel_flops(name: str, B: int, T: int, M: int, L: int) -> float:
     C = -(-T // L)
     n_full = B * (C - 1) * L
     table = {
-        "fwd_basis": n_full * (M + 1) * 2 * M,  # zero-state + M basis recursions
+        "fwd_scan": n_full * (M + 1) * 2 * M,  # zero-state + M basis recursions
         "fwd_emit": n * 2 * M,
-        "bwd_zs": n * 2 * M,
-        "recompute_s": n * 2 * M,
-        "bwd_emit": n * (2 * M + M),
+        "bwd_scan": n * 2 * M,
+        "bwd_emit": n * (2 * M + 2 * M + M),   # recompute s, adjoint, coefficient gradient
     }
     return float(table.get(name, 0.0))
 

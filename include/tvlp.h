@@ -86,6 +86,11 @@ int lp_plan_set_timing(lp_plan *p, int on);
 int lp_plan_timings(lp_plan *p, char *names, int name_len, double *ms, int64_t *launches, int cap);
 int lp_plan_reset_timings(lp_plan *p);
 
+/* Synchronises the device and reports whether any chunk-scan wave of this
+ * plan gave up waiting for a neighbouring group (a failure that leaves the
+ * affected results invalid).  Returns LP_OK, or LP_EDEVICE and clears the flag. */
+int lp_plan_status(lp_plan *p);
+
 /* Grow the plan's workspace for a batch of B sequences of length T (or, for
  * varlen use, a total of N samples in B sequences: pass T = ceil(N / B) + L). */
 int lp_plan_reserve(lp_plan *p, int64_t B, int64_t T);

@@ -43,6 +43,7 @@ SIGNATURES = {
     "lp_plan_set_timing": (_INT, [_P, _INT]),
     "lp_plan_timings": (_INT, [_P, _P, _INT, _P, _P, _INT]),
     "lp_plan_reset_timings": (_INT, [_P]),
+    "lp_plan_status": (_INT, [_P]),
     "lp_saved_bytes": (_SZ, [_P, _I64, _I64]),
     "lp_saved_bytes_varlen": (_SZ, [_P, _I64, _I64]),
     "lp_forward": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P]),

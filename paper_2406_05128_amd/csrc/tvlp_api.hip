@@ -2,6 +2,8 @@
 // workspace management and kernel dispatch over the compiled filter orders.
 #include "tvlp.h"
 #include "tvlp_device.hpp"
+#include "tvlp_systolic.hpp"
+#include "tvlp_scan.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -120,21 +122,32 @@ size_t bytes_phi(int M, int64_t nch) { return (size_t)nch * M * M * sizeof(doubl
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+constexpr size_t kStatusOffset = 256;  // byte offset of the scan status word in every workspace
+
 // Workspace layout for one call with nch chunks and n samples over B sequences.
 struct WsLayout {
-    size_t xs, phi, z, q, yend, sbuf, cbase, total;
+    size_t xs, phi, yend, cbase, gbf, gbb, aggf, inclf, flagf, aggb, inclb, flagb, tickets, status, total;
 };
 
-WsLayout ws_layout(int M, int64_t nch, int64_t nsamp, int64_t B) {
+// ngf / ngb: group slots of the forward / adjoint scans.
+WsLayout ws_layout(int M, int64_t nch, int64_t B, int64_t ngf, int64_t ngb) {
     WsLayout w{};
     size_t off = 0;
-    w.xs = off;   off += align_up(bytes_state(M, nch));
-    w.phi = off;  off += align_up(bytes_phi(M, nch));
-    w.z = off;    off += align_up(bytes_state(M, nch));
-    w.q = off;    off += align_up(bytes_state(M, nch));
-    w.yend = off; off += align_up(bytes_state(M, nch));
-    w.sbuf = off; off += align_up((size_t)nsamp * sizeof(float));
+    const size_t agg = (size_t)(M * M + M) * sizeof(double);
+    w.tickets = off; off += 256;  // fixed offsets: tickets, then the status word
+    w.status = off;  off += 256;
+    w.xs = off;    off += align_up(bytes_state(M, nch));
+    w.phi = off;   off += align_up(bytes_phi(M, nch));
+    w.yend = off;  off += align_up(bytes_state(M, nch));
     w.cbase = off; off += align_up((size_t)(B + 1) * sizeof(int64_t));
+    w.gbf = off;   off += align_up((size_t)(B + 1) * sizeof(int64_t));
+    w.gbb = off;   off += align_up((size_t)(B + 1) * sizeof(int64_t));
+    w.aggf = off;  off += align_up((size_t)ngf * agg);
+    w.inclf = off; off += align_up((size_t)ngf * M * sizeof(double));
+    w.flagf = off; off += align_up((size_t)ngf * sizeof(int));
+    w.aggb = off;  off += align_up((size_t)ngb * agg);
+    w.inclb = off; off += align_up((size_t)ngb * M * sizeof(double));
+    w.flagb = off; off += align_up((size_t)ngb * sizeof(int));
     w.total = off;
     return w;
 }
@@ -153,94 +166,157 @@ int ensure_ws(lp_plan *p, size_t need, hipStream_t stream) {
     }
     void *ptr = nullptr;
     if (hipMalloc(&ptr, need) != hipSuccess) return fail(LP_ENOMEM, "hipMalloc(%zu) for the workspace failed", need);
+    if (hipMemset(ptr, 0, kStatusOffset + 256) != hipSuccess) {
+        (void)hipFree(ptr);
+        return fail(LP_EDEVICE, "workspace initialisation failed");
+    }
     p->ws = ptr;
     p->ws_bytes = need;
     return LP_OK;
 }
 
 // Prefix of chunk counts over a packed varlen batch (single block).
-__global__ __launch_bounds__(1024) void k_build_cbase(const int64_t *__restrict__ offsets, int64_t n, int L,
-                                                      int64_t N, int64_t *__restrict__ cbase) {
-    __shared__ int64_t part[1024];
-    __shared__ int64_t carry;
-    if (threadIdx.x == 0) carry = 0;
+// Prefix sums over a packed varlen batch (single block): chunk counts (cbase)
+// and the group counts of the forward (gbf, cpwf chunks per group) and adjoint
+// (gbb, cpwb) scans.  Lengths are clamped exactly as seq_view clamps them.
+__global__ __launch_bounds__(1024) void k_build_tables(const int64_t *__restrict__ offsets, int64_t n, int L,
+                                                       int64_t N, int cpwf, int cpwb, int64_t *__restrict__ cbase,
+                                                       int64_t *__restrict__ gbf, int64_t *__restrict__ gbb) {
+    __shared__ int64_t part[3][1024];
+    __shared__ int64_t carry[3];
+    if (threadIdx.x < 3) carry[threadIdx.x] = 0;
     __syncthreads();
     for (int64_t base = 0; base < n; base += 1024) {
         const int64_t b = base + threadIdx.x;
         int64_t cnt = 0;
         if (b < n) {
-            // same clamping as seq_view
             const int64_t lo = min(max(offsets[b], (int64_t)0), N);
             const int64_t hi = min(max(offsets[b + 1], lo), N);
             const int64_t len = hi - lo;
             cnt = len <= 0 ? 0 : (len + L - 1) / L;
         }
-        part[threadIdx.x] = cnt;
+        part[0][threadIdx.x] = cnt;
+        part[1][threadIdx.x] = (cnt + cpwf - 1) / cpwf;
+        part[2][threadIdx.x] = (cnt + cpwb - 1) / cpwb;
         __syncthreads();
         for (int d = 1; d < 1024; d <<= 1) {
-            int64_t v = threadIdx.x >= (unsigned)d ? part[threadIdx.x - d] : 0;
+            int64_t v0 = 0, v1 = 0, v2 = 0;
+            if (threadIdx.x >= (unsigned)d) {
+                v0 = part[0][threadIdx.x - d];
+                v1 = part[1][threadIdx.x - d];
+                v2 = part[2][threadIdx.x - d];
+            }
             __syncthreads();
-            part[threadIdx.x] += v;
+            part[0][threadIdx.x] += v0;
+            part[1][threadIdx.x] += v1;
+            part[2][threadIdx.x] += v2;
             __syncthreads();
         }
-        if (b < n) cbase[b + 1] = carry + part[threadIdx.x];
+        if (b < n) {
+            cbase[b + 1] = carry[0] + part[0][threadIdx.x];
+            gbf[b + 1] = carry[1] + part[1][threadIdx.x];
+            gbb[b + 1] = carry[2] + part[2][threadIdx.x];
+        }
         __syncthreads();
-        if (threadIdx.x == 1023) carry += part[1023];
+        if (threadIdx.x == 1023) {
+            carry[0] += part[0][1023];
+            carry[1] += part[1][1023];
+            carry[2] += part[2][1023];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) cbase[0] = 0;
+    if (threadIdx.x == 0) {
+        cbase[0] = 0;
+        gbf[0] = 0;
+        gbb[0] = 0;
+    }
 }
+
+// Basis-pass mapping of the forward scan for order M: LPC lanes per chunk,
+// CPL float64 columns per lane (LPC*CPL >= M+1), R coefficient rows per LDS
+// slab (R divides M).
+template <int M> struct FwdShape;
+#define TVLP_FWD_SHAPE(m, lpc, cpl, r)          \
+    template <> struct FwdShape<m> {           \
+        static constexpr int LPC = lpc, CPL = cpl, R = r; \
+        static constexpr int CPW = 64 / lpc;   \
+    };
+TVLP_FWD_SHAPE(1, 1, 2, 1)
+TVLP_FWD_SHAPE(2, 1, 3, 2)
+TVLP_FWD_SHAPE(3, 2, 2, 3)
+TVLP_FWD_SHAPE(4, 2, 3, 4)
+TVLP_FWD_SHAPE(6, 4, 2, 6)
+TVLP_FWD_SHAPE(8, 3, 3, 8)
+TVLP_FWD_SHAPE(10, 4, 3, 10)
+TVLP_FWD_SHAPE(12, 5, 3, 4)
+TVLP_FWD_SHAPE(16, 6, 3, 2)
+TVLP_FWD_SHAPE(20, 7, 3, 2)
+TVLP_FWD_SHAPE(22, 8, 3, 2)
+TVLP_FWD_SHAPE(24, 13, 2, 3)
+TVLP_FWD_SHAPE(32, 17, 2, 2)
+#undef TVLP_FWD_SHAPE
+
+// Lanes per chunk of the systolic reruns and rows per LDS slab.
+template <int M>
+struct RerunShape {
+    static constexpr int G = M >= 8 ? 8 : 4;
+    static constexpr int R = 16;
+    static constexpr int CPW = 64 / G;
+};
 
 template <int M>
 struct Ops {
-    using BS = BasisShape<M>;
-    static constexpr int CPW = 64 / BS::LPC;
+    using FS = FwdShape<M>;
+    using RS = RerunShape<M>;
 
-    static void forward(const Seqs &S, int64_t nch, int64_t nseq, const float *e, const float *a,
-                        const double *zi, float *s, double *zf, double *xs, double *phi, double *z,
+    // Everything one call needs, resolved by the host driver.
+    struct Bufs {
+        Seqs S;
+        Groups gf, gb;
+        int64_t nch;
+        double *xs, *phiT, *yend;
+        double *aggf, *inclf, *aggb, *inclb;
+        int *flagf, *flagb;
+        unsigned *ticketf, *ticketb;
+        int *status;
+    };
+
+    static void forward(const Bufs &w, const float *e, const float *a, const double *zi, float *s, double *zf,
                         hipStream_t st, Timer &tm) {
-        if (nch <= 0) return;
-        tm.begin("fwd_basis");
-        hipLaunchKernelGGL((k_fwd_basis<M, BS::LPC, BS::CPL>), dim3((unsigned)ceil_div(nch, CPW)), dim3(64), 0, st,
-                           S, e, a, phi, z, nch);
-        tm.end();
-        tm.begin("fwd_chain");
-        hipLaunchKernelGGL((k_fwd_chain<M>), dim3((unsigned)nseq), dim3(64), 0, st, S, phi, z, zi, xs);
+        if (w.nch <= 0) return;
+        const unsigned rb = (unsigned)std::max<int64_t>(1, ceil_div(w.gf.ngroups, 256));
+        hipLaunchKernelGGL(k_scan_reset, dim3(rb), dim3(256), 0, st, w.flagf, w.gf.ngroups, w.ticketf, w.status);
+        tm.begin("fwd_scan");
+        hipLaunchKernelGGL((k_fwd_scan<M, FS::LPC, FS::CPL, FS::R>), dim3((unsigned)w.gf.ngroups), dim3(64), 0, st,
+                           w.S, w.gf, e, a, zi, w.phiT, w.xs, w.aggf, w.inclf, w.flagf, w.ticketf, w.status);
         tm.end();
         tm.begin("fwd_emit");
-        hipLaunchKernelGGL((k_fwd_emit<M>), dim3((unsigned)ceil_div(nch, 64)), dim3(64), 0, st, S, e, a, xs, s,
-                           zf, nch);
+        hipLaunchKernelGGL((k_fwd_rerun<M, RS::G, RS::R>), dim3((unsigned)ceil_div(w.nch, RS::CPW)), dim3(64), 0,
+                           st, w.S, e, a, w.xs, s, zf, w.nch);
         tm.end();
     }
 
-    static void backward(const Seqs &S, int64_t nch, int64_t nseq, const float *g, const float *a,
-                         const float *e, const float *s_in, const double *xs, const double *phi, double *q,
-                         double *yend, float *sbuf, float *ge, float *ga, double *gzi, hipStream_t st,
-                         Timer &tm) {
-        if (nch <= 0) return;
-        tm.begin("bwd_zs");
-        hipLaunchKernelGGL((k_bwd_zs<M>), dim3((unsigned)ceil_div(nch, 64)), dim3(64), 0, st, S, g, a, q, nch,
-                           gzi ? 1 : 0);
+    static void backward(const Bufs &w, const float *g, const float *a, const float *e, const float *s_in,
+                         float *ge, float *ga, double *gzi, hipStream_t st, Timer &tm) {
+        if (w.nch <= 0) return;
+        const unsigned rb = (unsigned)std::max<int64_t>(1, ceil_div(w.gb.ngroups, 256));
+        hipLaunchKernelGGL(k_scan_reset, dim3(rb), dim3(256), 0, st, w.flagb, w.gb.ngroups, w.ticketb, w.status);
+        tm.begin("bwd_scan");
+        hipLaunchKernelGGL((k_bwd_scan<M, RS::G, RS::R>), dim3((unsigned)w.gb.ngroups), dim3(64), 0, st, w.S,
+                           w.gb, g, a, w.phiT, w.yend, gzi, w.aggb, w.inclb, w.flagb, w.ticketb, w.status);
         tm.end();
-        tm.begin("bwd_chain");
-        hipLaunchKernelGGL((k_bwd_chain<M>), dim3((unsigned)nseq), dim3(64), 0, st, S, phi, q, yend, gzi);
-        tm.end();
-        const float *s = s_in;
-        if (ga && !s) {
-            tm.begin("recompute_s");
-            hipLaunchKernelGGL((k_recompute_s<M>), dim3((unsigned)ceil_div(nch, 64)), dim3(64), 0, st, S, e, a,
-                               xs, sbuf, nch);
+        if (ge || ga) {
+            const unsigned grid = (unsigned)ceil_div(w.nch, RS::CPW);
+            const size_t dyn = (size_t)RS::CPW * (M + w.S.L) * sizeof(float);
+            tm.begin("bwd_emit");
+            if (s_in)
+                hipLaunchKernelGGL((k_adj_rerun<M, RS::G, RS::R, true, true>), dim3(grid), dim3(64), dyn, st, w.S,
+                                   g, a, e, s_in, w.xs, w.yend, (double *)nullptr, ge, ga, w.nch, 1);
+            else
+                hipLaunchKernelGGL((k_adj_rerun<M, RS::G, RS::R, true, false>), dim3(grid), dim3(64), dyn, st, w.S,
+                                   g, a, e, s_in, w.xs, w.yend, (double *)nullptr, ge, ga, w.nch, 1);
             tm.end();
-            s = sbuf;
         }
-        tm.begin("bwd_emit");
-        if (ga)
-            hipLaunchKernelGGL((k_bwd_emit<M, true>), dim3((unsigned)ceil_div(nch, 64)), dim3(64), 0, st, S, g,
-                               a, s, xs, yend, ge, ga, nch);
-        else if (ge)
-            hipLaunchKernelGGL((k_bwd_emit<M, false>), dim3((unsigned)ceil_div(nch, 64)), dim3(64), 0, st, S, g,
-                               a, s, xs, yend, ge, ga, nch);
-        tm.end();
     }
 
     static void plain_fwd(int64_t B, int64_t T, const float *e, const float *a, const double *zi, float *s,
@@ -259,6 +335,27 @@ struct Ops {
                                a, zi, s, ge, ga, gzi);
     }
 };
+
+// Forward / adjoint scan group sizes (chunks per wave) of order M.
+int scan_cpw(int M, bool fwd) {
+    int r = 0;
+    auto pick = [&](auto ops) {
+        using O = decltype(ops);
+        r = fwd ? O::FS::CPW : O::RS::CPW;
+    };
+    switch (M) {
+#define TVLP_CPW(m) \
+    case m:         \
+        pick(Ops<m>{}); \
+        break;
+        TVLP_CPW(1) TVLP_CPW(2) TVLP_CPW(3) TVLP_CPW(4) TVLP_CPW(6) TVLP_CPW(8) TVLP_CPW(10)
+        TVLP_CPW(12) TVLP_CPW(16) TVLP_CPW(20) TVLP_CPW(22) TVLP_CPW(24) TVLP_CPW(32)
+#undef TVLP_CPW
+    default:
+        r = 1;
+    }
+    return r;
+}
 
 template <class F>
 bool dispatch(int M, F &&f) {
@@ -293,6 +390,61 @@ int check_plan(const lp_plan *p) {
 
 int64_t uniform_nchunks(int64_t B, int64_t T, int L) { return B * ceil_div(T, L); }
 
+// Resolves sequence tables, group counts and workspace regions for one call.
+template <class O>
+int prepare(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, const void *saved, hipStream_t st,
+            typename O::Bufs &w) {
+    const int M = p->M, L = p->L;
+    const int cpwf = O::FS::CPW, cpwb = O::RS::CPW;
+    int64_t nch, ngf, ngb;
+    if (offsets) {
+        nch = ceil_div(T_or_N, L) + B;
+        ngf = ceil_div(nch, cpwf) + B;
+        ngb = ceil_div(nch, cpwb) + B;
+    } else {
+        const int64_t C = ceil_div(T_or_N, L);
+        nch = B * C;
+        ngf = B * ceil_div(C, cpwf);
+        ngb = B * ceil_div(C, cpwb);
+    }
+    WsLayout lay = ws_layout(M, nch, B, ngf, ngb);
+    if (int r = ensure_ws(p, lay.total, st)) return r;
+    char *ws = (char *)p->ws;
+    w.nch = nch;
+    w.S = Seqs{nullptr, nullptr, offsets ? 0 : T_or_N, B, L, offsets ? T_or_N : 0, nch};
+    w.gf = Groups{nullptr, ngf, cpwf};
+    w.gb = Groups{nullptr, ngb, cpwb};
+    if (offsets) {
+        int64_t *cb = (int64_t *)(ws + lay.cbase);
+        int64_t *gbf = (int64_t *)(ws + lay.gbf);
+        int64_t *gbb = (int64_t *)(ws + lay.gbb);
+        hipLaunchKernelGGL(k_build_tables, dim3(1), dim3(1024), 0, st, offsets, B, L, T_or_N, cpwf, cpwb, cb, gbf,
+                           gbb);
+        w.S.offsets = offsets;
+        w.S.cbase = cb;
+        w.gf.gbase = gbf;
+        w.gb.gbase = gbb;
+    }
+    if (saved) {
+        w.xs = (double *)saved;
+        w.phiT = (double *)((char *)saved + bytes_state(M, nch));
+    } else {
+        w.xs = (double *)(ws + lay.xs);
+        w.phiT = (double *)(ws + lay.phi);
+    }
+    w.yend = (double *)(ws + lay.yend);
+    w.aggf = (double *)(ws + lay.aggf);
+    w.inclf = (double *)(ws + lay.inclf);
+    w.flagf = (int *)(ws + lay.flagf);
+    w.aggb = (double *)(ws + lay.aggb);
+    w.inclb = (double *)(ws + lay.inclb);
+    w.flagb = (int *)(ws + lay.flagb);
+    w.ticketf = (unsigned *)(ws + lay.tickets);
+    w.ticketb = w.ticketf + 2;
+    w.status = (int *)(ws + lay.status);
+    return LP_OK;
+}
+
 // Common driver of the uniform and varlen forward.
 int forward_impl(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, const float *e, const float *a,
                  const double *zi, float *s, double *zf, void *saved, void *stream) {
@@ -303,26 +455,15 @@ int forward_impl(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, 
     DeviceGuard dg(p->device);
     if (!dg.ok) return fail(LP_EDEVICE, "cannot select device %d", p->device);
     hipStream_t st = (hipStream_t)stream;
-    const int M = p->M, L = p->L;
-    const int64_t nsamp = offsets ? T_or_N : B * T_or_N;
-    const int64_t nch = offsets ? ceil_div(T_or_N, L) + B : uniform_nchunks(B, T_or_N, L);
-    WsLayout w = ws_layout(M, nch, 0, B);
-    if (int r = ensure_ws(p, w.total, st)) return r;
-    char *ws = (char *)p->ws;
-    double *xs = saved ? (double *)saved : (double *)(ws + w.xs);
-    double *phi = saved ? (double *)((char *)saved + bytes_state(M, nch)) : (double *)(ws + w.phi);
-    Seqs S{nullptr, nullptr, offsets ? 0 : T_or_N, B, L, offsets ? T_or_N : 0, nch};
-    if (offsets) {
-        int64_t *cb = (int64_t *)(ws + w.cbase);
-        hipLaunchKernelGGL(k_build_cbase, dim3(1), dim3(1024), 0, st, offsets, B, L, T_or_N, cb);
-        S.offsets = offsets;
-        S.cbase = cb;
-    }
-    (void)nsamp;
+    int rc = LP_OK;
     Timer tm{p, st};
-    dispatch(M, [&](auto ops) {
-        decltype(ops)::forward(S, nch, B, e, a, zi, s, zf, xs, phi, (double *)(ws + w.z), st, tm);
+    dispatch(p->M, [&](auto ops) {
+        using O = decltype(ops);
+        typename O::Bufs w;
+        rc = prepare<O>(p, B, offsets, T_or_N, saved, st, w);
+        if (rc == LP_OK) O::forward(w, e, a, zi, s, zf, st, tm);
     });
+    if (rc != LP_OK) return rc;
     return check_hip(hipGetLastError(), "kernel launch (forward)");
 }
 
@@ -333,32 +474,21 @@ int backward_impl(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N,
     if (B < 1) return fail(LP_EINVAL, "B must be >= 1 (got %lld)", (long long)B);
     if (T_or_N < 1) return fail(LP_EINVAL, "T (or N) must be >= 1 (got %lld)", (long long)T_or_N);
     if (!g || !a || !saved) return fail(LP_EINVAL, "g, a and saved are required");
-    if (ga && !s && !e) return fail(LP_EINVAL, "grad_a needs s or e (to recompute s)");
+    if ((ga || ge) && !s && !e) return fail(LP_EINVAL, "the adjoint needs s or e (to recompute s)");
     if (!ge && !ga && !gzi) return LP_OK;
     (void)zi;
     DeviceGuard dg(p->device);
     if (!dg.ok) return fail(LP_EDEVICE, "cannot select device %d", p->device);
     hipStream_t st = (hipStream_t)stream;
-    const int M = p->M, L = p->L;
-    const int64_t nsamp = offsets ? T_or_N : B * T_or_N;
-    const int64_t nch = offsets ? ceil_div(T_or_N, L) + B : uniform_nchunks(B, T_or_N, L);
-    WsLayout w = ws_layout(M, nch, (ga && !s) ? nsamp : 0, B);
-    if (int r = ensure_ws(p, w.total, st)) return r;
-    char *ws = (char *)p->ws;
-    const double *xs = (const double *)saved;
-    const double *phi = (const double *)((const char *)saved + bytes_state(M, nch));
-    Seqs S{nullptr, nullptr, offsets ? 0 : T_or_N, B, L, offsets ? T_or_N : 0, nch};
-    if (offsets) {
-        int64_t *cb = (int64_t *)(ws + w.cbase);
-        hipLaunchKernelGGL(k_build_cbase, dim3(1), dim3(1024), 0, st, offsets, B, L, T_or_N, cb);
-        S.offsets = offsets;
-        S.cbase = cb;
-    }
+    int rc = LP_OK;
     Timer tm{p, st};
-    dispatch(M, [&](auto ops) {
-        decltype(ops)::backward(S, nch, B, g, a, e, s, xs, phi, (double *)(ws + w.q), (double *)(ws + w.yend),
-                                (float *)(ws + w.sbuf), ge, ga, gzi, st, tm);
+    dispatch(p->M, [&](auto ops) {
+        using O = decltype(ops);
+        typename O::Bufs w;
+        rc = prepare<O>(p, B, offsets, T_or_N, saved, st, w);
+        if (rc == LP_OK) O::backward(w, g, a, e, s, ge, ga, gzi, st, tm);
     });
+    if (rc != LP_OK) return rc;
     return check_hip(hipGetLastError(), "kernel launch (backward)");
 }
 
@@ -454,6 +584,23 @@ int lp_plan_timings(lp_plan *p, char *names, int name_len, double *ms, int64_t *
     return i;
 }
 
+int lp_plan_status(lp_plan *p) {
+    if (int r = check_plan(p)) return r;
+    if (!p->ws) return LP_OK;
+    DeviceGuard dg(p->device);
+    if (hipDeviceSynchronize() != hipSuccess) return fail(LP_EDEVICE, "device error before status read");
+    // the status word sits at a fixed offset from the end of the workspace layout
+    int v = 0;
+    if (hipMemcpy(&v, (char *)p->ws + kStatusOffset, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(LP_EDEVICE, "status read failed");
+    if (v != 0) {
+        const int zero = 0;
+        (void)hipMemcpy((char *)p->ws + kStatusOffset, &zero, sizeof(int), hipMemcpyHostToDevice);
+        return fail(LP_EDEVICE, "a scan wave timed out waiting for a neighbour group (status %d)", v);
+    }
+    return LP_OK;
+}
+
 int lp_plan_reset_timings(lp_plan *p) {
     if (int r = check_plan(p)) return r;
     (void)lp_plan_timings(p, nullptr, 0, nullptr, nullptr, 0);
@@ -466,7 +613,8 @@ int lp_plan_reserve(lp_plan *p, int64_t B, int64_t T) {
     if (B < 1 || T < 1) return fail(LP_EINVAL, "B and T must be >= 1");
     DeviceGuard dg(p->device);
     const int64_t nch = uniform_nchunks(B, T, p->L) + B;
-    WsLayout w = ws_layout(p->M, nch, B * T, B);
+    const int cf = scan_cpw(p->M, true), cb = scan_cpw(p->M, false);
+    WsLayout w = ws_layout(p->M, nch, B, ceil_div(nch, cf) + B, ceil_div(nch, cb) + B);
     return ensure_ws(p, w.total, nullptr);
 }
 

@@ -1,0 +1,611 @@
+// Single-pass chunk scans with decoupled look-back (gfx950, one wave per group).
+//
+// Forward (k_fwd_scan).  A wave owns a group of CPW consecutive chunks of one
+// sequence.  It computes each chunk's transition (Phi_c, z_c) with the basis
+// pass (LPC lanes per chunk, CPL float64 columns per lane, coefficient rows
+// staged through LDS), stores Phi_c (column-major, for the adjoint), composes
+// the group's affine map (Phi_G, z_G) in LDS and publishes it.  It then obtains
+// the group's entry state by looking back over the preceding groups of its
+// sequence — taking the first published inclusive state and applying the
+// aggregates after it — publishes its own inclusive state, and writes every
+// chunk's entry state x_c.
+//
+// Adjoint (k_bwd_scan).  The mirror image, right to left: per chunk the
+// zero-terminal adjoint response q_c (systolic push form of Eq. 12), the
+// group's reverse map y_start = Psi_G y_end + w_G with Psi_G the product of the
+// Phi_c^T, look-back over the following groups, and every chunk's terminal
+// pending vector yend[c] = y_{c+1} (plus dL/dzi = y_0).
+//
+// Ordering and progress: the wave's group comes from an atomic ticket taken
+// when the wave starts, in an order where every group a wave may wait on has a
+// smaller ticket, so it has already started and never waits on a later one.
+// Publication is release (agent scope) after the data, consumption acquire.
+// Waits are bounded: on timeout the wave raises status[0] and continues.
+#pragma once
+
+#include "tvlp_systolic.hpp"
+
+namespace tvlp {
+
+enum : int { FLAG_EMPTY = 0, FLAG_AGG = 1, FLAG_INCL = 2 };
+constexpr unsigned SPIN_LIMIT = 1u << 22;
+
+// Groups of CPW chunks per sequence (uniform batches or varlen prefix gbase).
+struct Groups {
+    const int64_t *gbase;  // varlen: [n+1] prefix of group counts; nullptr for uniform
+    int64_t ngroups;
+    int cpw;
+};
+
+__device__ __forceinline__ int64_t groups_of(int64_t C, int cpw) { return (C + cpw - 1) / cpw; }
+
+// gid -> (sequence, group index within the sequence), sequence-major.
+__device__ __forceinline__ void group_at(const Seqs &S, const Groups &G, int64_t gid, int64_t &b, int64_t &g) {
+    if (!G.gbase) {
+        const int64_t gp = groups_of(nchunks_of(S.T, S.L), G.cpw);
+        b = gid / gp;
+        g = gid - b * gp;
+        return;
+    }
+    int64_t lo = 0, hi = S.n;
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (G.gbase[mid] <= gid) lo = mid; else hi = mid;
+    }
+    b = lo;
+    g = gid - G.gbase[lo];
+}
+
+__device__ __forceinline__ int64_t group_id(const Seqs &S, const Groups &G, int64_t b, int64_t g) {
+    if (!G.gbase) return b * groups_of(nchunks_of(S.T, S.L), G.cpw) + g;
+    return G.gbase[b] + g;
+}
+
+__device__ __forceinline__ void publish_flag(int *flags, int64_t gid, int v, int lane) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (lane == 0) __hip_atomic_store(flags + gid, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until flags[gid] != 0; returns the flag (wave-uniform).
+__device__ __forceinline__ int wait_flag(const int *flags, int64_t gid, int lane, int *status) {
+    int f = 0;
+    for (unsigned it = 0;; ++it) {
+        int v = 0;
+        if (lane == 0) v = __hip_atomic_load(flags + gid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        f = __builtin_amdgcn_readfirstlane(v);
+        if (f != FLAG_EMPTY) break;
+        if (it >= SPIN_LIMIT) {
+            if (lane == 0) atomicOr(status, 1);
+            f = FLAG_INCL;  // give up: treat as available (result is flagged invalid)
+            break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return f;
+}
+
+// ---------------------------------------------------------------- small dense helpers in LDS
+
+// y = A x + z for an M x M matrix given column-major (AT[j][i] = A[i][j]); lanes i < M.
+template <int M>
+__device__ __forceinline__ double matvec_cm(const double *AT, const double *x, double zi_, int i) {
+    double acc0 = zi_, acc1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const double v = AT[j * M + i] * 1.0;
+        if (j & 1) acc1 = fma(v, x[j], acc1);
+        else acc0 = fma(v, x[j], acc0);
+    }
+    return acc0 + acc1;
+}
+
+// y = A x + z for A row-major (lanes i < M).
+template <int M>
+__device__ __forceinline__ double matvec_rm(const double *A, const double *x, double zi_, int i) {
+    double acc0 = zi_, acc1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        if (j & 1) acc1 = fma(A[i * M + j], x[j], acc1);
+        else acc0 = fma(A[i * M + j], x[j], acc0);
+    }
+    return acc0 + acc1;
+}
+
+// C = A B for M x M matrices stored column-major (XT[j][i] = X[i][j]).
+// Lanes l < M*JP: row i = l % M, columns j = l / M + JP*q.
+template <int M>
+__device__ __forceinline__ void matmul_cm(const double *AT, const double *BT, double *CT, int lane) {
+    constexpr int JP = 64 / M > 0 ? 64 / M : 1;
+    if (lane < M * JP) {
+        const int i = lane % M, jp = lane / M;
+        double arow[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) arow[m] = AT[m * M + i];
+        for (int j = jp; j < M; j += JP) {
+            double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                if (m & 1) acc1 = fma(arow[m], BT[j * M + m], acc1);
+                else acc0 = fma(arow[m], BT[j * M + m], acc0);
+            }
+            CT[j * M + i] = acc0 + acc1;
+        }
+    }
+}
+
+// C = A B for row-major matrices (lanes l < M*JP: row i, columns j).
+template <int M>
+__device__ __forceinline__ void matmul_rm(const double *A, const double *B, double *C, int lane) {
+    constexpr int JP = 64 / M > 0 ? 64 / M : 1;
+    if (lane < M * JP) {
+        const int i = lane % M, jp = lane / M;
+        double arow[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) arow[m] = A[i * M + m];
+        for (int j = jp; j < M; j += JP) {
+            double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                if (m & 1) acc1 = fma(arow[m], B[m * M + j], acc1);
+                else acc0 = fma(arow[m], B[m * M + j], acc0);
+            }
+            C[i * M + j] = acc0 + acc1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- forward scan
+
+template <int M, int LPC, int CPL, int R>
+struct FwdScanShape {
+    static constexpr int CPW = 64 / LPC;
+    // DMA ring: each step moves one coefficient row (M floats) and one
+    // excitation value for each of the CPW chunks into a ring slot of
+    // DMA_N x 64 floats; D steps are kept in flight.
+    static constexpr int ROWF = CPW * M + CPW;           // floats per step slot actually used
+    static constexpr int DMA_N = (ROWF + 63) / 64;       // dword DMA instructions per step
+    static constexpr int D = (63 / DMA_N) < 15 ? (63 / DMA_N) : 15;  // steps in flight (vmcnt <= 63)
+    static constexpr int NS = D + 1;                     // ring slots
+    static constexpr int RING_BYTES = NS * DMA_N * 64 * 4;
+    static constexpr int RM = R * M;
+    static constexpr bool VEC2 = (M % 2 == 0);
+    static constexpr int WORDS = VEC2 ? RM / 2 : RM;
+    static constexpr int PER_LANE = (WORDS + LPC - 1) / LPC;
+    static constexpr int EPER_LANE = (R + LPC - 1) / LPC;
+    static constexpr int STRIDE = ((RM + 1) / 2) * 2 + 2;  // floats per chunk slab
+    // chunk slabs, per-row scalars, and a 2-float dummy target for masked writes
+    static constexpr int SLAB_BYTES = (CPW * STRIDE + CPW * R + 2) * 4;
+    static constexpr int MAT_BYTES = (3 * M * M + 4 * M) * 8;
+    static constexpr int LDS_BYTES = RING_BYTES > MAT_BYTES ? RING_BYTES : MAT_BYTES;
+};
+
+// s_waitcnt immediate that waits for vmcnt <= n only (gfx9 encoding).
+constexpr int waitcnt_vm(int n) { return (n & 0xF) | (0x7 << 4) | (0xF << 8) | (((n >> 4) & 0x3) << 14); }
+
+template <int M, int LPC, int CPL, int R>
+__global__ __launch_bounds__(64) void k_fwd_scan(Seqs S, Groups GR, const float *__restrict__ e,
+                                                 const float *__restrict__ a, const double *__restrict__ zi,
+                                                 double *__restrict__ phiT, double *__restrict__ xs,
+                                                 double *__restrict__ aggbuf, double *__restrict__ inclbuf,
+                                                 int *__restrict__ flags, unsigned *__restrict__ ticket,
+                                                 int *__restrict__ status) {
+    using SH = FwdScanShape<M, LPC, CPL, R>;
+    constexpr int CPW = SH::CPW;
+    constexpr int MM = M * M;
+    static_assert(M % R == 0, "slab rows must divide M");
+    __shared__ __attribute__((aligned(16))) unsigned char lds_raw[SH::LDS_BYTES];
+    double *PT = reinterpret_cast<double *>(lds_raw);  // aggregate, column-major
+    double *FT = PT + MM;                              // current chunk's Phi, column-major
+    double *QT = FT + MM;                              // product scratch
+    double *vr = QT + MM;                              // aggregate offset
+    double *vz = vr + M;                               // chunk offset
+    double *vx = vz + M;                               // state vector
+    double *vt = vx + M;                               // scratch vector
+
+    const int lane = threadIdx.x;
+    unsigned tk = 0;
+    if (lane == 0) tk = atomicAdd(ticket, 1u);
+    const int64_t gid = (int64_t)__builtin_amdgcn_readfirstlane(tk);
+    if (gid >= GR.ngroups) return;
+    int64_t b, g;
+    group_at(S, GR, gid, b, g);
+    const SeqView v = seq_view(S, b);
+    if (g >= groups_of(v.C, CPW)) return;  // slot beyond the real group count
+    const int L = S.L;
+    const int64_t c0 = g * CPW;
+    const int nk = (int)min((int64_t)CPW, v.C - c0);  // chunks in this group
+    const int nbasis = (int)min((int64_t)CPW, v.C - 1 - c0);  // chunks carrying a transition
+
+    // ---- basis pass
+    const int slot = lane / LPC, sub = lane % LPC;
+    const int64_t c = c0 + slot;
+    const bool act = slot < CPW && slot < nbasis;
+    double h[CPL][M];
+#pragma unroll
+    for (int m = 0; m < CPL; ++m) {
+        const int col = sub * CPL + m;
+#pragma unroll
+        for (int p = 0; p < M; ++p) h[m][p] = (col >= 1 && p == M - col) ? 1.0 : 0.0;
+    }
+    typedef __attribute__((address_space(3))) void lds_void;
+    if (nbasis > 0) {
+        // Per-lane DMA sources: instruction i, lane l moves ring float j = 64 i + l,
+        // which is coefficient (k, f) = (j / M, j % M) for j < CPW*M and the
+        // excitation value of chunk j - CPW*M above that.  Rows advance by M floats.
+        const float *src[SH::DMA_N];
+        int stride[SH::DMA_N];
+#pragma unroll
+        for (int i = 0; i < SH::DMA_N; ++i) {
+            const int j = 64 * i + lane;
+            const float *p = a;  // valid dummy for unused slots
+            int st = 0;
+            if (j < CPW * M) {
+                const int k = j / M, f = j % M;
+                if (k < nbasis) {
+                    p = a + (v.start + (c0 + k) * L) * M + f;
+                    st = M;
+                }
+            } else if (j < SH::ROWF) {
+                const int k = j - CPW * M;
+                if (k < nbasis) {
+                    p = e + v.start + (c0 + k) * L;
+                    st = 1;
+                }
+            }
+            src[i] = p;
+            stride[i] = st;
+        }
+        float *ring = reinterpret_cast<float *>(lds_raw);
+        auto issue = [&](int t) {  // rows t of every chunk into ring slot t % NS (rows >= L: dummy)
+            const int ts = t < L ? t : 0;
+            float *dst = ring + (t % SH::NS) * (SH::DMA_N * 64);
+#pragma unroll
+            for (int i = 0; i < SH::DMA_N; ++i)
+                __builtin_amdgcn_global_load_lds((const void *)(src[i] + (int64_t)ts * stride[i]),
+                                                 (lds_void *)(dst + 64 * i), 4, 0, 0);
+        };
+        for (int t = 0; t < SH::D; ++t) issue(t);
+        for (int t0 = 0; t0 < L; t0 += M) {
+            Unroll<M, 0>::run([&](auto kc) {
+                constexpr int K = decltype(kc)::value;
+                const int t = t0 + K;
+                issue(t + SH::D);
+                __builtin_amdgcn_s_waitcnt(waitcnt_vm(SH::DMA_N * SH::D));  // row t has landed
+                const float *slotp = ring + (t % SH::NS) * (SH::DMA_N * 64);
+                const float *row = slotp + slot * M;
+                const float ex = slotp[CPW * M + (slot < CPW ? slot : 0)];
+                double acc[CPL][2];
+#pragma unroll
+                for (int m = 0; m < CPL; ++m) {
+                    acc[m][0] = (m == 0 && sub == 0) ? (double)ex : 0.0;
+                    acc[m][1] = 0.0;
+                }
+#pragma unroll
+                for (int i = 1; i <= M; ++i) {
+                    const double ai = (double)row[i - 1];
+#pragma unroll
+                    for (int m = 0; m < CPL; ++m) acc[m][i & 1] = fma(-ai, h[m][wrap<M>(K - i)], acc[m][i & 1]);
+                }
+#pragma unroll
+                for (int m = 0; m < CPL; ++m) h[m][K] = acc[m][0] + acc[m][1];
+            });
+        }
+        __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));  // drain the look-ahead before the ring is reused
+        // Phi_c column-major to global (column j-1 = response to unit state s(cL-j))
+        if (act) {
+#pragma unroll
+            for (int m = 0; m < CPL; ++m) {
+                const int col = sub * CPL + m;
+                if (col >= 1 && col <= M) {
+#pragma unroll
+                    for (int k = 0; k < M; ++k) phiT[(((v.cbase + c) * M) + (col - 1)) * M + k] = h[m][M - 1 - k];
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // Writes chunk k's Phi (column-major) and z into FT / vz.
+    auto stage_chunk = [&](int k) {
+        if (slot == k) {
+#pragma unroll
+            for (int m = 0; m < CPL; ++m) {
+                const int col = sub * CPL + m;
+                if (col == 0) {
+#pragma unroll
+                    for (int q = 0; q < M; ++q) vz[q] = h[m][M - 1 - q];
+                } else if (col <= M) {
+#pragma unroll
+                    for (int q = 0; q < M; ++q) FT[(col - 1) * M + q] = h[m][M - 1 - q];
+                }
+            }
+        }
+        __syncthreads();
+    };
+
+    const bool last_group = (c0 + CPW >= v.C);
+    // ---- compose the group's map over its transition-carrying chunks
+    if (!last_group) {
+        // nbasis == CPW here
+        stage_chunk(0);
+        for (int q = lane; q < MM; q += 64) PT[q] = FT[q];
+        if (lane < M) vr[lane] = vz[lane];
+        __syncthreads();
+        for (int k = 1; k < nbasis; ++k) {
+            stage_chunk(k);
+            matmul_cm<M>(FT, PT, QT, lane);
+            double rn = 0.0;
+            if (lane < M) rn = matvec_cm<M>(FT, vr, vz[lane], lane);
+            __syncthreads();
+            for (int q = lane; q < MM; q += 64) PT[q] = QT[q];
+            if (lane < M) vr[lane] = rn;
+            __syncthreads();
+        }
+        // publish the aggregate (column-major matrix, then offset)
+        double *ag = aggbuf + gid * (MM + M);
+        for (int q = lane; q < MM; q += 64) ag[q] = PT[q];
+        if (lane < M) ag[MM + lane] = vr[lane];
+        publish_flag(flags, gid, FLAG_AGG, lane);
+    }
+
+    // ---- look-back: entry state of this group
+    double x = 0.0;
+    if (g == 0) {
+        x = (zi && lane < M) ? zi[b * M + lane] : 0.0;
+    } else {
+        int64_t j = g - 1;
+        int64_t stop = -1;  // index of the group whose inclusive state starts the fold (-1: sequence start)
+        for (;;) {
+            const int64_t jg = group_id(S, GR, b, j);
+            const int f = wait_flag(flags, jg, lane, status);
+            if (f == FLAG_INCL) { stop = j; break; }
+            if (j == 0) { stop = -1; break; }
+            --j;
+        }
+        int64_t first;
+        if (stop >= 0) {
+            x = lane < M ? inclbuf[group_id(S, GR, b, stop) * M + lane] : 0.0;
+            first = stop + 1;
+        } else {
+            x = (zi && lane < M) ? zi[b * M + lane] : 0.0;
+            first = 0;
+        }
+        for (int64_t jj = first; jj < g; ++jj) {
+            const double *ag = aggbuf + group_id(S, GR, b, jj) * (MM + M);
+            if (lane < M) vt[lane] = x;
+            __syncthreads();
+            if (lane < M) x = matvec_cm<M>(ag, vt, ag[MM + lane], lane);
+            __syncthreads();
+        }
+    }
+    // ---- inclusive state for the successors
+    if (!last_group) {
+        if (lane < M) vx[lane] = x;
+        __syncthreads();
+        double xn = 0.0;
+        if (lane < M) xn = matvec_cm<M>(PT, vx, vr[lane], lane);
+        if (lane < M) inclbuf[gid * M + lane] = xn;
+        publish_flag(flags, gid, FLAG_INCL, lane);
+        __syncthreads();
+    }
+    // ---- chunk entry states
+    for (int k = 0; k < nk; ++k) {
+        if (lane < M) xs[(v.cbase + c0 + k) * M + lane] = x;
+        if (k < nbasis) {
+            stage_chunk(k);
+            if (lane < M) vx[lane] = x;
+            __syncthreads();
+            if (lane < M) x = matvec_cm<M>(FT, vx, vz[lane], lane);
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------- adjoint scan
+
+template <int M, int G, int R>
+struct BwdScanShape {
+    using SL = Slab<M, G, R>;
+    static constexpr int CPW = SL::CPW;
+    static constexpr int SLAB_BYTES = (CPW * SL::STRIDE + CPW * R) * 4;
+    static constexpr int MAT_BYTES = (3 * M * M + 4 * M + CPW * M) * 8;
+    static constexpr int LDS_BYTES = SLAB_BYTES > MAT_BYTES ? SLAB_BYTES : MAT_BYTES;
+};
+
+template <int M, int G, int R>
+__global__ __launch_bounds__(64) void k_bwd_scan(Seqs S, Groups GR, const float *__restrict__ g_in,
+                                                 const float *__restrict__ a, const double *__restrict__ phiT,
+                                                 double *__restrict__ yend, double *__restrict__ grad_zi,
+                                                 double *__restrict__ aggbuf, double *__restrict__ inclbuf,
+                                                 int *__restrict__ flags, unsigned *__restrict__ ticket,
+                                                 int *__restrict__ status) {
+    using SH = BwdScanShape<M, G, R>;
+    using SL = typename SH::SL;
+    constexpr int CPW = SH::CPW;
+    constexpr int TPL = (M + G - 1) / G;
+    constexpr int MM = M * M;
+    __shared__ __attribute__((aligned(16))) unsigned char lds_raw[SH::LDS_BYTES];
+    float *sa = reinterpret_cast<float *>(lds_raw);
+    float *sg = sa + CPW * SL::STRIDE;
+    double *PS = reinterpret_cast<double *>(lds_raw);  // aggregate Psi, row-major
+    double *FT = PS + MM;                              // Phi_k^T row-major (= Phi_k column-major)
+    double *QT = FT + MM;
+    double *vw = QT + MM;
+    double *vy = vw + M;
+    double *vt = vy + M;
+    double *vq = vt + M;  // [CPW][M] q of each chunk (filled after the slab phase)
+    (void)vt;
+
+    const int lane = threadIdx.x;
+    unsigned tk = 0;
+    if (lane == 0) tk = atomicAdd(ticket, 1u);
+    const int64_t tid_ = (int64_t)__builtin_amdgcn_readfirstlane(tk);
+    if (tid_ >= GR.ngroups) return;
+    // reverse order inside each sequence: the last group gets the first ticket
+    int64_t b, gr;
+    group_at(S, GR, tid_, b, gr);
+    const SeqView v = seq_view(S, b);
+    const int L = S.L;
+    const int64_t ng = groups_of(v.C, CPW);
+    if (gr >= ng) return;  // slot beyond the real group count
+    const int64_t g = ng - 1 - gr;
+    const int64_t gid = group_id(S, GR, b, g);
+    const int64_t c0 = g * CPW;
+    const int nk = (int)min((int64_t)CPW, v.C - c0);
+
+    // ---- zero-terminal adjoint per chunk (systolic push form, descending)
+    const int slot = lane / G, r = lane % G;
+    const int64_t c = c0 + slot;
+    const bool act = slot < nk;
+    const int64_t base = v.start + c * L;
+    const int64_t len = act ? min((int64_t)L, v.len - c * L) : 0;
+    double P[TPL], P0 = 0.0;
+#pragma unroll
+    for (int m = 0; m < TPL; ++m) P[m] = 0.0;
+    {
+        SL slab;
+        slab.prefetch(a, g_in, base, len, len - R, r, act);
+        for (int j0 = 0; j0 < L; j0 += R) {
+            __syncthreads();
+            slab.commit(sa, sg, slot, r);
+            __syncthreads();
+            if (j0 + R < L) slab.prefetch(a, g_in, base, len, len - j0 - 2 * R, r, act);
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const int u = j0 + k;
+                const int lr = R - 1 - k;
+                const double gh = (double)sg[slot * R + lr] + P0;
+                double np[TPL];
+#pragma unroll
+                for (int m = 0; m < TPL; ++m) {
+                    const int tap = r * TPL + m;
+                    const float av = (tap < M) ? sa[slot * SL::STRIDE + lr * M + tap] : 0.f;
+                    np[m] = fma(-(double)av, gh, P[m]);
+                }
+                if (u < len) {
+                    if (u + 1 < len) {
+                        const double down = dpp_f64<DPP_ROW_SHL1>(np[0]);
+                        P0 = group_bcast0<G>(np[0], r);
+#pragma unroll
+                        for (int m = 0; m + 1 < TPL; ++m) P[m] = np[m + 1];
+                        P[TPL - 1] = (r == G - 1) ? 0.0 : down;
+                    } else {
+#pragma unroll
+                        for (int m = 0; m < TPL; ++m) P[m] = np[m];
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // q_c[i-1] = p(-i): lane slot (tap i) -> LDS
+    if (act) {
+#pragma unroll
+        for (int m = 0; m < TPL; ++m) {
+            const int i = r * TPL + m + 1;
+            if (i <= M) vq[slot * M + (i - 1)] = P[m];
+        }
+    }
+    __syncthreads();
+
+    auto stage_phi = [&](int k) {  // Phi_{c0+k}^T row-major into FT
+        const double *src = phiT + (v.cbase + c0 + k) * MM;
+        for (int q = lane; q < MM; q += 64) FT[q] = src[q];
+        __syncthreads();
+    };
+
+    const bool seq_last_group = (c0 + CPW >= v.C);
+    // ---- reverse map of the group: y(c0) = Psi y(c0+nk) + w
+    if (g > 0) {
+        // start from the group's last chunk
+        const int kl = nk - 1;
+        const bool kl_has_phi = (c0 + kl) < v.C - 1;
+        if (kl_has_phi) {
+            stage_phi(kl);
+            for (int q = lane; q < MM; q += 64) PS[q] = FT[q];
+        } else {
+            for (int q = lane; q < MM; q += 64) PS[q] = 0.0;
+        }
+        if (lane < M) vw[lane] = vq[kl * M + lane];
+        __syncthreads();
+        for (int k = kl - 1; k >= 0; --k) {
+            stage_phi(k);
+            matmul_rm<M>(FT, PS, QT, lane);
+            double wn = 0.0;
+            if (lane < M) wn = matvec_rm<M>(FT, vw, vq[k * M + lane], lane);
+            __syncthreads();
+            for (int q = lane; q < MM; q += 64) PS[q] = QT[q];
+            if (lane < M) vw[lane] = wn;
+            __syncthreads();
+        }
+        double *ag = aggbuf + gid * (MM + M);
+        for (int q = lane; q < MM; q += 64) ag[q] = PS[q];
+        if (lane < M) ag[MM + lane] = vw[lane];
+        publish_flag(flags, gid, FLAG_AGG, lane);
+    }
+
+    // ---- look-back over the following groups: y entering this group from the right
+    double y = 0.0;
+    if (!seq_last_group) {
+        int64_t j = g + 1;
+        int64_t stop = ng;  // ng: sequence end (y = 0)
+        for (;;) {
+            const int f = wait_flag(flags, group_id(S, GR, b, j), lane, status);
+            if (f == FLAG_INCL) { stop = j; break; }
+            if (j == ng - 1) { stop = ng; break; }
+            ++j;
+        }
+        int64_t first;
+        if (stop < ng) {
+            y = lane < M ? inclbuf[group_id(S, GR, b, stop) * M + lane] : 0.0;
+            first = stop - 1;
+        } else {
+            y = 0.0;
+            first = ng - 1;
+        }
+        for (int64_t jj = first; jj > g; --jj) {
+            const double *ag = aggbuf + group_id(S, GR, b, jj) * (MM + M);
+            if (lane < M) vy[lane] = y;
+            __syncthreads();
+            if (lane < M) y = matvec_rm<M>(ag, vy, ag[MM + lane], lane);
+            __syncthreads();
+        }
+    }
+    if (g > 0) {
+        if (lane < M) vy[lane] = y;
+        __syncthreads();
+        double yn = 0.0;
+        if (lane < M) yn = matvec_rm<M>(PS, vy, vw[lane], lane);
+        if (lane < M) inclbuf[gid * M + lane] = yn;
+        publish_flag(flags, gid, FLAG_INCL, lane);
+        __syncthreads();
+    }
+    // ---- per-chunk terminal pending vectors, right to left
+    for (int k = nk - 1; k >= 0; --k) {
+        const int64_t cc = c0 + k;
+        if (lane < M) yend[(v.cbase + cc) * M + lane] = y;
+        if (cc == 0 && !grad_zi) break;
+        const bool has_phi = cc < v.C - 1;
+        if (has_phi) stage_phi(k);
+        if (lane < M) vy[lane] = y;
+        __syncthreads();
+        if (lane < M) y = (has_phi ? matvec_rm<M>(FT, vy, 0.0, lane) : 0.0) + vq[k * M + lane];
+        __syncthreads();
+    }
+    if (g == 0 && grad_zi && lane < M) grad_zi[b * M + lane] = y;
+}
+
+// Reset tickets and flags before a scan (a kernel, so it can be captured in graphs).
+__global__ void k_scan_reset(int *__restrict__ flags, int64_t n, unsigned *__restrict__ ticket,
+                             int *__restrict__ status) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flags[i] = 0;
+    if (i == 0) {
+        ticket[0] = 0u;
+        ticket[1] = 0u;
+    }
+    (void)status;
+}
+
+}  // namespace tvlp

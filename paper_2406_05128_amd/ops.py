@@ -77,6 +77,10 @@ class Plan:
     def set_timing(self, on: bool = True):
         _lib.check(_lib.load().lp_plan_set_timing(self._h, 1 if on else 0))
 
+    def check_status(self):
+        """Synchronise and raise if a scan wave of this plan timed out waiting for a neighbour."""
+        _lib.check(_lib.load().lp_plan_status(self._h))
+
     def reset_timings(self):
         _lib.check(_lib.load().lp_plan_reset_timings(self._h))
 

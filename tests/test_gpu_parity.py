@@ -65,6 +65,7 @@ def check_all(tv, e, a, g, zi=None, chunk=None, store_s=False, plain=False, tol=
         s, zf, saved = plan.forward(e_d, a_d, zi_d, want_zf=True)
         ge, ga, gz = plan.backward(g_d, a_d, e_d, saved, s=s if store_s else None, zi=zi_d,
                                    need_zi=zi is not None)
+        plan.check_status()
     torch.cuda.synchronize()
     errs = {"s": per_seq_err(host(s), s_ref), "zf": rms_rel(host(zf), zf_ref),
             "grad_e": per_seq_err(host(ge), ge_ref), "grad_a": per_seq_err(host(ga), ga_ref)}
@@ -148,6 +149,7 @@ def test_varlen_matches_oracle_and_alone(tv):
     e_d, a_d, g_d, o_d = to_dev(e), to_dev(a), to_dev(g), to_dev(offs)
     s, zf, saved = plan.forward_varlen(e_d, a_d, o_d, want_zf=True)
     ge, ga, _ = plan.backward_varlen(g_d, a_d, e_d, o_d, saved)
+    plan.check_status()
     torch.cuda.synchronize()
     s, ge, ga = host(s), host(ge), host(ga)
     for b in range(len(lens)):
@@ -205,3 +207,10 @@ def test_autograd_function(tv):
     s2.backward(to_dev(g))
     torch.cuda.synchronize()
     assert np.array_equal(host(e2.grad), host(e_t.grad))
+
+
+def test_long_lookback_chains(tv):
+    """Many groups per sequence (short chunks): look-back walks over long predecessor chains."""
+    e, a, g = inputs(2, 120000, 22, seed=41)
+    errs = check_all(tv, e, a, g, chunk=22)
+    print("long chains (L=22, 5455 chunks/seq):", errs)
