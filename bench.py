@@ -65,6 +65,88 @@ def kernel_flops(name: str, B: int, T: int, M: int, L: int) -> float:
     return float(table.get(name, 0.0))
 
 
+def serve_bench(tv, n_req: int, seed: int, slots: int, budget_gib: float, batch: int):
+    """Poisson arrivals (200 req/s, lengths U(12000, 240000), M = 22) through the native server.
+
+    Returns latency percentiles and throughput, plus the same jobs run as
+    padded fixed batches of `batch` in arrival order (host-device copies
+    included on both sides; host-side packing of the padded batches excluded).
+    """
+    import numpy as np
+    import torch
+    from synth import make_coeffs, make_excitation, poisson_requests
+    from paper_2406_05128_amd.serve import latency_percentiles
+
+    M = 22
+    rng = np.random.default_rng(seed)
+    arrivals, lengths = poisson_requests(rng, n_req, 200.0, 12000, 240000)
+    pool_T = 600_000
+    log(f"serve: coefficient pool of {pool_T} samples")
+    a_pool = torch.from_numpy(make_coeffs(rng, 1, pool_T, M, 0.9)[0]).pin_memory()
+    e_pool = torch.from_numpy(make_excitation(rng, 1, pool_T)[0]).pin_memory()
+    offs = [int(rng.integers(0, pool_T - int(T) + 1)) for T in lengths]
+    outs = [torch.empty(int(T), dtype=torch.float32, pin_memory=True) for T in lengths]
+    budget = int(budget_gib * (1 << 30))
+    with tv.Server(M, budget, max_slots=slots) as srv:
+        # warm the kernels and the scheduler once
+        t = srv.submit(e_pool[:24000], a_pool[:24000])
+        srv.wait(t, 60.0)
+        log(f"serve: {n_req} requests, {slots} slots, {budget_gib} GiB arena")
+        tickets = []
+        t0 = time.perf_counter()
+        for k in range(n_req):
+            delay = float(arrivals[k]) - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            o, T = offs[k], int(lengths[k])
+            tickets.append(srv.submit(e_pool[o:o + T], a_pool[o:o + T], out=outs[k]))
+        lat = [srv.wait(tk, 120.0)[1] for tk in tickets]
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+    useful = float(np.sum(lengths))
+    res = latency_percentiles(lat)
+    res = {k: round(v, 3) for k, v in res.items()}
+    res.update({"requests": n_req, "rate_hz": 200.0, "len_range": [12000, 240000], "slots": slots,
+                "arena_GiB": budget_gib, "iterations": st["iterations"],
+                "samples_per_s": round(useful / wall, 1), "offered_samples_per_s": round(useful / float(arrivals[-1]), 1),
+                "wall_s": round(wall, 3)})
+
+    # the same jobs as padded fixed batches (uniform lp_forward over [batch, max T])
+    plan = tv.Plan(M, torch.device("cuda", 0))
+    dev = torch.device("cuda", 0)
+    tmax = int(np.max(lengths))
+    e_pad = torch.zeros((batch, tmax), dtype=torch.float32, pin_memory=True)
+    a_pad = torch.zeros((batch, tmax, M), dtype=torch.float32, pin_memory=True)
+    s_pad = torch.empty((batch, tmax), dtype=torch.float32, pin_memory=True)
+    plan.reserve(batch, tmax)
+    busy = 0.0
+    padded = 0
+    for b0 in range(0, n_req, batch):
+        ids = list(range(b0, min(b0 + batch, n_req)))
+        Tb = int(max(lengths[i] for i in ids))
+        e_pad.zero_()
+        a_pad.zero_()
+        for r, i in enumerate(ids):
+            o, T = offs[i], int(lengths[i])
+            e_pad[r, :T] = e_pool[o:o + T]
+            a_pad[r, :T] = a_pool[o:o + T]
+        ev = e_pad[:len(ids), :Tb].contiguous().pin_memory()
+        av = a_pad[:len(ids), :Tb].contiguous().pin_memory()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ed = ev.to(dev, non_blocking=True)
+        ad = av.to(dev, non_blocking=True)
+        sd, _, _ = plan.forward(ed, ad, save=False)
+        s_pad[:len(ids), :Tb].copy_(sd, non_blocking=True)
+        torch.cuda.synchronize()
+        busy += time.perf_counter() - t1
+        padded += len(ids) * Tb
+    res["padded_fixed_batch"] = {"batch": batch, "samples_per_s": round(useful / busy, 1),
+                                 "padding_efficiency": round(useful / padded, 4),
+                                 "note": "busy time only (batches back to back, no arrival waits)"}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +158,10 @@ def main():
     ap.add_argument("--no-sequential", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seq-steps", type=int, default=2)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=100)
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-batch", type=int, default=8)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -206,6 +292,11 @@ def main():
                          f"float64, {dt:.1f} s"}
         log(f"oracle: {dt:.1f} s")
 
+    serve = None
+    if not args.no_serve:
+        serve = serve_bench(tv, args.serve_requests, 2024, args.serve_slots, 4.0, args.serve_batch)
+        log(f"serve: p50 {serve['p50_ms']} ms, p99 {serve['p99_ms']} ms, {serve['samples_per_s'] / 1e6:.1f} M samples/s")
+
     out = {
         "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
@@ -218,7 +309,7 @@ def main():
         "kernels": kernels,
         "sequential": sequential,
         "cpu_baseline": cpu,
-        "serve": None,
+        "serve": serve,
     }
     print(json.dumps(out), flush=True)
 

@@ -42,6 +42,7 @@ extern "C" {
 #endif
 
 typedef struct lp_plan lp_plan;
+typedef struct lp_graph lp_graph;
 
 enum {
     LP_OK = 0,
@@ -73,9 +74,20 @@ int lp_supported_orders(int *out, int cap);
 int lp_plan_create(lp_plan **out, int device, int M, int flags);
 int lp_plan_destroy(lp_plan *p);
 
-/* Override / query the chunk length.  L must be a positive multiple of M. */
+/* Override / query the chunk length.  L must be a positive multiple of M and
+ * at most 2048 (LP_EINVAL otherwise). */
 int lp_plan_set_chunk(lp_plan *p, int L);
 int lp_plan_get_chunk(const lp_plan *p);
+
+/* Chunk-length autotuner: times one forward + recompute-adjoint step of a
+ * B x T batch (B capped so that the timed batch holds about 32 M samples) for
+ * candidate chunk lengths near 64 .. 1024 samples (multiples of M), `reps`
+ * timed repetitions each after one warm-up, and keeps the fastest on the plan.
+ * Allocates and frees its own zero-filled buffers (timing does not depend on
+ * the values) and synchronises the device.  Writes the chosen L and its best
+ * step time in ms (either pointer may be NULL).  On error the plan keeps its
+ * previous chunk length. */
+int lp_plan_autotune(lp_plan *p, int64_t B, int64_t T, int reps, int *chosen, double *best_ms);
 
 /* Per-kernel timing.  When on, every kernel the plan launches is bracketed by
  * hipEvents recorded on the launch stream.  lp_plan_timings waits for the
@@ -135,6 +147,87 @@ int lp_backward_varlen(lp_plan *p, int64_t B, const int64_t *offsets, int64_t N,
                        const float *g, const float *a, const float *e, const double *zi,
                        const float *s, const void *saved,
                        float *grad_e, float *grad_a, double *grad_zi, void *stream);
+
+/* Segment tables: sequence b occupies samples [starts[b], starts[b] + lens[b])
+ * of arrays with N samples (device int64 arrays; segments need not be packed
+ * or ordered but must not overlap; lens[b] may be 0, which leaves zf[b]
+ * untouched).  total_bound > 0 is an upper bound on sum(lens) that sizes the
+ * launch (0: N); if the table holds more, the excess is not computed and the
+ * next lp_plan_status returns LP_EINVAL.  zi / zf are [B][M] and may alias
+ * (every state is read before any is written), which lets a caller continue
+ * sequences slice by slice from device-resident state; the result then
+ * differs from one call over the whole sequence only by the rounding of the
+ * float64 chunk states.  Forward only (serving path). */
+int lp_forward_segments(lp_plan *p, int64_t B, const int64_t *starts, const int64_t *lens, int64_t N,
+                        int64_t total_bound, const float *e, const float *a, const double *zi,
+                        float *s, double *zf, void *stream);
+
+/*
+ * Harmonic-plus-noise filter pair (Eq. 1: S = G H + N C with two LP filters per
+ * item): both filters of every item run in one launch per direction as a
+ * stacked batch of 2B sequences.
+ *   e2 [2][B][T], a2 [2][B][T][M]: filter 0 (e.g. H on the glottal pulses)
+ *   then filter 1 (C on the noise); s2 [2][B][T] receives both outputs and
+ *   y [B][T] = s2[0] + s2[1].  saved: lp_saved_bytes_pair(p, B, T) bytes.
+ * The adjoint takes the single upstream gradient g = dL/dy [B][T] (shared by
+ * both filters) and writes ge2 [2][B][T], ga2 [2][B][T][M] (either may be
+ * NULL); s2 may be passed to skip recomputing s, or NULL.
+ */
+size_t lp_saved_bytes_pair(const lp_plan *p, int64_t B, int64_t T);
+int lp_forward_pair(lp_plan *p, int64_t B, int64_t T, const float *e2, const float *a2,
+                    float *y, float *s2, void *saved, void *stream);
+int lp_backward_pair(lp_plan *p, int64_t B, int64_t T, const float *g, const float *a2,
+                     const float *e2, const float *s2, const void *saved,
+                     float *ge2, float *ga2, void *stream);
+
+/*
+ * hipGraph capture of one full pair step (forward, sum, adjoint) with fixed
+ * buffers; the plan's workspace is reserved before capture, so replays launch
+ * kernels only (no allocation, no memset).  Replays reuse the captured
+ * pointers: refill the input buffers between replays.  store_s != 0 makes the
+ * adjoint read s2 instead of recomputing it.  A plan must not be used by
+ * other calls while one of its graphs is running.
+ */
+int lp_graph_capture_pair_step(lp_plan *p, int64_t B, int64_t T, const float *e2, const float *a2,
+                               float *y, float *s2, void *saved, const float *g,
+                               float *ge2, float *ga2, int store_s, lp_graph **out);
+int lp_graph_launch(lp_graph *g, void *stream);
+int lp_graph_destroy(lp_graph *g);
+
+/*
+ * Serving runtime (continuous batching of forward-filter jobs, Sec. 3.2's
+ * filter applied per request).  A server owns an HBM arena of
+ * hbm_budget_bytes for the inputs and outputs of admitted jobs
+ * ((M + 2) * 4 bytes per sample), max_slots device-resident float64 filter
+ * states, and a scheduler thread.  Jobs are admitted in submission order while
+ * a slot and arena space are free; every scheduler iteration advances each
+ * running job by up to slice_len samples (rounded up to a multiple of the
+ * chunk length; <= 0 picks 48 chunks) with one lp_forward_segments launch over
+ * all slots, so short jobs finish while long ones keep running.  Inputs are
+ * uploaded and outputs downloaded on their own streams, overlapping compute.
+ *
+ * lp_serve_submit copies nothing at call time: e_host [T], a_host [T][M] must
+ * stay valid and s_host_out [T] must stay writable until the job completes
+ * (pinned host memory makes the copies asynchronous).  Zero initial state.
+ * A job's result does not depend on the other jobs in flight (bit-identical to
+ * running it alone through a server with the same slice_len).
+ * Returns: submit LP_EBUDGET if T exceeds the whole arena; poll / wait
+ * LP_PENDING while the job runs, LP_OK once s_host_out holds the result (the
+ * ticket is then retired: a second poll gives LP_ENOTFOUND), LP_EDEVICE if it
+ * failed; latency_ms_out (may be NULL) receives submit-to-completion time.
+ * lp_serve_destroy finishes every admitted and queued job, then frees all.
+ * All functions are thread-safe.
+ */
+typedef struct lp_server lp_server;
+int lp_serve_create(lp_server **out, int device, int M, size_t hbm_budget_bytes, int max_slots,
+                    int64_t slice_len, int flags);
+int lp_serve_submit(lp_server *srv, int64_t T, const float *e_host, const float *a_host,
+                    float *s_host_out, uint64_t *ticket);
+int lp_serve_poll(lp_server *srv, uint64_t ticket, double *latency_ms_out);
+int lp_serve_wait(lp_server *srv, uint64_t ticket, double timeout_s, double *latency_ms_out);
+int lp_serve_stats(lp_server *srv, int64_t *iterations, int64_t *samples, int64_t *jobs_done,
+                   int64_t *queued, int64_t *active);
+int lp_serve_destroy(lp_server *srv);
 
 /*
  * Sequential baseline: one GPU thread per sequence runs Eq. 6 (forward) and

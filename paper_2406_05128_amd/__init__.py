@@ -8,8 +8,9 @@ from . import _lib
 
 _lib.load()
 
-from .ops import Plan, forward_plain, backward_plain  # noqa: E402
+from .ops import Plan, PairStepGraph, forward_plain, backward_plain  # noqa: E402
 from .autograd import LPFunction, lp, get_plan  # noqa: E402
+from .serve import Server  # noqa: E402
 
-__all__ = ["Plan", "forward_plain", "backward_plain", "LPFunction", "lp", "get_plan"]
+__all__ = ["Plan", "PairStepGraph", "forward_plain", "backward_plain", "LPFunction", "lp", "get_plan", "Server"]
 __version__ = "0.1.0"

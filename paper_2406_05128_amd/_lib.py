@@ -40,6 +40,7 @@ SIGNATURES = {
     "lp_plan_set_chunk": (_INT, [_P, _INT]),
     "lp_plan_get_chunk": (_INT, [_P]),
     "lp_plan_reserve": (_INT, [_P, _I64, _I64]),
+    "lp_plan_autotune": (_INT, [_P, _I64, _I64, _INT, _P, _P]),
     "lp_plan_set_timing": (_INT, [_P, _INT]),
     "lp_plan_timings": (_INT, [_P, _P, _INT, _P, _P, _INT]),
     "lp_plan_reset_timings": (_INT, [_P]),
@@ -50,6 +51,20 @@ SIGNATURES = {
     "lp_backward": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "lp_forward_varlen": (_INT, [_P, _I64, _P, _I64, _P, _P, _P, _P, _P, _P, _P]),
     "lp_backward_varlen": (_INT, [_P, _I64, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "lp_forward_segments": (_INT, [_P, _I64, _P, _P, _I64, _I64, _P, _P, _P, _P, _P, _P]),
+    "lp_serve_create": (_INT, [ctypes.POINTER(_P), ctypes.c_int, ctypes.c_int, ctypes.c_size_t, ctypes.c_int, _I64, ctypes.c_int]),
+    "lp_serve_submit": (_INT, [_P, _I64, _P, _P, _P, _P]),
+    "lp_serve_poll": (_INT, [_P, ctypes.c_uint64, _P]),
+    "lp_serve_wait": (_INT, [_P, ctypes.c_uint64, ctypes.c_double, _P]),
+    "lp_serve_stats": (_INT, [_P, _P, _P, _P, _P, _P]),
+    "lp_serve_destroy": (_INT, [_P]),
+    "lp_saved_bytes_pair": (_SZ, [_P, _I64, _I64]),
+    "lp_forward_pair": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _P, _P]),
+    "lp_backward_pair": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "lp_graph_capture_pair_step": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _INT,
+                                          ctypes.POINTER(_P)]),
+    "lp_graph_launch": (_INT, [_P, _P]),
+    "lp_graph_destroy": (_INT, [_P]),
     "lp_forward_plain": (_INT, [_INT, _I64, _I64, _P, _P, _P, _P, _P, _P]),
     "lp_backward_plain": (_INT, [_INT, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P]),
 }

@@ -48,6 +48,15 @@ int fail(int code, const char *fmt, ...) {
     return code;
 }
 
+}  // namespace
+
+// Error reporting shared with the other translation units of the library.
+namespace tvlp_host {
+int set_error(int code, const char *msg) { return fail(code, "%s", msg); }
+}  // namespace tvlp_host
+
+namespace {
+
 int check_hip(hipError_t e, const char *what) {
     if (e == hipSuccess) return LP_OK;
     return fail(LP_EDEVICE, "%s: %s", what, hipGetErrorString(e));
@@ -97,6 +106,8 @@ bool order_supported(int M) {
         if (m == M) return true;
     return false;
 }
+
+constexpr int kMaxChunk = 2048;
 
 int default_chunk(int M) {
     int mult = (256 + M - 1) / M;
@@ -175,13 +186,16 @@ int ensure_ws(lp_plan *p, size_t need, hipStream_t stream) {
     return LP_OK;
 }
 
-// Prefix of chunk counts over a packed varlen batch (single block).
-// Prefix sums over a packed varlen batch (single block): chunk counts (cbase)
-// and the group counts of the forward (gbf, cpwf chunks per group) and adjoint
-// (gbb, cpwb) scans.  Lengths are clamped exactly as seq_view clamps them.
-__global__ __launch_bounds__(1024) void k_build_tables(const int64_t *__restrict__ offsets, int64_t n, int L,
-                                                       int64_t N, int cpwf, int cpwb, int64_t *__restrict__ cbase,
-                                                       int64_t *__restrict__ gbf, int64_t *__restrict__ gbb) {
+// Prefix sums over a sequence table (single block): chunk counts (cbase) and
+// the group counts of the forward (gbf, cpwf chunks per group) and adjoint
+// (gbb, cpwb) scans.  The table is either packed offsets or starts + lens;
+// lengths are clamped exactly as seq_view clamps them.
+__global__ __launch_bounds__(1024) void k_build_tables(const int64_t *__restrict__ offsets,
+                                                       const int64_t *__restrict__ starts,
+                                                       const int64_t *__restrict__ lens, int64_t n, int L,
+                                                       int64_t N, int cpwf, int cpwb, int64_t nch_cap,
+                                                       int64_t *__restrict__ cbase, int64_t *__restrict__ gbf,
+                                                       int64_t *__restrict__ gbb, int *__restrict__ status) {
     __shared__ int64_t part[3][1024];
     __shared__ int64_t carry[3];
     if (threadIdx.x < 3) carry[threadIdx.x] = 0;
@@ -190,8 +204,14 @@ __global__ __launch_bounds__(1024) void k_build_tables(const int64_t *__restrict
         const int64_t b = base + threadIdx.x;
         int64_t cnt = 0;
         if (b < n) {
-            const int64_t lo = min(max(offsets[b], (int64_t)0), N);
-            const int64_t hi = min(max(offsets[b + 1], lo), N);
+            int64_t lo, hi;
+            if (offsets) {
+                lo = min(max(offsets[b], (int64_t)0), N);
+                hi = min(max(offsets[b + 1], lo), N);
+            } else {
+                lo = min(max(starts[b], (int64_t)0), N);
+                hi = min(max(lo + lens[b], lo), N);
+            }
             const int64_t len = hi - lo;
             cnt = len <= 0 ? 0 : (len + L - 1) / L;
         }
@@ -229,6 +249,22 @@ __global__ __launch_bounds__(1024) void k_build_tables(const int64_t *__restrict
         cbase[0] = 0;
         gbf[0] = 0;
         gbb[0] = 0;
+        // more chunks than the launch was sized for: the excess is not computed
+        if (carry[0] > nch_cap) atomicOr(status, 2);
+    }
+}
+
+// y = s0 + s1 for a stacked filter pair (n samples each); vec: y, s2 and
+// s2 + n are 16-byte aligned.
+__global__ __launch_bounds__(256) void k_pair_sum(float *__restrict__ y, const float *__restrict__ s2, int64_t n,
+                                                  int vec) {
+    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (vec && i0 + 3 < n) {
+        const float4 u = *reinterpret_cast<const float4 *>(s2 + i0);
+        const float4 v = *reinterpret_cast<const float4 *>(s2 + n + i0);
+        *reinterpret_cast<float4 *>(y + i0) = make_float4(u.x + v.x, u.y + v.y, u.z + v.z, u.w + v.w);
+    } else {
+        for (int64_t i = i0; i < n; ++i) y[i] = s2[i] + s2[n + i];
     }
 }
 
@@ -291,8 +327,8 @@ struct Ops {
                            w.S, w.gf, e, a, zi, w.phiT, w.xs, w.aggf, w.inclf, w.flagf, w.ticketf, w.status);
         tm.end();
         tm.begin("fwd_emit");
-        hipLaunchKernelGGL((k_fwd_rerun<M, RS::G, RS::R>), dim3((unsigned)ceil_div(w.nch, RS::CPW)), dim3(64), 0,
-                           st, w.S, e, a, w.xs, s, zf, w.nch);
+        hipLaunchKernelGGL((k_fwd_rerun2<M, RS::G>), dim3((unsigned)ceil_div(w.nch, RS::CPW)), dim3(64), 0, st,
+                           w.S, e, a, w.xs, s, zf, w.nch);
         tm.end();
     }
 
@@ -310,11 +346,11 @@ struct Ops {
             const size_t dyn = (size_t)RS::CPW * (M + w.S.L) * sizeof(float);
             tm.begin("bwd_emit");
             if (s_in)
-                hipLaunchKernelGGL((k_adj_rerun<M, RS::G, RS::R, true, true>), dim3(grid), dim3(64), dyn, st, w.S,
-                                   g, a, e, s_in, w.xs, w.yend, (double *)nullptr, ge, ga, w.nch, 1);
+                hipLaunchKernelGGL((k_adj_emit2<M, RS::G, true>), dim3(grid), dim3(64), dyn, st, w.S, g, a, e, s_in,
+                                   w.xs, w.yend, ge, ga, w.nch);
             else
-                hipLaunchKernelGGL((k_adj_rerun<M, RS::G, RS::R, true, false>), dim3(grid), dim3(64), dyn, st, w.S,
-                                   g, a, e, s_in, w.xs, w.yend, (double *)nullptr, ge, ga, w.nch, 1);
+                hipLaunchKernelGGL((k_adj_emit2<M, RS::G, false>), dim3(grid), dim3(64), dyn, st, w.S, g, a, e,
+                                   s_in, w.xs, w.yend, ge, ga, w.nch);
             tm.end();
         }
     }
@@ -393,12 +429,16 @@ int64_t uniform_nchunks(int64_t B, int64_t T, int L) { return B * ceil_div(T, L)
 // Resolves sequence tables, group counts and workspace regions for one call.
 template <class O>
 int prepare(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, const void *saved, hipStream_t st,
-            typename O::Bufs &w) {
+            typename O::Bufs &w, const int64_t *starts = nullptr, const int64_t *lens = nullptr,
+            int64_t bound = 0) {
     const int M = p->M, L = p->L;
     const int cpwf = O::FS::CPW, cpwb = O::RS::CPW;
     int64_t nch, ngf, ngb;
-    if (offsets) {
-        nch = ceil_div(T_or_N, L) + B;
+    const bool tabled = offsets || starts;
+    if (tabled) {
+        // non-overlapping sequences inside [0, N) hold at most N samples
+        const int64_t tot = (bound > 0 && bound < T_or_N) ? bound : T_or_N;
+        nch = ceil_div(tot, L) + B;
         ngf = ceil_div(nch, cpwf) + B;
         ngb = ceil_div(nch, cpwb) + B;
     } else {
@@ -411,16 +451,18 @@ int prepare(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, const
     if (int r = ensure_ws(p, lay.total, st)) return r;
     char *ws = (char *)p->ws;
     w.nch = nch;
-    w.S = Seqs{nullptr, nullptr, offsets ? 0 : T_or_N, B, L, offsets ? T_or_N : 0, nch};
+    w.S = Seqs{nullptr, nullptr, nullptr, nullptr, tabled ? 0 : T_or_N, B, L, tabled ? T_or_N : 0, nch, 0};
     w.gf = Groups{nullptr, ngf, cpwf};
     w.gb = Groups{nullptr, ngb, cpwb};
-    if (offsets) {
+    if (tabled) {
         int64_t *cb = (int64_t *)(ws + lay.cbase);
         int64_t *gbf = (int64_t *)(ws + lay.gbf);
         int64_t *gbb = (int64_t *)(ws + lay.gbb);
-        hipLaunchKernelGGL(k_build_tables, dim3(1), dim3(1024), 0, st, offsets, B, L, T_or_N, cpwf, cpwb, cb, gbf,
-                           gbb);
+        hipLaunchKernelGGL(k_build_tables, dim3(1), dim3(1024), 0, st, offsets, starts, lens, B, L, T_or_N, cpwf,
+                           cpwb, nch, cb, gbf, gbb, (int *)(ws + lay.status));
         w.S.offsets = offsets;
+        w.S.starts = starts;
+        w.S.lens = lens;
         w.S.cbase = cb;
         w.gf.gbase = gbf;
         w.gb.gbase = gbb;
@@ -447,7 +489,8 @@ int prepare(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, const
 
 // Common driver of the uniform and varlen forward.
 int forward_impl(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, const float *e, const float *a,
-                 const double *zi, float *s, double *zf, void *saved, void *stream) {
+                 const double *zi, float *s, double *zf, void *saved, void *stream,
+                 const int64_t *starts = nullptr, const int64_t *lens = nullptr, int64_t bound = 0) {
     if (int r = check_plan(p)) return r;
     if (B < 1) return fail(LP_EINVAL, "B must be >= 1 (got %lld)", (long long)B);
     if (T_or_N < 1) return fail(LP_EINVAL, "T (or N) must be >= 1 (got %lld)", (long long)T_or_N);
@@ -460,7 +503,7 @@ int forward_impl(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, 
     dispatch(p->M, [&](auto ops) {
         using O = decltype(ops);
         typename O::Bufs w;
-        rc = prepare<O>(p, B, offsets, T_or_N, saved, st, w);
+        rc = prepare<O>(p, B, offsets, T_or_N, saved, st, w, starts, lens, bound);
         if (rc == LP_OK) O::forward(w, e, a, zi, s, zf, st, tm);
     });
     if (rc != LP_OK) return rc;
@@ -469,7 +512,7 @@ int forward_impl(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, 
 
 int backward_impl(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, const float *g, const float *a,
                   const float *e, const double *zi, const float *s, const void *saved, float *ge, float *ga,
-                  double *gzi, void *stream) {
+                  double *gzi, void *stream, int64_t gshare = 0) {
     if (int r = check_plan(p)) return r;
     if (B < 1) return fail(LP_EINVAL, "B must be >= 1 (got %lld)", (long long)B);
     if (T_or_N < 1) return fail(LP_EINVAL, "T (or N) must be >= 1 (got %lld)", (long long)T_or_N);
@@ -486,6 +529,7 @@ int backward_impl(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N,
         using O = decltype(ops);
         typename O::Bufs w;
         rc = prepare<O>(p, B, offsets, T_or_N, saved, st, w);
+        w.S.gshare = gshare;
         if (rc == LP_OK) O::backward(w, g, a, e, s, ge, ga, gzi, st, tm);
     });
     if (rc != LP_OK) return rc;
@@ -543,6 +587,8 @@ int lp_plan_destroy(lp_plan *p) {
 int lp_plan_set_chunk(lp_plan *p, int L) {
     if (int r = check_plan(p)) return r;
     if (L < p->M || L % p->M != 0) return fail(LP_EINVAL, "chunk length %d must be a positive multiple of M = %d", L, p->M);
+    // the adjoint emit kernel keeps each of its chunks' s in LDS
+    if (L > kMaxChunk) return fail(LP_EINVAL, "chunk length %d exceeds the maximum %d", L, kMaxChunk);
     p->L = L;
     return LP_OK;
 }
@@ -596,7 +642,8 @@ int lp_plan_status(lp_plan *p) {
     if (v != 0) {
         const int zero = 0;
         (void)hipMemcpy((char *)p->ws + kStatusOffset, &zero, sizeof(int), hipMemcpyHostToDevice);
-        return fail(LP_EDEVICE, "a scan wave timed out waiting for a neighbour group (status %d)", v);
+        if (v & 1) return fail(LP_EDEVICE, "a scan wave timed out waiting for a neighbour group (status %d)", v);
+        return fail(LP_EINVAL, "segments held more samples than total_bound (status %d)", v);
     }
     return LP_OK;
 }
@@ -640,6 +687,69 @@ int lp_backward(lp_plan *p, int64_t B, int64_t T, const float *g, const float *a
     return backward_impl(p, B, nullptr, T, g, a, e, zi, s, saved, grad_e, grad_a, grad_zi, stream);
 }
 
+int lp_plan_autotune(lp_plan *p, int64_t B, int64_t T, int reps, int *chosen, double *best_ms) {
+    if (int r = check_plan(p)) return r;
+    if (B < 1 || T < 1) return fail(LP_EINVAL, "B and T must be >= 1");
+    if (reps < 1) reps = 3;
+    const int M = p->M;
+    // the timed batch keeps T and at most ~32 M samples (beyond that every candidate fills the chip)
+    const int64_t Bt = std::max<int64_t>(1, std::min<int64_t>(B, (int64_t(1) << 25) / T));
+    DeviceGuard dg(p->device);
+    const size_t n = (size_t)Bt * T;
+    float *buf = nullptr;
+    const size_t floats = n * (size_t)(2 * M + 4);  // e, g, s, ge, a, ga
+    if (hipMalloc(&buf, floats * sizeof(float)) != hipSuccess)
+        return fail(LP_ENOMEM, "autotune buffers (%zu bytes)", floats * sizeof(float));
+    // timing does not depend on the values: zero inputs
+    int rc = check_hip(hipMemset(buf, 0, floats * sizeof(float)), "autotune memset");
+    float *e = buf, *g = e + n, *s = g + n, *ge = s + n, *a = ge + n, *ga = a + n * M;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (rc == LP_OK && (hipStreamCreate(&st) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+                        hipEventCreate(&e1) != hipSuccess))
+        rc = fail(LP_EDEVICE, "autotune stream/event creation failed");
+    const int oldL = p->L;
+    const bool timing = p->timing;
+    p->timing = false;
+    int bestL = oldL;
+    float best = 1e30f;
+    std::vector<int> cands;
+    for (int target : {64, 96, 128, 176, 256, 352, 512, 768, 1024}) {
+        const int L = std::max(1, (target + M / 2) / M) * M;
+        if (L <= kMaxChunk && std::find(cands.begin(), cands.end(), L) == cands.end()) cands.push_back(L);
+    }
+    for (int L : cands) {
+        if (rc != LP_OK) break;
+        p->L = L;
+        float bestL_ms = 1e30f;
+        for (int r = 0; r <= reps && rc == LP_OK; ++r) {  // r = 0 warms up (and sizes the workspace)
+            (void)hipEventRecord(e0, st);
+            rc = lp_forward(p, Bt, T, e, a, nullptr, s, nullptr, nullptr, st);
+            if (rc == LP_OK)
+                rc = lp_backward(p, Bt, T, g, a, e, nullptr, nullptr, nullptr, ge, ga, nullptr, st);
+            (void)hipEventRecord(e1, st);
+            if (rc == LP_OK) rc = check_hip(hipEventSynchronize(e1), "autotune sync");
+            float ms = 0.f;
+            if (rc == LP_OK && r > 0 && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) bestL_ms = std::min(bestL_ms, ms);
+        }
+        if (rc == LP_OK && bestL_ms < best) {
+            best = bestL_ms;
+            bestL = L;
+        }
+    }
+    p->timing = timing;
+    p->L = rc == LP_OK ? bestL : oldL;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+    (void)hipFree(buf);
+    if (rc == LP_OK) rc = lp_plan_status(p);  // a scan timeout during tuning is an error, not a choice
+    if (rc != LP_OK) return rc;
+    if (chosen) *chosen = bestL;
+    if (best_ms) *best_ms = (double)best;
+    return LP_OK;
+}
+
 int lp_forward_varlen(lp_plan *p, int64_t B, const int64_t *offsets, int64_t N, const float *e, const float *a,
                       const double *zi, float *s, double *zf, void *saved, void *stream) {
     if (!offsets) return fail(LP_EINVAL, "offsets is NULL");
@@ -651,6 +761,14 @@ int lp_backward_varlen(lp_plan *p, int64_t B, const int64_t *offsets, int64_t N,
                        float *grad_a, double *grad_zi, void *stream) {
     if (!offsets) return fail(LP_EINVAL, "offsets is NULL");
     return backward_impl(p, B, offsets, N, g, a, e, zi, s, saved, grad_e, grad_a, grad_zi, stream);
+}
+
+int lp_forward_segments(lp_plan *p, int64_t B, const int64_t *starts, const int64_t *lens, int64_t N,
+                        int64_t total_bound, const float *e, const float *a, const double *zi, float *s, double *zf,
+                        void *stream) {
+    if (!starts || !lens) return fail(LP_EINVAL, "starts and lens are required");
+    if (total_bound < 0) return fail(LP_EINVAL, "total_bound must be >= 0");
+    return forward_impl(p, B, nullptr, N, e, a, zi, s, zf, nullptr, stream, starts, lens, total_bound);
 }
 
 int lp_forward_plain(int M, int64_t B, int64_t T, const float *e, const float *a, const double *zi, float *s,
@@ -674,6 +792,98 @@ int lp_backward_plain(int M, int64_t B, int64_t T, const float *g, const float *
     });
     if (!ok) return fail(LP_EINVAL, "order M = %d is not compiled", M);
     return check_hip(hipGetLastError(), "kernel launch (plain backward)");
+}
+
+size_t lp_saved_bytes_pair(const lp_plan *p, int64_t B, int64_t T) { return lp_saved_bytes(p, 2 * B, T); }
+
+int lp_forward_pair(lp_plan *p, int64_t B, int64_t T, const float *e2, const float *a2, float *y, float *s2,
+                    void *saved, void *stream) {
+    if (!y || !s2) return fail(LP_EINVAL, "y and s2 are required");
+    if (B < 1 || T < 1) return fail(LP_EINVAL, "B and T must be >= 1");
+    if (int r = forward_impl(p, 2 * B, nullptr, T, e2, a2, nullptr, s2, nullptr, saved, stream)) return r;
+    DeviceGuard dg(p->device);
+    const int64_t n = B * T;
+    const unsigned grid = (unsigned)ceil_div(ceil_div(n, 4), 256);
+    Timer tm{p, (hipStream_t)stream};
+    tm.begin("pair_sum");
+    const int vec = ((uintptr_t)y % 16 == 0) && ((uintptr_t)s2 % 16 == 0) && (n % 4 == 0);
+    hipLaunchKernelGGL(k_pair_sum, dim3(grid), dim3(256), 0, (hipStream_t)stream, y, s2, n, vec);
+    tm.end();
+    return check_hip(hipGetLastError(), "kernel launch (pair sum)");
+}
+
+int lp_backward_pair(lp_plan *p, int64_t B, int64_t T, const float *g, const float *a2, const float *e2,
+                     const float *s2, const void *saved, float *ge2, float *ga2, void *stream) {
+    if (B < 1 || T < 1) return fail(LP_EINVAL, "B and T must be >= 1");
+    return backward_impl(p, 2 * B, nullptr, T, g, a2, e2, nullptr, s2, saved, ge2, ga2, nullptr, stream, B);
+}
+
+}  // extern "C"
+
+struct lp_graph {
+    int device;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+extern "C" {
+
+int lp_graph_capture_pair_step(lp_plan *p, int64_t B, int64_t T, const float *e2, const float *a2, float *y,
+                               float *s2, void *saved, const float *g, float *ge2, float *ga2, int store_s,
+                               lp_graph **out) {
+    if (!out) return fail(LP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (int r = check_plan(p)) return r;
+    if (int r = lp_plan_reserve(p, 2 * B, T)) return r;
+    DeviceGuard dg(p->device);
+    const bool timing = p->timing;
+    p->timing = false;
+    hipStream_t st = nullptr;
+    if (hipStreamCreate(&st) != hipSuccess) {
+        p->timing = timing;
+        return fail(LP_EDEVICE, "stream creation failed");
+    }
+    int rc = LP_OK;
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        rc = fail(LP_EDEVICE, "hipStreamBeginCapture failed");
+    } else {
+        rc = lp_forward_pair(p, B, T, e2, a2, y, s2, saved, st);
+        if (rc == LP_OK) rc = lp_backward_pair(p, B, T, g, a2, e2, store_s ? s2 : nullptr, saved, ge2, ga2, st);
+        const hipError_t ec = hipStreamEndCapture(st, &graph);
+        if (rc == LP_OK && ec != hipSuccess) rc = fail(LP_EDEVICE, "hipStreamEndCapture failed");
+    }
+    p->timing = timing;
+    lp_graph *gr = nullptr;
+    if (rc == LP_OK) {
+        gr = new (std::nothrow) lp_graph{p->device, graph, nullptr};
+        if (!gr) rc = fail(LP_ENOMEM, "out of host memory");
+    }
+    if (rc == LP_OK && hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0) != hipSuccess)
+        rc = fail(LP_EDEVICE, "hipGraphInstantiate failed");
+    (void)hipStreamDestroy(st);
+    if (rc != LP_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        delete gr;
+        return rc;
+    }
+    *out = gr;
+    return LP_OK;
+}
+
+int lp_graph_launch(lp_graph *gr, void *stream) {
+    if (!gr) return fail(LP_EINVAL, "graph is NULL");
+    DeviceGuard dg(gr->device);
+    return check_hip(hipGraphLaunch(gr->exec, (hipStream_t)stream), "hipGraphLaunch");
+}
+
+int lp_graph_destroy(lp_graph *gr) {
+    if (!gr) return LP_OK;
+    DeviceGuard dg(gr->device);
+    if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+    if (gr->graph) (void)hipGraphDestroy(gr->graph);
+    delete gr;
+    return LP_OK;
 }
 
 }  // extern "C"

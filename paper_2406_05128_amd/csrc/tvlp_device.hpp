@@ -39,12 +39,26 @@ namespace tvlp {
 struct Seqs {
     const int64_t *offsets;
     const int64_t *cbase;
+    // segment-table mode (offsets == nullptr, starts != nullptr): sequence b
+    // occupies [starts[b], starts[b] + lens[b]) of the arrays, in any order,
+    // possibly with gaps; cbase as for packed batches
+    const int64_t *starts;
+    const int64_t *lens;
     int64_t T;
     int64_t n;
     int L;
     int64_t N;    // packed samples (varlen only)
     int64_t nch;  // chunk slots allocated (varlen only)
+    // uniform batches only: when > 0, sequences b and b + gshare read the same
+    // upstream-gradient row (a filter pair sharing dL/dy)
+    int64_t gshare;
 };
+
+// Element offset to add to a sequence's own row index when reading the shared
+// upstream-gradient stream (0 unless the batch is a stacked filter pair).
+__device__ __forceinline__ int64_t gshare_offset(const Seqs &S, int64_t b) {
+    return S.gshare > 0 ? -(b / S.gshare) * S.gshare * S.T : 0;
+}
 
 struct SeqView {
     int64_t start;  // element offset of sample 0
@@ -59,9 +73,15 @@ __device__ __forceinline__ int64_t nchunks_of(int64_t len, int L) {
 
 __device__ __forceinline__ SeqView seq_view(const Seqs &S, int64_t b) {
     SeqView v;
-    if (S.offsets) {
-        const int64_t lo = min(max(S.offsets[b], (int64_t)0), S.N);
-        const int64_t hi = min(max(S.offsets[b + 1], lo), S.N);
+    if (S.offsets || S.starts) {
+        int64_t lo, hi;
+        if (S.offsets) {
+            lo = min(max(S.offsets[b], (int64_t)0), S.N);
+            hi = min(max(S.offsets[b + 1], lo), S.N);
+        } else {
+            lo = min(max(S.starts[b], (int64_t)0), S.N);
+            hi = min(max(lo + S.lens[b], lo), S.N);
+        }
         v.start = lo;
         v.len = hi - lo;
         v.cbase = min(max(S.cbase[b], (int64_t)0), S.nch);
@@ -77,7 +97,7 @@ __device__ __forceinline__ SeqView seq_view(const Seqs &S, int64_t b) {
 
 // Sequence owning global chunk gc: the largest b with cbase[b] <= gc.
 __device__ __forceinline__ int64_t seq_of_chunk(const Seqs &S, int64_t gc) {
-    if (!S.offsets) return gc / nchunks_of(S.T, S.L);
+    if (!S.cbase) return gc / nchunks_of(S.T, S.L);
     int64_t lo = 0, hi = S.n;
     while (hi - lo > 1) {
         int64_t mid = (lo + hi) >> 1;

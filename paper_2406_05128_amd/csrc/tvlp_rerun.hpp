@@ -1,0 +1,283 @@
+// Chunk reruns (G lanes per chunk, DPP butterflies) fed by an LDS row ring.
+//
+// RowRing streams, for the CPW chunks of a wave, one coefficient row (M floats)
+// plus one per-sample scalar (e or g) per step into an LDS ring slot with
+// global_load_lds (no VGPRs held for prefetch).  D steps are kept in flight;
+// before reading slot u the wave waits until at most DMA_N*D vector-memory
+// operations are outstanding, which is only reached once row u has landed
+// (the ring loads are issued unconditionally, one group per step, in order).
+// Rows outside a chunk are replaced by a read of a valid dummy address.
+#pragma once
+
+#include "tvlp_systolic.hpp"
+
+namespace tvlp {
+
+// s_waitcnt immediate that waits for vmcnt <= n only (gfx9 encoding).
+constexpr int waitcnt_vm_only(int n) { return (n & 0xF) | (0x7 << 4) | (0xF << 8) | (((n >> 4) & 0x3) << 14); }
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+template <int M, int CPW, bool DESC>
+struct RowRing {
+    static constexpr int ROWF = CPW * M + CPW;      // floats per step actually used
+    static constexpr int DMA_N = (ROWF + 63) / 64;  // dword DMA instructions per step
+    static constexpr int D = (63 / DMA_N) < 15 ? (63 / DMA_N) : 15;
+    static constexpr int NS = D + 1;
+    static constexpr int SLOT = DMA_N * 64;  // floats per ring slot
+    static constexpr int FLOATS = NS * SLOT;
+
+    const float *p0[DMA_N];
+    int64_t len[DMA_N];
+    int stride[DMA_N];
+    const float *dummy;
+
+    // my_base: element index of row 0 of this lane's chunk; my_len: its rows
+    // (0 if the lane's chunk is inactive); G: lanes per chunk; my_xoff: offset
+    // added to my_base for the scalar stream x.
+    __device__ __forceinline__ void init(const float *a, const float *x, int lane, int64_t my_base,
+                                         int64_t my_len, int G, int64_t my_xoff = 0) {
+        dummy = a;
+#pragma unroll
+        for (int i = 0; i < DMA_N; ++i) {
+            const int j = 64 * i + lane;
+            int k = 0, f = 0;
+            bool coef = false, valid = true;
+            if (j < CPW * M) {
+                k = j / M;
+                f = j % M;
+                coef = true;
+            } else if (j < ROWF) {
+                k = j - CPW * M;
+            } else {
+                valid = false;
+            }
+            const int64_t kb = __shfl(my_base, k * G, 64);
+            const int64_t kl = __shfl(my_len, k * G, 64);
+            const int64_t kx = __shfl(my_xoff, k * G, 64);
+            p0[i] = coef ? a + kb * M + f : x + kb + kx;
+            len[i] = valid ? kl : 0;
+            stride[i] = coef ? M : 1;
+        }
+    }
+
+    __device__ __forceinline__ void issue(float *ring, int u) const {
+        float *dst = ring + (u % NS) * SLOT;
+#pragma unroll
+        for (int i = 0; i < DMA_N; ++i) {
+            const int64_t row = DESC ? len[i] - 1 - u : (int64_t)u;
+            const bool ok = row >= 0 && row < len[i];
+            const float *p = ok ? p0[i] + row * stride[i] : dummy;
+            __builtin_amdgcn_global_load_lds((const void *)p, (lds_void_t *)(dst + 64 * i), 4, 0, 0);
+        }
+    }
+
+    __device__ __forceinline__ static void wait() { __builtin_amdgcn_s_waitcnt(waitcnt_vm_only(DMA_N * D)); }
+    __device__ __forceinline__ static void drain() { __builtin_amdgcn_s_waitcnt(waitcnt_vm_only(0)); }
+    __device__ __forceinline__ static const float *slot_ptr(const float *ring, int u) {
+        return ring + (u % NS) * SLOT;
+    }
+};
+
+// Forward rerun of each chunk from its saved entry state: writes s and, for a
+// sequence's last chunk, zf.  Also recomputes s for the adjoint.
+template <int M, int G>
+__global__ __launch_bounds__(64) void k_fwd_rerun2(Seqs S, const float *__restrict__ e,
+                                                   const float *__restrict__ a,
+                                                   const double *__restrict__ xs,
+                                                   float *__restrict__ s, double *__restrict__ zf,
+                                                   int64_t nch) {
+    constexpr int CPW = 64 / G;
+    constexpr int TPL = (M + G - 1) / G;
+    using RR = RowRing<M, CPW, false>;
+    __shared__ __attribute__((aligned(16))) float ring[RR::FLOATS];
+
+    const int lane = threadIdx.x;
+    const int slot = lane / G, r = lane % G;
+    const int64_t gc = (int64_t)blockIdx.x * CPW + slot;
+    bool active = gc < nch;
+    int64_t b = 0, c = 0, len = 0, base = 0;
+    if (active) {
+        b = seq_of_chunk(S, gc);
+        const SeqView v = seq_view(S, b);
+        c = gc - v.cbase;
+        active = c < v.C;
+        if (active) {
+            base = v.start + c * S.L;
+            len = min((int64_t)S.L, v.len - c * S.L);
+        }
+    }
+    double hist[TPL];
+#pragma unroll
+    for (int m = 0; m < TPL; ++m) {
+        const int k = r * TPL + m;
+        hist[m] = (active && k < M) ? xs[gc * M + k] : 0.0;
+    }
+    RR rr;
+    rr.init(a, e, lane, base, len, G);
+    const int L = S.L;
+    for (int u = 0; u < RR::D; ++u) rr.issue(ring, u);
+    for (int u = 0; u < L; ++u) {
+        rr.issue(ring, u + RR::D);
+        RR::wait();
+        const float *sp = RR::slot_ptr(ring, u);
+        double part = 0.0;
+#pragma unroll
+        for (int m = 0; m < TPL; ++m) {
+            const int tap = r * TPL + m;
+            const float av = sp[slot * M + (tap < M ? tap : 0)];
+            part = fma((double)(tap < M ? av : 0.f), hist[m], part);
+        }
+        const double tot = group_sum<G>(part);
+        const double y = (double)sp[CPW * M + slot] - tot;
+        const double up = dpp_f64<DPP_ROW_SHR1>(hist[TPL - 1]);
+        if (u < len) {
+            if (r == 0) s[base + u] = (float)y;
+#pragma unroll
+            for (int m = TPL - 1; m > 0; --m) hist[m] = hist[m - 1];
+            hist[0] = (r == 0) ? y : up;
+        }
+    }
+    RR::drain();
+    if (zf && active) {
+        const SeqView v = seq_view(S, b);
+        if (c == v.C - 1) {
+#pragma unroll
+            for (int m = 0; m < TPL; ++m) {
+                const int k = r * TPL + m;
+                if (k < M) zf[b * M + k] = hist[m];
+            }
+        }
+    }
+}
+
+// Adjoint rerun of each chunk (push form of Eq. 12, descending), from the
+// carried pending vector yend[gc] (p(len-1-j) = yend[j]); writes ghat and
+// -ghat(t) s(t-i).  s of the chunk comes from `s_in` (stored) or is recomputed
+// from the saved entry state xs into LDS by an ascending pass first.
+template <int M, int G, bool STORED_S>
+__global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restrict__ g,
+                                                  const float *__restrict__ a, const float *__restrict__ e,
+                                                  const float *__restrict__ s_in,
+                                                  const double *__restrict__ xs,
+                                                  const double *__restrict__ yend,
+                                                  float *__restrict__ ge, float *__restrict__ ga,
+                                                  int64_t nch) {
+    constexpr int CPW = 64 / G;
+    constexpr int TPL = (M + G - 1) / G;
+    using RA = RowRing<M, CPW, false>;
+    using RD = RowRing<M, CPW, true>;
+    static_assert(RA::FLOATS == RD::FLOATS, "ring sizes");
+    __shared__ __attribute__((aligned(16))) float ring[RA::FLOATS];
+    extern __shared__ float ssh_dyn[];  // [CPW][M + L]: ssh[M + t] = s(t), ssh[M-1-k] = s(-1-k)
+
+    const int lane = threadIdx.x;
+    const int slot = lane / G, r = lane % G;
+    const int L = S.L;
+    const int64_t gc = (int64_t)blockIdx.x * CPW + slot;
+    bool active = gc < nch;
+    int64_t len = 0, base = 0, goff = 0;
+    if (active) {
+        const int64_t b = seq_of_chunk(S, gc);
+        const SeqView v = seq_view(S, b);
+        const int64_t c = gc - v.cbase;
+        active = c < v.C;
+        if (active) {
+            base = v.start + c * L;
+            len = min((int64_t)L, v.len - c * L);
+            goff = gshare_offset(S, b);
+        }
+    }
+    float *ssh = ssh_dyn + slot * (M + L);
+    for (int k = r; k < M; k += G) ssh[M - 1 - k] = active ? (float)xs[gc * M + k] : 0.f;
+    if constexpr (STORED_S) {
+        for (int t = r; t < L; t += G) ssh[M + t] = (active && t < len) ? s_in[base + t] : 0.f;
+    } else {
+        double hist[TPL];
+#pragma unroll
+        for (int m = 0; m < TPL; ++m) {
+            const int k = r * TPL + m;
+            hist[m] = (active && k < M) ? xs[gc * M + k] : 0.0;
+        }
+        RA ra;
+        ra.init(a, e, lane, base, len, G);
+        for (int u = 0; u < RA::D; ++u) ra.issue(ring, u);
+        for (int u = 0; u < L; ++u) {
+            ra.issue(ring, u + RA::D);
+            RA::wait();
+            const float *sp = RA::slot_ptr(ring, u);
+            double part = 0.0;
+#pragma unroll
+            for (int m = 0; m < TPL; ++m) {
+                const int tap = r * TPL + m;
+                const float av = sp[slot * M + (tap < M ? tap : 0)];
+                part = fma((double)(tap < M ? av : 0.f), hist[m], part);
+            }
+            const double tot = group_sum<G>(part);
+            const double y = (double)sp[CPW * M + slot] - tot;
+            const double up = dpp_f64<DPP_ROW_SHR1>(hist[TPL - 1]);
+            if (r == 0) ssh[M + u] = (float)y;
+            if (u < len) {
+#pragma unroll
+                for (int m = TPL - 1; m > 0; --m) hist[m] = hist[m - 1];
+                hist[0] = (r == 0) ? y : up;
+            }
+        }
+        RA::drain();
+    }
+    __syncthreads();
+
+    // ---- descending adjoint pass
+    double P[TPL], P0 = 0.0;
+#pragma unroll
+    for (int m = 0; m < TPL; ++m) P[m] = 0.0;
+    if (active) {
+        P0 = yend[gc * M + 0];
+#pragma unroll
+        for (int m = 0; m < TPL; ++m) {
+            const int i = r * TPL + m + 1;
+            P[m] = (i < M) ? yend[gc * M + i] : 0.0;
+        }
+    }
+    RD rd;
+    rd.init(a, g, lane, base, len, G, goff);
+    for (int u = 0; u < RD::D; ++u) rd.issue(ring, u);
+    for (int u = 0; u < L; ++u) {
+        rd.issue(ring, u + RD::D);
+        RD::wait();
+        const float *sp = RD::slot_ptr(ring, u);
+        const int64_t t = len - 1 - u;
+        const double gh = (double)sp[CPW * M + slot] + P0;
+        double np[TPL];
+        float gav[TPL];
+#pragma unroll
+        for (int m = 0; m < TPL; ++m) {
+            const int tap = r * TPL + m;
+            const float av = tap < M ? sp[slot * M + tap] : 0.f;
+            np[m] = fma(-(double)av, gh, P[m]);
+            const int64_t si = M + t - (tap + 1);
+            const float sv = ssh[si >= 0 ? si : 0];
+            gav[m] = (float)(-gh * (double)sv);
+        }
+        // cross-lane moves by every lane, then the step is committed where valid
+        const double down = dpp_f64<DPP_ROW_SHL1>(np[0]);
+        const double b0 = group_bcast0<G>(np[0], r);
+        if (u < len) {
+            if (ga) {
+#pragma unroll
+                for (int m = 0; m < TPL; ++m) {
+                    const int tap = r * TPL + m;
+                    if (tap < M) ga[(base + t) * M + tap] = gav[m];
+                }
+            }
+            if (ge && r == 0) ge[base + t] = (float)gh;
+            P0 = b0;
+#pragma unroll
+            for (int m = 0; m + 1 < TPL; ++m) P[m] = np[m + 1];
+            P[TPL - 1] = (r == G - 1) ? 0.0 : down;
+        }
+    }
+    RD::drain();
+}
+
+}  // namespace tvlp

@@ -23,7 +23,7 @@
 // Waits are bounded: on timeout the wave raises status[0] and continues.
 #pragma once
 
-#include "tvlp_systolic.hpp"
+#include "tvlp_rerun.hpp"
 
 namespace tvlp {
 
@@ -406,11 +406,11 @@ __global__ __launch_bounds__(64) void k_fwd_scan(Seqs S, Groups GR, const float 
 
 template <int M, int G, int R>
 struct BwdScanShape {
-    using SL = Slab<M, G, R>;
-    static constexpr int CPW = SL::CPW;
-    static constexpr int SLAB_BYTES = (CPW * SL::STRIDE + CPW * R) * 4;
+    static constexpr int CPW = 64 / G;
+    using RD = RowRing<M, CPW, true>;
+    static constexpr int RING_BYTES = RD::FLOATS * 4;
     static constexpr int MAT_BYTES = (3 * M * M + 4 * M + CPW * M) * 8;
-    static constexpr int LDS_BYTES = SLAB_BYTES > MAT_BYTES ? SLAB_BYTES : MAT_BYTES;
+    static constexpr int LDS_BYTES = RING_BYTES > MAT_BYTES ? RING_BYTES : MAT_BYTES;
 };
 
 template <int M, int G, int R>
@@ -421,13 +421,12 @@ __global__ __launch_bounds__(64) void k_bwd_scan(Seqs S, Groups GR, const float 
                                                  int *__restrict__ flags, unsigned *__restrict__ ticket,
                                                  int *__restrict__ status) {
     using SH = BwdScanShape<M, G, R>;
-    using SL = typename SH::SL;
+    using RD = typename SH::RD;
     constexpr int CPW = SH::CPW;
     constexpr int TPL = (M + G - 1) / G;
     constexpr int MM = M * M;
     __shared__ __attribute__((aligned(16))) unsigned char lds_raw[SH::LDS_BYTES];
-    float *sa = reinterpret_cast<float *>(lds_raw);
-    float *sg = sa + CPW * SL::STRIDE;
+    float *ring = reinterpret_cast<float *>(lds_raw);
     double *PS = reinterpret_cast<double *>(lds_raw);  // aggregate Psi, row-major
     double *FT = PS + MM;                              // Phi_k^T row-major (= Phi_k column-major)
     double *QT = FT + MM;
@@ -464,39 +463,37 @@ __global__ __launch_bounds__(64) void k_bwd_scan(Seqs S, Groups GR, const float 
 #pragma unroll
     for (int m = 0; m < TPL; ++m) P[m] = 0.0;
     {
-        SL slab;
-        slab.prefetch(a, g_in, base, len, len - R, r, act);
-        for (int j0 = 0; j0 < L; j0 += R) {
-            __syncthreads();
-            slab.commit(sa, sg, slot, r);
-            __syncthreads();
-            if (j0 + R < L) slab.prefetch(a, g_in, base, len, len - j0 - 2 * R, r, act);
+        RD rd;
+        rd.init(a, g_in, lane, base, len, G, gshare_offset(S, b));
+        for (int u = 0; u < RD::D; ++u) rd.issue(ring, u);
+        for (int u = 0; u < L; ++u) {
+            rd.issue(ring, u + RD::D);
+            RD::wait();
+            const float *sp = RD::slot_ptr(ring, u);
+            const double gh = (double)sp[CPW * M + slot] + P0;
+            double np[TPL];
 #pragma unroll
-            for (int k = 0; k < R; ++k) {
-                const int u = j0 + k;
-                const int lr = R - 1 - k;
-                const double gh = (double)sg[slot * R + lr] + P0;
-                double np[TPL];
+            for (int m = 0; m < TPL; ++m) {
+                const int tap = r * TPL + m;
+                const float av = tap < M ? sp[slot * M + tap] : 0.f;
+                np[m] = fma(-(double)av, gh, P[m]);
+            }
+            const double down = dpp_f64<DPP_ROW_SHL1>(np[0]);
+            const double b0 = group_bcast0<G>(np[0], r);
+            if (u < len) {
+                if (u + 1 < len) {
+                    P0 = b0;
 #pragma unroll
-                for (int m = 0; m < TPL; ++m) {
-                    const int tap = r * TPL + m;
-                    const float av = (tap < M) ? sa[slot * SL::STRIDE + lr * M + tap] : 0.f;
-                    np[m] = fma(-(double)av, gh, P[m]);
-                }
-                if (u < len) {
-                    if (u + 1 < len) {
-                        const double down = dpp_f64<DPP_ROW_SHL1>(np[0]);
-                        P0 = group_bcast0<G>(np[0], r);
+                    for (int m = 0; m + 1 < TPL; ++m) P[m] = np[m + 1];
+                    P[TPL - 1] = (r == G - 1) ? 0.0 : down;
+                } else {
+                    // last step of the chunk: keep the un-shifted pendings p(-i)
 #pragma unroll
-                        for (int m = 0; m + 1 < TPL; ++m) P[m] = np[m + 1];
-                        P[TPL - 1] = (r == G - 1) ? 0.0 : down;
-                    } else {
-#pragma unroll
-                        for (int m = 0; m < TPL; ++m) P[m] = np[m];
-                    }
+                    for (int m = 0; m < TPL; ++m) P[m] = np[m];
                 }
             }
         }
+        RD::drain();
     }
     __syncthreads();
     // q_c[i-1] = p(-i): lane slot (tap i) -> LDS
@@ -509,9 +506,24 @@ __global__ __launch_bounds__(64) void k_bwd_scan(Seqs S, Groups GR, const float 
     }
     __syncthreads();
 
-    auto stage_phi = [&](int k) {  // Phi_{c0+k}^T row-major into FT
+    // Phi_{c0+k}^T (row-major) goes through registers: the next chunk's matrix
+    // is fetched while the current one is used, then committed to FT.
+    constexpr int PF = (MM + 63) / 64;
+    double pre[PF];
+    auto fetch_phi = [&](int k) {
         const double *src = phiT + (v.cbase + c0 + k) * MM;
-        for (int q = lane; q < MM; q += 64) FT[q] = src[q];
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int idx = lane + 64 * q;
+            pre[q] = src[idx < MM ? idx : 0];
+        }
+    };
+    auto commit_phi = [&]() {
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int idx = lane + 64 * q;
+            if (idx < MM) FT[idx] = pre[q];
+        }
         __syncthreads();
     };
 
@@ -522,15 +534,18 @@ __global__ __launch_bounds__(64) void k_bwd_scan(Seqs S, Groups GR, const float 
         const int kl = nk - 1;
         const bool kl_has_phi = (c0 + kl) < v.C - 1;
         if (kl_has_phi) {
-            stage_phi(kl);
+            fetch_phi(kl);
+            commit_phi();
             for (int q = lane; q < MM; q += 64) PS[q] = FT[q];
         } else {
             for (int q = lane; q < MM; q += 64) PS[q] = 0.0;
         }
         if (lane < M) vw[lane] = vq[kl * M + lane];
+        if (kl > 0) fetch_phi(kl - 1);
         __syncthreads();
         for (int k = kl - 1; k >= 0; --k) {
-            stage_phi(k);
+            commit_phi();
+            if (k > 0) fetch_phi(k - 1);
             matmul_rm<M>(FT, PS, QT, lane);
             double wn = 0.0;
             if (lane < M) wn = matvec_rm<M>(FT, vw, vq[k * M + lane], lane);
@@ -582,12 +597,14 @@ __global__ __launch_bounds__(64) void k_bwd_scan(Seqs S, Groups GR, const float 
         __syncthreads();
     }
     // ---- per-chunk terminal pending vectors, right to left
+    if (c0 + nk - 1 < v.C - 1) fetch_phi(nk - 1);
     for (int k = nk - 1; k >= 0; --k) {
         const int64_t cc = c0 + k;
         if (lane < M) yend[(v.cbase + cc) * M + lane] = y;
         if (cc == 0 && !grad_zi) break;
         const bool has_phi = cc < v.C - 1;
-        if (has_phi) stage_phi(k);
+        if (has_phi) commit_phi();
+        if (k > 0) fetch_phi(k - 1);  // chunk k-1 < C-1 always carries a transition
         if (lane < M) vy[lane] = y;
         __syncthreads();
         if (lane < M) y = (has_phi ? matvec_rm<M>(FT, vy, 0.0, lane) : 0.0) + vq[k * M + lane];

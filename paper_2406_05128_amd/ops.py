@@ -74,11 +74,35 @@ class Plan:
     def reserve(self, B: int, T: int):
         _lib.check(_lib.load().lp_plan_reserve(self._h, int(B), int(T)))
 
+    def autotune(self, B: int, T: int, reps: int = 3, cache: bool = True) -> dict:
+        """Pick the fastest chunk length for a B x T forward + adjoint step (lp_plan_autotune).
+
+        Results are cached per (device name, M, B, T) in a JSON file
+        ($TVLP_AUTOTUNE_CACHE, default ~/.cache/tvlp/autotune.json); a cached
+        entry is applied without measuring.  Returns {"chunk", "ms", "cached"}.
+        """
+        from . import autotune as _at
+        key = _at.cache_key(torch.cuda.get_device_name(self.device), self.M, B, T)
+        if cache:
+            hit = _at.lookup(key)
+            if hit is not None:
+                self.set_chunk(hit["chunk"])
+                return {**hit, "cached": True}
+        L = ctypes.c_int()
+        ms = ctypes.c_double()
+        _lib.check(_lib.load().lp_plan_autotune(self._h, int(B), int(T), int(reps), ctypes.byref(L),
+                                                ctypes.byref(ms)))
+        res = {"chunk": int(L.value), "ms": float(ms.value)}
+        if cache:
+            _at.store(key, res)
+        return {**res, "cached": False}
+
     def set_timing(self, on: bool = True):
         _lib.check(_lib.load().lp_plan_set_timing(self._h, 1 if on else 0))
 
     def check_status(self):
-        """Synchronise and raise if a scan wave of this plan timed out waiting for a neighbour."""
+        """Synchronise; raise if a scan wave timed out waiting for a neighbour group (LP_EDEVICE) or a
+        segment table held more samples than its total_bound (LP_EINVAL).  Clears the flag."""
         _lib.check(_lib.load().lp_plan_status(self._h))
 
     def reset_timings(self):
@@ -175,6 +199,108 @@ class Plan:
                                                   _ptr(zi), _ptr(s), _ptr(saved), _ptr(ge), _ptr(ga), _ptr(gz),
                                                   _stream(g.device)))
         return ge, ga, gz
+
+    # ------------------------------------------------------------ segment tables (serving)
+    def forward_segments(self, e: torch.Tensor, a: torch.Tensor, starts: torch.Tensor, lens: torch.Tensor,
+                         state: Optional[torch.Tensor] = None, s: Optional[torch.Tensor] = None,
+                         total_bound: int = 0):
+        """Sequence b = samples [starts[b], starts[b] + lens[b]) of e [N], a [N,M]; non-overlapping.
+
+        `state` float64 [B,M] is read as the initial state and overwritten with the
+        final state of every sequence with lens[b] > 0 (in place).  Returns s [N]
+        (only the covered samples are written).
+        """
+        _need(e, "e", torch.float32, 1)
+        _need(a, "a", torch.float32, 2)
+        _need(starts, "starts", torch.int64, 1)
+        _need(lens, "lens", torch.int64, 1)
+        N = e.shape[0]
+        B = starts.shape[0]
+        if lens.shape[0] != B:
+            raise ValueError("starts and lens must have the same length")
+        if state is not None:
+            _need(state, "state", torch.float64, 2)
+            if state.shape != (B, self.M):
+                raise ValueError(f"state must have shape {(B, self.M)}")
+        if s is None:
+            s = torch.empty_like(e)
+        else:
+            _need(s, "s", torch.float32, 1)
+        _lib.check(_lib.load().lp_forward_segments(self._h, B, _ptr(starts), _ptr(lens), N, int(total_bound),
+                                                   _ptr(e), _ptr(a), _ptr(state), _ptr(s), _ptr(state),
+                                                   _stream(e.device)))
+        return s
+
+    # ------------------------------------------------------------ filter pair (Eq. 1)
+    def saved_bytes_pair(self, B: int, T: int) -> int:
+        return int(_lib.load().lp_saved_bytes_pair(self._h, int(B), int(T)))
+
+    def forward_pair(self, e2: torch.Tensor, a2: torch.Tensor, y: Optional[torch.Tensor] = None,
+                     s2: Optional[torch.Tensor] = None, saved: Optional[torch.Tensor] = None):
+        """Two filters per item, stacked: e2 [2,B,T], a2 [2,B,T,M] -> (y = s2[0] + s2[1], s2, saved)."""
+        _need(e2, "e2", torch.float32, 3)
+        _need(a2, "a2", torch.float32, 4)
+        _, B, T = e2.shape
+        if a2.shape != (2, B, T, self.M):
+            raise ValueError(f"a2 must have shape {(2, B, T, self.M)}")
+        if y is None:
+            y = torch.empty((B, T), dtype=torch.float32, device=e2.device)
+        else:
+            _need(y, "y", torch.float32, 2)
+            if y.shape != (B, T):
+                raise ValueError(f"y must have shape {(B, T)}")
+        if s2 is None:
+            s2 = torch.empty_like(e2)
+        else:
+            _need(s2, "s2", torch.float32, 3)
+            if s2.shape != e2.shape:
+                raise ValueError(f"s2 must have shape {tuple(e2.shape)}")
+        if saved is None:
+            saved = torch.empty(self.saved_bytes_pair(B, T), dtype=torch.uint8, device=e2.device)
+        _lib.check(_lib.load().lp_forward_pair(self._h, B, T, _ptr(e2), _ptr(a2), _ptr(y), _ptr(s2),
+                                               _ptr(saved), _stream(e2.device)))
+        return y, s2, saved
+
+    def backward_pair(self, g: torch.Tensor, a2: torch.Tensor, e2: torch.Tensor, saved: torch.Tensor,
+                      s2: Optional[torch.Tensor] = None, need_e: bool = True, need_a: bool = True):
+        """Shared upstream gradient g = dL/dy [B,T] -> (grad_e2 [2,B,T], grad_a2 [2,B,T,M])."""
+        _need(g, "g", torch.float32, 2)
+        B, T = g.shape
+        ge2 = torch.empty_like(e2) if need_e else None
+        ga2 = torch.empty_like(a2) if need_a else None
+        _lib.check(_lib.load().lp_backward_pair(self._h, B, T, _ptr(g), _ptr(a2), _ptr(e2), _ptr(s2),
+                                                _ptr(saved), _ptr(ge2), _ptr(ga2), _stream(g.device)))
+        return ge2, ga2
+
+
+class PairStepGraph:
+    """A captured hipGraph of one forward + adjoint step of a filter pair on fixed buffers."""
+
+    def __init__(self, plan: Plan, e2, a2, y, s2, saved, g, ge2, ga2, store_s: bool = False):
+        self.plan = plan
+        self.buffers = (e2, a2, y, s2, saved, g, ge2, ga2)  # keep alive
+        _, B, T = e2.shape
+        h = ctypes.c_void_p()
+        torch.cuda.synchronize(e2.device)
+        _lib.check(_lib.load().lp_graph_capture_pair_step(
+            plan.handle, B, T, _ptr(e2), _ptr(a2), _ptr(y), _ptr(s2), _ptr(saved), _ptr(g), _ptr(ge2),
+            _ptr(ga2), 1 if store_s else 0, ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream: Optional[torch.cuda.Stream] = None):
+        st = torch.cuda.current_stream() if stream is None else stream
+        _lib.check(_lib.load().lp_graph_launch(self._h, ctypes.c_void_p(st.cuda_stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.load().lp_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------- sequential baseline

@@ -46,14 +46,16 @@ def reflection_to_lpc(k: np.ndarray) -> np.ndarray:
     """
     k = np.asarray(k, dtype=np.float64)
     M = k.shape[-1]
-    a = np.zeros_like(k)
+    # coefficient-major copy: every update below streams contiguous rows
+    kt = np.ascontiguousarray(np.moveaxis(k, -1, 0))
+    at = np.zeros_like(kt)
     for m in range(1, M + 1):
-        km = k[..., m - 1:m]
+        km = kt[m - 1]
         if m > 1:
-            prev = a[..., : m - 1].copy()
-            a[..., : m - 1] = prev + km * prev[..., ::-1]
-        a[..., m - 1] = k[..., m - 1]
-    return a
+            prev = at[: m - 1].copy()
+            at[: m - 1] = prev + km * prev[::-1]
+        at[m - 1] = km
+    return np.ascontiguousarray(np.moveaxis(at, 0, -1))
 
 
 def interp_frames(frames: np.ndarray, T: int, hop: int = HOP) -> np.ndarray:

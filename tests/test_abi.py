@@ -48,3 +48,25 @@ def test_null_plan_and_bad_sizes_are_errors():
     assert lib.lp_forward_plain(16, 1, 1, None, None, None, None, None, None) == _lib.LP_EINVAL
     assert lib.lp_backward_plain(16, 1, 1, None, None, None, None, None, None, None, None) == _lib.LP_EINVAL
     assert lib.lp_plan_destroy(None) == _lib.LP_OK
+
+
+def test_segments_pair_graph_and_server_argument_errors():
+    """Argument checks that return before any device call."""
+    lib = _lib.load()
+    assert lib.lp_forward_segments(None, 1, None, None, 10, 0, None, None, None, None, None, None) == _lib.LP_EINVAL
+    assert "starts" in _lib.last_error()
+    assert lib.lp_forward_pair(None, 1, 1, None, None, None, None, None, None) == _lib.LP_EINVAL
+    assert lib.lp_graph_launch(None, None) == _lib.LP_EINVAL
+    assert lib.lp_graph_destroy(None) == _lib.LP_OK
+    h = ctypes.c_void_p()
+    assert lib.lp_serve_create(None, 0, 16, 1 << 20, 4, 0, 0) == _lib.LP_EINVAL
+    for slots in (0, -1, 5000):
+        assert lib.lp_serve_create(ctypes.byref(h), 0, 16, 1 << 20, slots, 0, 0) == _lib.LP_EINVAL
+        assert "max_slots" in _lib.last_error()
+        assert not h.value
+    t = ctypes.c_uint64()
+    assert lib.lp_serve_submit(None, 10, None, None, None, ctypes.byref(t)) == _lib.LP_EINVAL
+    assert lib.lp_serve_poll(None, 1, None) == _lib.LP_EINVAL
+    assert lib.lp_serve_wait(None, 1, 0.0, None) == _lib.LP_EINVAL
+    assert lib.lp_serve_stats(None, None, None, None, None, None) == _lib.LP_EINVAL
+    assert lib.lp_serve_destroy(None) == _lib.LP_OK

@@ -214,3 +214,65 @@ def test_long_lookback_chains(tv):
     e, a, g = inputs(2, 120000, 22, seed=41)
     errs = check_all(tv, e, a, g, chunk=22)
     print("long chains (L=22, 5455 chunks/seq):", errs)
+
+
+def _pair_inputs(B, T, M, seed):
+    """Filter pair of the harmonic-plus-noise synthesiser (Eq. 1): H on a pulse train, C on noise."""
+    from synth import pulse_train
+    rng = np.random.default_rng(seed)
+    a_h = make_coeffs(rng, B, T, M, 0.95, 0.98)
+    a_c = make_coeffs(rng, B, T, M, 0.95, 0.98)
+    e_h = pulse_train(rng, B, T)
+    e_c = make_excitation(rng, B, T)
+    g = make_upstream_grad(rng, B, T)
+    return np.stack([e_h, e_c]), np.stack([a_h, a_c]), g
+
+
+def _pair_reference(e2, a2, g):
+    s_h, _ = oracle.lp_forward(e2[0], a2[0])
+    s_c, _ = oracle.lp_forward(e2[1], a2[1])
+    ge_h, ga_h, _ = oracle.lp_backward(g, a2[0], s_h)
+    ge_c, ga_c, _ = oracle.lp_backward(g, a2[1], s_c)
+    return s_h + s_c, np.stack([ge_h, ge_c]), np.stack([ga_h, ga_c])
+
+
+@pytest.mark.parametrize("store_s", [False, True])
+def test_filter_pair(tv, store_s):
+    e2, a2, g = _pair_inputs(3, 5000, 22, seed=51)
+    y_ref, ge_ref, ga_ref = _pair_reference(e2, a2, g)
+    plan = tv.Plan(22, dev())
+    e2d, a2d, gd = to_dev(e2), to_dev(a2), to_dev(g)
+    y, s2, saved = plan.forward_pair(e2d, a2d)
+    ge2, ga2 = plan.backward_pair(gd, a2d, e2d, saved, s2=s2 if store_s else None)
+    plan.check_status()
+    torch.cuda.synchronize()
+    assert per_seq_err(host(y), y_ref) <= TOL
+    for f in range(2):
+        assert per_seq_err(host(ge2)[f], ge_ref[f]) <= TOL
+        assert per_seq_err(host(ga2)[f], ga_ref[f]) <= TOL
+
+
+def test_filter_pair_graph_replays(tv):
+    """Captured pair step: every replay (with eager work in between) equals the eager result."""
+    B, T, M = 2, 4000, 22
+    e2, a2, g = _pair_inputs(B, T, M, seed=52)
+    plan = tv.Plan(M, dev())
+    e2d, a2d, gd = to_dev(e2), to_dev(a2), to_dev(g)
+    y0, s20, sv0 = plan.forward_pair(e2d, a2d)
+    ge0, ga0 = plan.backward_pair(gd, a2d, e2d, sv0)
+    torch.cuda.synchronize()
+    y = torch.empty_like(y0); s2 = torch.empty_like(s20); sv = torch.empty_like(sv0)
+    ge2 = torch.empty_like(ge0); ga2 = torch.empty_like(ga0)
+    graph = tv.PairStepGraph(plan, e2d, a2d, y, s2, sv, gd, ge2, ga2)
+    for rep in range(4):
+        y.fill_(float("nan")); ge2.fill_(float("nan")); ga2.fill_(float("nan"))
+        graph.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(y, y0), rep
+        assert torch.equal(ge2, ge0), rep
+        assert torch.equal(ga2, ga0), rep
+        # eager work between replays
+        plan.forward_pair(e2d, a2d)
+        torch.cuda.synchronize()
+    plan.check_status()
+    graph.close()
