@@ -695,38 +695,44 @@ int lp_plan_autotune(lp_plan *p, int64_t B, int64_t T, int reps, int *chosen, do
     // the timed batch keeps T and at most ~32 M samples (beyond that every candidate fills the chip)
     const int64_t Bt = std::max<int64_t>(1, std::min<int64_t>(B, (int64_t(1) << 25) / T));
     DeviceGuard dg(p->device);
-    const size_t n = (size_t)Bt * T;
-    float *buf = nullptr;
-    const size_t floats = n * (size_t)(2 * M + 4);  // e, g, s, ge, a, ga
-    if (hipMalloc(&buf, floats * sizeof(float)) != hipSuccess)
-        return fail(LP_ENOMEM, "autotune buffers (%zu bytes)", floats * sizeof(float));
-    // timing does not depend on the values: zero inputs
-    int rc = check_hip(hipMemset(buf, 0, floats * sizeof(float)), "autotune memset");
-    float *e = buf, *g = e + n, *s = g + n, *ge = s + n, *a = ge + n, *ga = a + n * M;
-    hipStream_t st = nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (rc == LP_OK && (hipStreamCreate(&st) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
-                        hipEventCreate(&e1) != hipSuccess))
-        rc = fail(LP_EDEVICE, "autotune stream/event creation failed");
-    const int oldL = p->L;
-    const bool timing = p->timing;
-    p->timing = false;
-    int bestL = oldL;
-    float best = 1e30f;
     std::vector<int> cands;
     for (int target : {64, 96, 128, 176, 256, 352, 512, 768, 1024}) {
         const int L = std::max(1, (target + M / 2) / M) * M;
         if (L <= kMaxChunk && std::find(cands.begin(), cands.end(), L) == cands.end()) cands.push_back(L);
     }
+    const int oldL = p->L;
+    size_t saved_bytes = 0;  // the smallest chunk length needs the most saved state
+    for (int L : cands) {
+        p->L = L;
+        saved_bytes = std::max(saved_bytes, lp_saved_bytes(p, Bt, T));
+    }
+    p->L = oldL;
+    const size_t n = (size_t)Bt * T;
+    float *buf = nullptr;
+    const size_t floats = n * (size_t)(2 * M + 4);  // e, g, s, ge, a, ga
+    const size_t bytes = floats * sizeof(float) + saved_bytes;
+    if (hipMalloc(&buf, bytes) != hipSuccess) return fail(LP_ENOMEM, "autotune buffers (%zu bytes)", bytes);
+    // timing does not depend on the values: zero inputs
+    int rc = check_hip(hipMemset(buf, 0, floats * sizeof(float)), "autotune memset");
+    float *e = buf, *g = e + n, *s = g + n, *ge = s + n, *a = ge + n, *ga = a + n * M;
+    void *saved = ga + n * M;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (rc == LP_OK && (hipStreamCreate(&st) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+                        hipEventCreate(&e1) != hipSuccess))
+        rc = fail(LP_EDEVICE, "autotune stream/event creation failed");
+    const bool timing = p->timing;
+    p->timing = false;
+    int bestL = oldL;
+    float best = 1e30f;
     for (int L : cands) {
         if (rc != LP_OK) break;
         p->L = L;
         float bestL_ms = 1e30f;
         for (int r = 0; r <= reps && rc == LP_OK; ++r) {  // r = 0 warms up (and sizes the workspace)
             (void)hipEventRecord(e0, st);
-            rc = lp_forward(p, Bt, T, e, a, nullptr, s, nullptr, nullptr, st);
-            if (rc == LP_OK)
-                rc = lp_backward(p, Bt, T, g, a, e, nullptr, nullptr, nullptr, ge, ga, nullptr, st);
+            rc = lp_forward(p, Bt, T, e, a, nullptr, s, nullptr, saved, st);
+            if (rc == LP_OK) rc = lp_backward(p, Bt, T, g, a, e, nullptr, nullptr, saved, ge, ga, nullptr, st);
             (void)hipEventRecord(e1, st);
             if (rc == LP_OK) rc = check_hip(hipEventSynchronize(e1), "autotune sync");
             float ms = 0.f;

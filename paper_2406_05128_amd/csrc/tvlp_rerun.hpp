@@ -7,6 +7,11 @@
 // operations are outstanding, which is only reached once row u has landed
 // (the ring loads are issued unconditionally, one group per step, in order).
 // Rows outside a chunk are replaced by a read of a valid dummy address.
+//
+// The compiler models a global_load_lds as a 4-byte LDS store at its pointer,
+// not as the 256-byte wave-wide write it is, so it may move the next step's
+// DMA above this step's reads of the slot that DMA overwrites.  Every loop over
+// ring steps therefore starts each step with a scheduling barrier.
 #pragma once
 
 #include "tvlp_systolic.hpp"
@@ -27,17 +32,22 @@ struct RowRing {
     static constexpr int SLOT = DMA_N * 64;  // floats per ring slot
     static constexpr int FLOATS = NS * SLOT;
 
-    const float *p0[DMA_N];
-    int64_t len[DMA_N];
-    int stride[DMA_N];
-    const float *dummy;
+    typedef __attribute__((address_space(1))) const char gchar;
+    typedef __attribute__((address_space(3))) float lfloat;
+
+    // Per DMA instruction: the lane's row-0 address, its current byte offset,
+    // the per-step byte increment and the last valid offset.  Steps walk the
+    // rows 0 .. len-1 (descending: len-1 .. 0) and then repeat the last row
+    // reached, so every address stays inside the lane's chunk; a lane with
+    // no rows reads the first element of `a` throughout.
+    gchar *base[DMA_N];
+    int off[DMA_N], step[DMA_N], lim[DMA_N];
 
     // my_base: element index of row 0 of this lane's chunk; my_len: its rows
     // (0 if the lane's chunk is inactive); G: lanes per chunk; my_xoff: offset
     // added to my_base for the scalar stream x.
     __device__ __forceinline__ void init(const float *a, const float *x, int lane, int64_t my_base,
                                          int64_t my_len, int G, int64_t my_xoff = 0) {
-        dummy = a;
 #pragma unroll
         for (int i = 0; i < DMA_N; ++i) {
             const int j = 64 * i + lane;
@@ -55,27 +65,48 @@ struct RowRing {
             const int64_t kb = __shfl(my_base, k * G, 64);
             const int64_t kl = __shfl(my_len, k * G, 64);
             const int64_t kx = __shfl(my_xoff, k * G, 64);
-            p0[i] = coef ? a + kb * M + f : x + kb + kx;
-            len[i] = valid ? kl : 0;
-            stride[i] = coef ? M : 1;
+            const bool live = valid && kl > 0;
+            const float *p0 = !live ? a : (coef ? a + kb * M + f : x + kb + kx);
+            const int st = live ? (coef ? 4 * M : 4) : 0;
+            base[i] = (gchar *)p0;
+            step[i] = st;
+            lim[i] = live ? st * (int)(kl - 1) : 0;
+            off[i] = DESC ? lim[i] : 0;
         }
     }
 
-    __device__ __forceinline__ void issue(float *ring, int u) const {
-        float *dst = ring + (u % NS) * SLOT;
+    __device__ __forceinline__ void issue(float *ring, int u) {
+        lfloat *dst = (lfloat *)ring + (u % NS) * SLOT;
 #pragma unroll
         for (int i = 0; i < DMA_N; ++i) {
-            const int64_t row = DESC ? len[i] - 1 - u : (int64_t)u;
-            const bool ok = row >= 0 && row < len[i];
-            const float *p = ok ? p0[i] + row * stride[i] : dummy;
-            __builtin_amdgcn_global_load_lds((const void *)p, (lds_void_t *)(dst + 64 * i), 4, 0, 0);
+            __builtin_amdgcn_global_load_lds((const void *)(base[i] + off[i]), (lds_void_t *)(dst + 64 * i), 4, 0,
+                                             0);
+            off[i] = DESC ? max(off[i] - step[i], 0) : min(off[i] + step[i], lim[i]);
         }
     }
 
     __device__ __forceinline__ static void wait() { __builtin_amdgcn_s_waitcnt(waitcnt_vm_only(DMA_N * D)); }
+    // After issue(u + D): row u + 1 has landed (rows u+2 .. u+D may still be in flight).
+    __device__ __forceinline__ static void wait_next() {
+        __builtin_amdgcn_s_waitcnt(waitcnt_vm_only(DMA_N * (D - 1)));
+    }
     __device__ __forceinline__ static void drain() { __builtin_amdgcn_s_waitcnt(waitcnt_vm_only(0)); }
     __device__ __forceinline__ static const float *slot_ptr(const float *ring, int u) {
         return ring + (u % NS) * SLOT;
+    }
+    // The taps r*TPL .. r*TPL+TPL-1 of this lane's chunk row (0 beyond M) and
+    // the chunk's scalar, from ring slot u, as float64.
+    template <int TPL>
+    __device__ __forceinline__ static void load(const float *ring, int u, int slot, int r, double (&av)[TPL],
+                                                double &x) {
+        const float *sp = slot_ptr(ring, u);
+#pragma unroll
+        for (int m = 0; m < TPL; ++m) {
+            const int tap = r * TPL + m;
+            const float v = sp[slot * M + (tap < M ? tap : 0)];
+            av[m] = tap < M ? (double)v : 0.0;
+        }
+        x = (double)sp[CPW * M + slot];
     }
 };
 
@@ -117,26 +148,30 @@ __global__ __launch_bounds__(64) void k_fwd_rerun2(Seqs S, const float *__restri
     rr.init(a, e, lane, base, len, G);
     const int L = S.L;
     for (int u = 0; u < RR::D; ++u) rr.issue(ring, u);
+    RR::wait_next();  // row 0
+    // step u's operands are read from LDS during step u-1
+    double av[TPL], ex;
+    RR::load(ring, 0, slot, r, av, ex);
     for (int u = 0; u < L; ++u) {
+        __builtin_amdgcn_sched_barrier(0);  // see RowRing: no DMA above the previous step's LDS reads
         rr.issue(ring, u + RR::D);
-        RR::wait();
-        const float *sp = RR::slot_ptr(ring, u);
+        RR::wait_next();
+        double nav[TPL], nex;
+        RR::load(ring, u + 1, slot, r, nav, nex);
         double part = 0.0;
 #pragma unroll
-        for (int m = 0; m < TPL; ++m) {
-            const int tap = r * TPL + m;
-            const float av = sp[slot * M + (tap < M ? tap : 0)];
-            part = fma((double)(tap < M ? av : 0.f), hist[m], part);
-        }
+        for (int m = 0; m < TPL; ++m) part = fma(av[m], hist[m], part);
         const double tot = group_sum<G>(part);
-        const double y = (double)sp[CPW * M + slot] - tot;
+        const double y = ex - tot;
         const double up = dpp_f64<DPP_ROW_SHR1>(hist[TPL - 1]);
-        if (u < len) {
-            if (r == 0) s[base + u] = (float)y;
+        const bool live = u < len;
+        if (live && r == 0) s[base + u] = (float)y;
 #pragma unroll
-            for (int m = TPL - 1; m > 0; --m) hist[m] = hist[m - 1];
-            hist[0] = (r == 0) ? y : up;
-        }
+        for (int m = TPL - 1; m > 0; --m) hist[m] = live ? hist[m - 1] : hist[m];
+        hist[0] = live ? ((r == 0) ? y : up) : hist[0];
+#pragma unroll
+        for (int m = 0; m < TPL; ++m) av[m] = nav[m];
+        ex = nex;
     }
     RR::drain();
     if (zf && active) {
@@ -202,26 +237,29 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
         RA ra;
         ra.init(a, e, lane, base, len, G);
         for (int u = 0; u < RA::D; ++u) ra.issue(ring, u);
+        RA::wait_next();  // row 0
+        double av[TPL], ex;
+        RA::load(ring, 0, slot, r, av, ex);
         for (int u = 0; u < L; ++u) {
+            __builtin_amdgcn_sched_barrier(0);
             ra.issue(ring, u + RA::D);
-            RA::wait();
-            const float *sp = RA::slot_ptr(ring, u);
+            RA::wait_next();
+            double nav[TPL], nex;
+            RA::load(ring, u + 1, slot, r, nav, nex);
             double part = 0.0;
 #pragma unroll
-            for (int m = 0; m < TPL; ++m) {
-                const int tap = r * TPL + m;
-                const float av = sp[slot * M + (tap < M ? tap : 0)];
-                part = fma((double)(tap < M ? av : 0.f), hist[m], part);
-            }
+            for (int m = 0; m < TPL; ++m) part = fma(av[m], hist[m], part);
             const double tot = group_sum<G>(part);
-            const double y = (double)sp[CPW * M + slot] - tot;
+            const double y = ex - tot;
             const double up = dpp_f64<DPP_ROW_SHR1>(hist[TPL - 1]);
-            if (r == 0) ssh[M + u] = (float)y;
-            if (u < len) {
+            if (r == 0) ssh[M + u] = (float)y;  // entries at u >= len are never read
+            const bool live = u < len;
 #pragma unroll
-                for (int m = TPL - 1; m > 0; --m) hist[m] = hist[m - 1];
-                hist[0] = (r == 0) ? y : up;
-            }
+            for (int m = TPL - 1; m > 0; --m) hist[m] = live ? hist[m - 1] : hist[m];
+            hist[0] = live ? ((r == 0) ? y : up) : hist[0];
+#pragma unroll
+            for (int m = 0; m < TPL; ++m) av[m] = nav[m];
+            ex = nex;
         }
         RA::drain();
     }
@@ -241,28 +279,43 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
     }
     RD rd;
     rd.init(a, g, lane, base, len, G, goff);
+    // s(t - tap - 1) of the lane's taps at step u (t = len - 1 - u), from LDS
+    auto load_s = [&](int u, float (&sv)[TPL]) {
+        const int t = (int)len - 1 - u;
+#pragma unroll
+        for (int m = 0; m < TPL; ++m) {
+            const int si = M + t - (r * TPL + m + 1);
+            sv[m] = ssh[si >= 0 ? si : 0];
+        }
+    };
     for (int u = 0; u < RD::D; ++u) rd.issue(ring, u);
+    RD::wait_next();  // row 0 (sample len - 1)
+    double av[TPL], gx;
+    float sv[TPL];
+    RD::load(ring, 0, slot, r, av, gx);
+    load_s(0, sv);
     for (int u = 0; u < L; ++u) {
+        __builtin_amdgcn_sched_barrier(0);
         rd.issue(ring, u + RD::D);
-        RD::wait();
-        const float *sp = RD::slot_ptr(ring, u);
+        RD::wait_next();
+        double nav[TPL], ngx;
+        float nsv[TPL];
+        RD::load(ring, u + 1, slot, r, nav, ngx);
+        load_s(u + 1, nsv);
         const int64_t t = len - 1 - u;
-        const double gh = (double)sp[CPW * M + slot] + P0;
+        const double gh = gx + P0;
         double np[TPL];
         float gav[TPL];
 #pragma unroll
         for (int m = 0; m < TPL; ++m) {
-            const int tap = r * TPL + m;
-            const float av = tap < M ? sp[slot * M + tap] : 0.f;
-            np[m] = fma(-(double)av, gh, P[m]);
-            const int64_t si = M + t - (tap + 1);
-            const float sv = ssh[si >= 0 ? si : 0];
-            gav[m] = (float)(-gh * (double)sv);
+            np[m] = fma(-av[m], gh, P[m]);
+            gav[m] = (float)(-gh * (double)sv[m]);
         }
         // cross-lane moves by every lane, then the step is committed where valid
         const double down = dpp_f64<DPP_ROW_SHL1>(np[0]);
         const double b0 = group_bcast0<G>(np[0], r);
-        if (u < len) {
+        const bool live = u < len;
+        if (live) {
             if (ga) {
 #pragma unroll
                 for (int m = 0; m < TPL; ++m) {
@@ -271,11 +324,17 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
                 }
             }
             if (ge && r == 0) ge[base + t] = (float)gh;
-            P0 = b0;
-#pragma unroll
-            for (int m = 0; m + 1 < TPL; ++m) P[m] = np[m + 1];
-            P[TPL - 1] = (r == G - 1) ? 0.0 : down;
         }
+        P0 = live ? b0 : P0;
+#pragma unroll
+        for (int m = 0; m + 1 < TPL; ++m) P[m] = live ? np[m + 1] : P[m];
+        P[TPL - 1] = live ? ((r == G - 1) ? 0.0 : down) : P[TPL - 1];
+#pragma unroll
+        for (int m = 0; m < TPL; ++m) {
+            av[m] = nav[m];
+            sv[m] = nsv[m];
+        }
+        gx = ngx;
     }
     RD::drain();
 }

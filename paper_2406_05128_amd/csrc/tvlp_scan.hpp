@@ -184,7 +184,7 @@ struct FwdScanShape {
 constexpr int waitcnt_vm(int n) { return (n & 0xF) | (0x7 << 4) | (0xF << 8) | (((n >> 4) & 0x3) << 14); }
 
 template <int M, int LPC, int CPL, int R>
-__global__ __launch_bounds__(64) void k_fwd_scan(Seqs S, Groups GR, const float *__restrict__ e,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_fwd_scan(Seqs S, Groups GR, const float *__restrict__ e,
                                                  const float *__restrict__ a, const double *__restrict__ zi,
                                                  double *__restrict__ phiT, double *__restrict__ xs,
                                                  double *__restrict__ aggbuf, double *__restrict__ inclbuf,
@@ -233,8 +233,9 @@ __global__ __launch_bounds__(64) void k_fwd_scan(Seqs S, Groups GR, const float 
         // Per-lane DMA sources: instruction i, lane l moves ring float j = 64 i + l,
         // which is coefficient (k, f) = (j / M, j % M) for j < CPW*M and the
         // excitation value of chunk j - CPW*M above that.  Rows advance by M floats.
-        const float *src[SH::DMA_N];
-        int stride[SH::DMA_N];
+        typedef __attribute__((address_space(1))) const char gchar;
+        gchar *src[SH::DMA_N];
+        unsigned off[SH::DMA_N], step[SH::DMA_N], lim[SH::DMA_N];  // bytes
 #pragma unroll
         for (int i = 0; i < SH::DMA_N; ++i) {
             const int j = 64 * i + lane;
@@ -253,23 +254,31 @@ __global__ __launch_bounds__(64) void k_fwd_scan(Seqs S, Groups GR, const float 
                     st = 1;
                 }
             }
-            src[i] = p;
-            stride[i] = st;
+            src[i] = (gchar *)p;
+            off[i] = 0;
+            step[i] = 4u * (unsigned)st;
+            lim[i] = 4u * (unsigned)st * (unsigned)(L - 1);
         }
         float *ring = reinterpret_cast<float *>(lds_raw);
-        auto issue = [&](int t) {  // rows t of every chunk into ring slot t % NS (rows >= L: dummy)
-            const int ts = t < L ? t : 0;
-            float *dst = ring + (t % SH::NS) * (SH::DMA_N * 64);
+        typedef __attribute__((address_space(3))) float lfloat;
+        lfloat *ring_l = (lfloat *)lds_raw;
+        // Rows are issued in order t = 0, 1, ...; every chunk of the basis pass
+        // has exactly L rows, and look-ahead issues past row L-1 repeat that row.
+        auto issue = [&](int t) {  // row min(t, L-1) of every chunk into ring slot t % NS
+            lfloat *dst = ring_l + (t % SH::NS) * (SH::DMA_N * 64);
 #pragma unroll
-            for (int i = 0; i < SH::DMA_N; ++i)
-                __builtin_amdgcn_global_load_lds((const void *)(src[i] + (int64_t)ts * stride[i]),
-                                                 (lds_void *)(dst + 64 * i), 4, 0, 0);
+            for (int i = 0; i < SH::DMA_N; ++i) {
+                __builtin_amdgcn_global_load_lds((const void *)(src[i] + off[i]), (lds_void *)(dst + 64 * i), 4,
+                                                 0, 0);
+                off[i] = min(off[i] + step[i], lim[i]);
+            }
         };
         for (int t = 0; t < SH::D; ++t) issue(t);
         for (int t0 = 0; t0 < L; t0 += M) {
             Unroll<M, 0>::run([&](auto kc) {
                 constexpr int K = decltype(kc)::value;
                 const int t = t0 + K;
+                __builtin_amdgcn_sched_barrier(0);  // no DMA above the previous step's LDS reads
                 issue(t + SH::D);
                 __builtin_amdgcn_s_waitcnt(waitcnt_vm(SH::DMA_N * SH::D));  // row t has landed
                 const float *slotp = ring + (t % SH::NS) * (SH::DMA_N * 64);
@@ -466,32 +475,31 @@ __global__ __launch_bounds__(64) void k_bwd_scan(Seqs S, Groups GR, const float 
         RD rd;
         rd.init(a, g_in, lane, base, len, G, gshare_offset(S, b));
         for (int u = 0; u < RD::D; ++u) rd.issue(ring, u);
+        RD::wait_next();  // row 0 (the chunk's last sample)
+        double av[TPL], gx;
+        RD::load(ring, 0, slot, r, av, gx);
         for (int u = 0; u < L; ++u) {
+            __builtin_amdgcn_sched_barrier(0);
             rd.issue(ring, u + RD::D);
-            RD::wait();
-            const float *sp = RD::slot_ptr(ring, u);
-            const double gh = (double)sp[CPW * M + slot] + P0;
+            RD::wait_next();
+            double nav[TPL], ngx;
+            RD::load(ring, u + 1, slot, r, nav, ngx);
+            const double gh = gx + P0;
             double np[TPL];
 #pragma unroll
-            for (int m = 0; m < TPL; ++m) {
-                const int tap = r * TPL + m;
-                const float av = tap < M ? sp[slot * M + tap] : 0.f;
-                np[m] = fma(-(double)av, gh, P[m]);
-            }
+            for (int m = 0; m < TPL; ++m) np[m] = fma(-av[m], gh, P[m]);
             const double down = dpp_f64<DPP_ROW_SHL1>(np[0]);
             const double b0 = group_bcast0<G>(np[0], r);
-            if (u < len) {
-                if (u + 1 < len) {
-                    P0 = b0;
+            // a step inside the chunk shifts the pendings one tap down; the
+            // chunk's first sample (u = len - 1) keeps the un-shifted p(-i)
+            const bool shift = u + 1 < len, last = u + 1 == len;
+            P0 = shift ? b0 : P0;
 #pragma unroll
-                    for (int m = 0; m + 1 < TPL; ++m) P[m] = np[m + 1];
-                    P[TPL - 1] = (r == G - 1) ? 0.0 : down;
-                } else {
-                    // last step of the chunk: keep the un-shifted pendings p(-i)
+            for (int m = 0; m + 1 < TPL; ++m) P[m] = shift ? np[m + 1] : (last ? np[m] : P[m]);
+            P[TPL - 1] = shift ? ((r == G - 1) ? 0.0 : down) : (last ? np[TPL - 1] : P[TPL - 1]);
 #pragma unroll
-                    for (int m = 0; m < TPL; ++m) P[m] = np[m];
-                }
-            }
+            for (int m = 0; m < TPL; ++m) av[m] = nav[m];
+            gx = ngx;
         }
         RD::drain();
     }

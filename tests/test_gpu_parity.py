@@ -276,3 +276,17 @@ def test_filter_pair_graph_replays(tv):
         torch.cuda.synchronize()
     plan.check_status()
     graph.close()
+
+
+def test_autotuned_chunk_is_valid_and_correct(tv, tmp_path, monkeypatch):
+    monkeypatch.setenv("TVLP_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    M = 22
+    plan = tv.Plan(M, dev())
+    res = plan.autotune(8, 5000, reps=2)
+    assert not res["cached"] and res["ms"] > 0
+    L = res["chunk"]
+    assert L % M == 0 and M <= L <= 2048 and plan.chunk == L
+    again = tv.Plan(M, dev()).autotune(8, 5000)
+    assert again["cached"] and again["chunk"] == L
+    e, a, g = inputs(3, 3001, M, seed=21)
+    check_all(tv, e, a, g, chunk=L)
