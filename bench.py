@@ -163,6 +163,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=100)
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-batch", type=int, default=8)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (hardware-counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -303,6 +305,18 @@ def main():
                "sample": f"{passes} passes over the full batch (B={B}, T={T}, M={M}), forward + adjoint "
                          f"incl. grad_a, float64, {dt:.1f} s"}
         log(f"oracle: {passes} passes in {dt:.1f} s")
+
+    if args.copy_probe_mb > 0:
+        # a plain device-to-device copy of known size: its FETCH_SIZE / WRITE_SIZE counters
+        # calibrate the counters of the filter kernels
+        n = args.copy_probe_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: 3 copies of {args.copy_probe_mb} MiB")
+        del src, dst
 
     serve = None
     if not args.no_serve:
