@@ -176,6 +176,62 @@ def serve_bench(tv, n_req: int, seed: int, slots: int, budget_gib: float, batch:
     return res
 
 
+def stress_bench(tv, steps: int):
+    """Long high-resonance workload (512 x 240000, M = 32, |k| <= 0.995, gamma 0.995).
+
+    Chained carry over 2048-sample chunks (the accurate configuration for these
+    inputs); reports fwd+adjoint throughput, the error against the float64
+    oracle on 8 sampled sequences, and the autotuner's speed-optimal chunk.
+    """
+    import numpy as np
+    import torch
+    import oracle
+    from synth import WORKLOADS
+    from synth.device import stress_inputs
+
+    wl = WORKLOADS["stress_b512_t240000_m32"]
+    B, T, M = wl.B, wl.T, wl.M
+    dev = torch.device("cuda", 0)
+    log(f"stress: building inputs B={B} T={T} M={M} on the device")
+    e, a, g = stress_inputs(B, T, M, wl.kappa, 0.995, wl.seed, dev)
+    plan = tv.Plan(M, dev, 2048, chained=True)
+    tune = tv.Plan(M, dev, chained=True).autotune(B, T, reps=2, cache=False)
+    saved = torch.empty(plan.saved_bytes(B, T), dtype=torch.uint8, device=dev)
+    s = torch.empty_like(e)
+
+    def step():
+        plan.forward(e, a, out=s, saved_out=saved)
+        return plan.backward(g, a, e, saved)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(steps):
+        ge, ga, _ = step()
+    t1.record()
+    torch.cuda.synchronize()
+    plan.check_status()
+    ms = t0.elapsed_time(t1) / steps
+    picks = np.random.default_rng(wl.seed).choice(B, 8, replace=False)
+    worst = {}
+    for b in picks:
+        eb, ab, gb = (x[b:b + 1].cpu().numpy() for x in (e, a, g))
+        s_ref, _ = oracle.lp_forward(eb, ab)
+        ge_ref, ga_ref, _ = oracle.lp_backward(gb, ab, s_ref)
+        for k, x, r in (("s", s[b], s_ref[0]), ("grad_e", ge[b], ge_ref[0]), ("grad_a", ga[b], ga_ref[0])):
+            x = x.cpu().numpy().astype(np.float64)
+            err = float(np.sqrt(np.mean((x - r) ** 2)) / max(np.sqrt(np.mean(r ** 2)), 1e-300))
+            worst[k] = max(worst.get(k, 0.0), err)
+    log(f"stress: {ms:.2f} ms/step, worst rms-rel {worst}")
+    return {"workload": wl.name, "carry": "chained", "chunk": 2048, "ms_per_step": round(ms, 3),
+            "samples_per_s": B * T / (ms * 1e-3),
+            "error_8_sampled_sequences_rms_rel": {k: float(f"{v:.3g}") for k, v in worst.items()},
+            "autotuned_chunk": tune["chunk"], "autotuned_ms": round(tune["ms"], 3),
+            "note": "autotuned chunk optimises speed only; 2048 is used for accuracy on these inputs"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,6 +245,7 @@ def main():
     ap.add_argument("--seq-steps", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-stress", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=100)
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-batch", type=int, default=8)
@@ -349,6 +406,11 @@ def main():
         log(f"copy probe: 3 copies of {args.copy_probe_mb} MiB")
         del src, dst
 
+    stress = None
+    if not args.no_stress:
+        stress = stress_bench(tv, 3)
+        torch.cuda.empty_cache()
+
     serve = None
     if not args.no_serve:
         serve = serve_bench(tv, args.serve_requests, 2024, args.serve_slots, 4.0, args.serve_batch)
@@ -368,6 +430,7 @@ def main():
         "sequential": sequential,
         "cpu_baseline": cpu,
         "serve": serve,
+        "stress": stress,
     }
     print(json.dumps(out), flush=True)
 

@@ -54,9 +54,18 @@ enum {
     LP_EBUDGET = -5
 };
 
-/* Plan flags. */
+/* Plan flags.
+ * LP_FLAG_CHAINED_CARRY: the chunk-to-chunk carry applies each chunk's
+ *   transition to the carried state in turn (one group of chunks after the
+ *   other) instead of composing transitions into group matrices first.  The
+ *   composed products can lose accuracy on strongly resonant, fast-varying
+ *   filters (time-varying pole radii near 1, where single transitions already
+ *   have entries in the thousands); the chained carry keeps the rounding error
+ *   at the level of one transition, at the cost of a serial dependency between
+ *   consecutive groups of a sequence. */
 enum {
-    LP_FLAG_NONE = 0
+    LP_FLAG_NONE = 0,
+    LP_FLAG_CHAINED_CARRY = 1
 };
 
 /* Library version string, e.g. "tvlp 0.1 gfx950". */
@@ -70,7 +79,8 @@ const char *lp_last_error(void);
 int lp_supported_orders(int *out, int cap);
 
 /* Create a plan for filter order M on `device`.  The plan selects the chunk
- * length L (a multiple of M, at least M) used by the chunked kernels. */
+ * length L (a multiple of M, at least M) used by the chunked kernels.  `flags`
+ * is a combination of the LP_FLAG_* values (others: LP_EINVAL). */
 int lp_plan_create(lp_plan **out, int device, int M, int flags);
 int lp_plan_destroy(lp_plan *p);
 

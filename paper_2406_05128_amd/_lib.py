@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libtvlp.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "tvlp.h")
 
 LP_OK, LP_PENDING, LP_EINVAL, LP_ENOMEM, LP_EDEVICE, LP_ENOTFOUND, LP_EBUDGET = 0, 1, -1, -2, -3, -4, -5
+LP_FLAG_NONE, LP_FLAG_CHAINED_CARRY = 0, 1
 _CODES = {LP_EINVAL: "LP_EINVAL", LP_ENOMEM: "LP_ENOMEM", LP_EDEVICE: "LP_EDEVICE",
           LP_ENOTFOUND: "LP_ENOTFOUND", LP_EBUDGET: "LP_EBUDGET"}
 

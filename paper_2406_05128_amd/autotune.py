@@ -16,8 +16,9 @@ def cache_path() -> str:
                           os.path.join(os.path.expanduser("~"), ".cache", "tvlp", "autotune.json"))
 
 
-def cache_key(device_name: str, M: int, B: int, T: int) -> str:
-    return f"{device_name}|M={int(M)}|B={int(B)}|T={int(T)}"
+def cache_key(device_name: str, M: int, B: int, T: int, carry: str = "grouped") -> str:
+    key = f"{device_name}|M={int(M)}|B={int(B)}|T={int(T)}"
+    return key if carry == "grouped" else f"{key}|carry={carry}"
 
 
 def _read(path: str) -> dict:

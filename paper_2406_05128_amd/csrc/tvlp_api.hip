@@ -315,6 +315,7 @@ struct Ops {
         int *flagf, *flagb;
         unsigned *ticketf, *ticketb;
         int *status;
+        int chain;  // chained carry: no matrix products between chunk transitions
     };
 
     static void forward(const Bufs &w, const float *e, const float *a, const double *zi, float *s, double *zf,
@@ -324,7 +325,8 @@ struct Ops {
         hipLaunchKernelGGL(k_scan_reset, dim3(rb), dim3(256), 0, st, w.flagf, w.gf.ngroups, w.ticketf, w.status);
         tm.begin("fwd_scan");
         hipLaunchKernelGGL((k_fwd_scan<M, FS::LPC, FS::CPL, FS::R>), dim3((unsigned)w.gf.ngroups), dim3(64), 0, st,
-                           w.S, w.gf, e, a, zi, w.phiT, w.xs, w.aggf, w.inclf, w.flagf, w.ticketf, w.status);
+                           w.S, w.gf, e, a, zi, w.phiT, w.xs, w.aggf, w.inclf, w.flagf, w.ticketf, w.status,
+                           w.chain);
         tm.end();
         tm.begin("fwd_emit");
         hipLaunchKernelGGL((k_fwd_rerun2<M, RS::G>), dim3((unsigned)ceil_div(w.nch, RS::CPW)), dim3(64), 0, st,
@@ -339,7 +341,8 @@ struct Ops {
         hipLaunchKernelGGL(k_scan_reset, dim3(rb), dim3(256), 0, st, w.flagb, w.gb.ngroups, w.ticketb, w.status);
         tm.begin("bwd_scan");
         hipLaunchKernelGGL((k_bwd_scan<M, RS::G, RS::R>), dim3((unsigned)w.gb.ngroups), dim3(64), 0, st, w.S,
-                           w.gb, g, a, w.phiT, w.yend, gzi, w.aggb, w.inclb, w.flagb, w.ticketb, w.status);
+                           w.gb, g, a, w.phiT, w.yend, gzi, w.aggb, w.inclb, w.flagb, w.ticketb, w.status,
+                           w.chain);
         tm.end();
         if (ge || ga) {
             const unsigned grid = (unsigned)ceil_div(w.nch, RS::CPW);
@@ -484,6 +487,7 @@ int prepare(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, const
     w.ticketf = (unsigned *)(ws + lay.tickets);
     w.ticketb = w.ticketf + 2;
     w.status = (int *)(ws + lay.status);
+    w.chain = (p->flags & LP_FLAG_CHAINED_CARRY) ? 1 : 0;
     return LP_OK;
 }
 
@@ -556,6 +560,7 @@ int lp_plan_create(lp_plan **out, int device, int M, int flags) {
     *out = nullptr;
     if (M < 1 || M > 64) return fail(LP_EINVAL, "order M must be in [1, 64] (got %d)", M);
     if (!order_supported(M)) return fail(LP_EINVAL, "order M = %d has no compiled chunked kernels", M);
+    if (flags & ~LP_FLAG_CHAINED_CARRY) return fail(LP_EINVAL, "unknown plan flags 0x%x", flags);
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
         return fail(LP_EINVAL, "device %d not available", device);

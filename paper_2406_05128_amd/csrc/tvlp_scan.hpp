@@ -189,7 +189,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
                                                  double *__restrict__ phiT, double *__restrict__ xs,
                                                  double *__restrict__ aggbuf, double *__restrict__ inclbuf,
                                                  int *__restrict__ flags, unsigned *__restrict__ ticket,
-                                                 int *__restrict__ status) {
+                                                 int *__restrict__ status, int chain) {
     using SH = FwdScanShape<M, LPC, CPL, R>;
     constexpr int CPW = SH::CPW;
     constexpr int MM = M * M;
@@ -334,8 +334,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     };
 
     const bool last_group = (c0 + CPW >= v.C);
-    // ---- compose the group's map over its transition-carrying chunks
-    if (!last_group) {
+    // ---- compose the group's map over its transition-carrying chunks (not in
+    // chained mode, where every carry is a matrix-vector product)
+    if (!last_group && !chain) {
         // nbasis == CPW here
         stage_chunk(0);
         for (int q = lane; q < MM; q += 64) PT[q] = FT[q];
@@ -389,7 +390,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         }
     }
     // ---- inclusive state for the successors
-    if (!last_group) {
+    if (!last_group && !chain) {
         if (lane < M) vx[lane] = x;
         __syncthreads();
         double xn = 0.0;
@@ -408,6 +409,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
             if (lane < M) x = matvec_cm<M>(FT, vx, vz[lane], lane);
             __syncthreads();
         }
+    }
+    // chained mode: x now enters the next group (a non-last group has CPW
+    // transition-carrying chunks)
+    if (chain && !last_group) {
+        if (lane < M) inclbuf[gid * M + lane] = x;
+        publish_flag(flags, gid, FLAG_INCL, lane);
     }
 }
 
@@ -428,7 +435,7 @@ __global__ __launch_bounds__(64) void k_bwd_scan(Seqs S, Groups GR, const float 
                                                  double *__restrict__ yend, double *__restrict__ grad_zi,
                                                  double *__restrict__ aggbuf, double *__restrict__ inclbuf,
                                                  int *__restrict__ flags, unsigned *__restrict__ ticket,
-                                                 int *__restrict__ status) {
+                                                 int *__restrict__ status, int chain) {
     using SH = BwdScanShape<M, G, R>;
     using RD = typename SH::RD;
     constexpr int CPW = SH::CPW;
@@ -536,8 +543,8 @@ __global__ __launch_bounds__(64) void k_bwd_scan(Seqs S, Groups GR, const float 
     };
 
     const bool seq_last_group = (c0 + CPW >= v.C);
-    // ---- reverse map of the group: y(c0) = Psi y(c0+nk) + w
-    if (g > 0) {
+    // ---- reverse map of the group: y(c0) = Psi y(c0+nk) + w (not in chained mode)
+    if (g > 0 && !chain) {
         // start from the group's last chunk
         const int kl = nk - 1;
         const bool kl_has_phi = (c0 + kl) < v.C - 1;
@@ -595,7 +602,7 @@ __global__ __launch_bounds__(64) void k_bwd_scan(Seqs S, Groups GR, const float 
             __syncthreads();
         }
     }
-    if (g > 0) {
+    if (g > 0 && !chain) {
         if (lane < M) vy[lane] = y;
         __syncthreads();
         double yn = 0.0;
@@ -617,6 +624,11 @@ __global__ __launch_bounds__(64) void k_bwd_scan(Seqs S, Groups GR, const float 
         __syncthreads();
         if (lane < M) y = (has_phi ? matvec_rm<M>(FT, vy, 0.0, lane) : 0.0) + vq[k * M + lane];
         __syncthreads();
+    }
+    // chained mode: y is now the pending vector at the group's first sample
+    if (chain && g > 0) {
+        if (lane < M) inclbuf[gid * M + lane] = y;
+        publish_flag(flags, gid, FLAG_INCL, lane);
     }
     if (g == 0 && grad_zi && lane < M) grad_zi[b * M + lane] = y;
 }

@@ -38,13 +38,17 @@ def _need(t: torch.Tensor, name: str, dtype: torch.dtype, dim: int):
 class Plan:
     """Owns an lp_plan (order M, chunk length, device workspace)."""
 
-    def __init__(self, M: int, device: Optional[torch.device] = None, chunk: Optional[int] = None):
+    def __init__(self, M: int, device: Optional[torch.device] = None, chunk: Optional[int] = None,
+                 chained: bool = False):
+        """chained: LP_FLAG_CHAINED_CARRY (carry chunk by chunk, for strongly resonant inputs)."""
         lib = _lib.load()
         dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self.device = dev
         self.M = int(M)
+        self.chained = bool(chained)
         h = ctypes.c_void_p()
-        _lib.check(lib.lp_plan_create(ctypes.byref(h), dev.index or 0, self.M, 0))
+        _lib.check(lib.lp_plan_create(ctypes.byref(h), dev.index or 0, self.M,
+                                      _lib.LP_FLAG_CHAINED_CARRY if chained else 0))
         self._h = h
         if chunk is not None:
             self.set_chunk(chunk)
@@ -82,7 +86,8 @@ class Plan:
         entry is applied without measuring.  Returns {"chunk", "ms", "cached"}.
         """
         from . import autotune as _at
-        key = _at.cache_key(torch.cuda.get_device_name(self.device), self.M, B, T)
+        key = _at.cache_key(torch.cuda.get_device_name(self.device), self.M, B, T,
+                            "chained" if self.chained else "grouped")
         if cache:
             hit = _at.lookup(key)
             if hit is not None:

@@ -32,6 +32,14 @@ def test_plan_rejects_bad_order(M):
     assert "order" in _lib.last_error()
 
 
+def test_plan_rejects_unknown_flags():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    assert lib.lp_plan_create(ctypes.byref(h), 0, 22, 4) == _lib.LP_EINVAL
+    assert "flags" in _lib.last_error()
+    assert not h.value
+
+
 def test_plan_rejects_uncompiled_order():
     lib = _lib.load()
     h = ctypes.c_void_p()

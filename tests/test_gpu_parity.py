@@ -52,7 +52,7 @@ def inputs(B, T, M, kappa=0.9, gamma=0.98, seed=0, family="iid"):
     return e, a, g
 
 
-def check_all(tv, e, a, g, zi=None, chunk=None, store_s=False, plain=False, tol=TOL):
+def check_all(tv, e, a, g, zi=None, chunk=None, store_s=False, plain=False, tol=TOL, chained=False):
     B, T, M = a.shape
     s_ref, zf_ref = oracle.lp_forward(e, a, zi)
     ge_ref, ga_ref, gz_ref = oracle.lp_backward(g, a, s_ref, zi, need_grad_zi=zi is not None)
@@ -61,7 +61,7 @@ def check_all(tv, e, a, g, zi=None, chunk=None, store_s=False, plain=False, tol=
         s, zf = tv.forward_plain(e_d, a_d, zi_d, want_zf=True)
         ge, ga, gz = tv.backward_plain(g_d, a_d, s, zi_d, need_zi=zi is not None)
     else:
-        plan = tv.Plan(M, dev(), chunk)
+        plan = tv.Plan(M, dev(), chunk, chained=chained)
         s, zf, saved = plan.forward(e_d, a_d, zi_d, want_zf=True)
         ge, ga, gz = plan.backward(g_d, a_d, e_d, saved, s=s if store_s else None, zi=zi_d,
                                    need_zi=zi is not None)
@@ -290,3 +290,24 @@ def test_autotuned_chunk_is_valid_and_correct(tv, tmp_path, monkeypatch):
     assert again["cached"] and again["chunk"] == L
     e, a, g = inputs(3, 3001, M, seed=21)
     check_all(tv, e, a, g, chunk=L)
+
+
+@pytest.mark.parametrize("B,T,M,L", [(3, 5000, 22, 66), (2, 9001, 32, 64), (4, 3000, 16, 32), (3, 2000, 4, 8)])
+def test_chained_carry_matches_oracle(tv, B, T, M, L):
+    e, a, g = inputs(B, T, M, seed=B + T + M)
+    zi = np.random.default_rng(7).standard_normal((B, M)) * 0.1
+    check_all(tv, e, a, g, zi=zi, chunk=L, chained=True)
+
+
+def test_chained_and_grouped_carry_agree(tv):
+    e, a, g = inputs(2, 20000, 22, seed=3)
+    e_d, a_d, g_d = to_dev(e), to_dev(a), to_dev(g)
+    out = []
+    for chained in (False, True):
+        plan = tv.Plan(22, dev(), 66, chained=chained)
+        s, _, saved = plan.forward(e_d, a_d)
+        ge, ga, _ = plan.backward(g_d, a_d, e_d, saved)
+        plan.check_status()
+        out.append((host(s), host(ge), host(ga)))
+    for x, y in zip(*out):
+        assert per_seq_err(x, y.astype(np.float64)) <= 1e-6
