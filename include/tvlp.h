@@ -85,7 +85,8 @@ int lp_plan_create(lp_plan **out, int device, int M, int flags);
 int lp_plan_destroy(lp_plan *p);
 
 /* Override / query the chunk length.  L must be a positive multiple of M and
- * at most 2048 (LP_EINVAL otherwise). */
+ * at most 2048 (at most about 1200 for M < 8, where the adjoint kernel keeps 16
+ * chunks per wave in LDS); LP_EINVAL otherwise. */
 int lp_plan_set_chunk(lp_plan *p, int L);
 int lp_plan_get_chunk(const lp_plan *p);
 
@@ -108,9 +109,10 @@ int lp_plan_set_timing(lp_plan *p, int on);
 int lp_plan_timings(lp_plan *p, char *names, int name_len, double *ms, int64_t *launches, int cap);
 int lp_plan_reset_timings(lp_plan *p);
 
-/* Synchronises the device and reports whether any chunk-scan wave of this
- * plan gave up waiting for a neighbouring group (a failure that leaves the
- * affected results invalid).  Returns LP_OK, or LP_EDEVICE and clears the flag. */
+/* Synchronises the device and reports whether a segment table of this plan
+ * (lp_forward_segments) held more samples than its total_bound since the last
+ * check.  Returns LP_OK, or LP_EINVAL and clears the flag; LP_EDEVICE if the
+ * device reports an error. */
 int lp_plan_status(lp_plan *p);
 
 /* Grow the plan's workspace for a batch of B sequences of length T (or, for

@@ -4,6 +4,7 @@
 #include "tvlp_device.hpp"
 #include "tvlp_systolic.hpp"
 #include "tvlp_scan.hpp"
+#include "tvlp_carry.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -137,7 +138,7 @@ constexpr size_t kStatusOffset = 256;  // byte offset of the scan status word in
 
 // Workspace layout for one call with nch chunks and n samples over B sequences.
 struct WsLayout {
-    size_t xs, phi, yend, cbase, gbf, gbb, aggf, inclf, flagf, aggb, inclb, flagb, tickets, status, total;
+    size_t xs, phi, yend, q, cbase, gbf, gbb, aggf, inclf, aggb, inclb, status, total;
 };
 
 // ngf / ngb: group slots of the forward / adjoint scans.
@@ -145,20 +146,19 @@ WsLayout ws_layout(int M, int64_t nch, int64_t B, int64_t ngf, int64_t ngb) {
     WsLayout w{};
     size_t off = 0;
     const size_t agg = (size_t)(M * M + M) * sizeof(double);
-    w.tickets = off; off += 256;  // fixed offsets: tickets, then the status word
-    w.status = off;  off += 256;
+    off += 256;                  // reserved
+    w.status = off;  off += 256;  // status word at a fixed offset
     w.xs = off;    off += align_up(bytes_state(M, nch));
     w.phi = off;   off += align_up(bytes_phi(M, nch));
-    w.yend = off;  off += align_up(bytes_state(M, nch));
+    w.yend = off;  off += align_up(bytes_state(M, nch));  // adjoint: yend; forward: z of every chunk
+    w.q = off;     off += align_up(bytes_state(M, nch));
     w.cbase = off; off += align_up((size_t)(B + 1) * sizeof(int64_t));
     w.gbf = off;   off += align_up((size_t)(B + 1) * sizeof(int64_t));
     w.gbb = off;   off += align_up((size_t)(B + 1) * sizeof(int64_t));
     w.aggf = off;  off += align_up((size_t)ngf * agg);
     w.inclf = off; off += align_up((size_t)ngf * M * sizeof(double));
-    w.flagf = off; off += align_up((size_t)ngf * sizeof(int));
     w.aggb = off;  off += align_up((size_t)ngb * agg);
     w.inclb = off; off += align_up((size_t)ngb * M * sizeof(double));
-    w.flagb = off; off += align_up((size_t)ngb * sizeof(int));
     w.total = off;
     return w;
 }
@@ -303,6 +303,18 @@ struct RerunShape {
 template <int M>
 struct Ops {
     using FS = FwdShape<M>;
+    // dynamic LDS of the adjoint emit kernel: s and ghat of each of its chunks
+    static size_t emit_lds_bytes(int L) { return (size_t)RerunShape<M>::CPW * (M + 2 * (size_t)L) * sizeof(float); }
+    // longest chunk whose emit kernel fits the 160 KiB LDS of a CU (with its row ring)
+    static int max_chunk() {
+        constexpr size_t lds = 160 * 1024;
+        constexpr size_t ring = RowRing<M, RerunShape<M>::CPW, false>::FLOATS * sizeof(float);
+        const size_t per_l = 2 * RerunShape<M>::CPW * sizeof(float);
+        const size_t fixed = ring + (size_t)RerunShape<M>::CPW * M * sizeof(float);
+        int L = (int)((lds - fixed) / per_l);
+        L = std::min(L, kMaxChunk);
+        return L / M * M;
+    }
     using RS = RerunShape<M>;
 
     // Everything one call needs, resolved by the host driver.
@@ -310,10 +322,8 @@ struct Ops {
         Seqs S;
         Groups gf, gb;
         int64_t nch;
-        double *xs, *phiT, *yend;
-        double *aggf, *inclf, *aggb, *inclb;
-        int *flagf, *flagb;
-        unsigned *ticketf, *ticketb;
+        double *xs, *phiT, *yend, *zbuf, *qbuf;
+        double *aggf, *inclf, *aggb, *inclb;  // group maps and group carries
         int *status;
         int chain;  // chained carry: no matrix products between chunk transitions
     };
@@ -321,12 +331,16 @@ struct Ops {
     static void forward(const Bufs &w, const float *e, const float *a, const double *zi, float *s, double *zf,
                         hipStream_t st, Timer &tm) {
         if (w.nch <= 0) return;
-        const unsigned rb = (unsigned)std::max<int64_t>(1, ceil_div(w.gf.ngroups, 256));
-        hipLaunchKernelGGL(k_scan_reset, dim3(rb), dim3(256), 0, st, w.flagf, w.gf.ngroups, w.ticketf, w.status);
         tm.begin("fwd_scan");
-        hipLaunchKernelGGL((k_fwd_scan<M, FS::LPC, FS::CPL, FS::R>), dim3((unsigned)w.gf.ngroups), dim3(64), 0, st,
-                           w.S, w.gf, e, a, zi, w.phiT, w.xs, w.aggf, w.inclf, w.flagf, w.ticketf, w.status,
-                           w.chain);
+        hipLaunchKernelGGL((k_fwd_local<M, FS::LPC, FS::CPL, FS::R>), dim3((unsigned)w.gf.ngroups), dim3(64), 0, st,
+                           w.S, w.gf, e, a, w.phiT, w.zbuf, w.aggf, w.chain);
+        tm.end();
+        tm.begin("fwd_carry");
+        hipLaunchKernelGGL((k_fwd_chain<M>), dim3((unsigned)w.S.n), dim3(64), 0, st, w.S, w.gf, zi, w.phiT, w.zbuf,
+                           w.aggf, w.inclf, w.xs, w.chain);
+        if (!w.chain)
+            hipLaunchKernelGGL((k_fwd_expand<M, FS::CPW>), dim3((unsigned)w.gf.ngroups), dim3(64), 0, st, w.S, w.gf,
+                               w.phiT, w.zbuf, w.inclf, w.xs);
         tm.end();
         tm.begin("fwd_emit");
         hipLaunchKernelGGL((k_fwd_rerun2<M, RS::G>), dim3((unsigned)ceil_div(w.nch, RS::CPW)), dim3(64), 0, st,
@@ -337,16 +351,20 @@ struct Ops {
     static void backward(const Bufs &w, const float *g, const float *a, const float *e, const float *s_in,
                          float *ge, float *ga, double *gzi, hipStream_t st, Timer &tm) {
         if (w.nch <= 0) return;
-        const unsigned rb = (unsigned)std::max<int64_t>(1, ceil_div(w.gb.ngroups, 256));
-        hipLaunchKernelGGL(k_scan_reset, dim3(rb), dim3(256), 0, st, w.flagb, w.gb.ngroups, w.ticketb, w.status);
         tm.begin("bwd_scan");
-        hipLaunchKernelGGL((k_bwd_scan<M, RS::G, RS::R>), dim3((unsigned)w.gb.ngroups), dim3(64), 0, st, w.S,
-                           w.gb, g, a, w.phiT, w.yend, gzi, w.aggb, w.inclb, w.flagb, w.ticketb, w.status,
-                           w.chain);
+        hipLaunchKernelGGL((k_bwd_local<M, RS::G, RS::R>), dim3((unsigned)w.gb.ngroups), dim3(64), 0, st, w.S,
+                           w.gb, g, a, w.phiT, w.qbuf, w.aggb, w.chain);
+        tm.end();
+        tm.begin("bwd_carry");
+        hipLaunchKernelGGL((k_bwd_chain<M>), dim3((unsigned)w.S.n), dim3(64), 0, st, w.S, w.gb, w.phiT, w.qbuf,
+                           w.aggb, w.inclb, w.yend, gzi, w.chain);
+        if (!w.chain)
+            hipLaunchKernelGGL((k_bwd_expand<M, RS::CPW>), dim3((unsigned)w.gb.ngroups), dim3(64), 0, st, w.S, w.gb,
+                               w.phiT, w.qbuf, w.inclb, w.yend, gzi);
         tm.end();
         if (ge || ga) {
             const unsigned grid = (unsigned)ceil_div(w.nch, RS::CPW);
-            const size_t dyn = (size_t)RS::CPW * (M + w.S.L) * sizeof(float);
+            const size_t dyn = emit_lds_bytes(w.S.L);
             tm.begin("bwd_emit");
             if (s_in)
                 hipLaunchKernelGGL((k_adj_emit2<M, RS::G, true>), dim3(grid), dim3(64), dyn, st, w.S, g, a, e, s_in,
@@ -478,14 +496,12 @@ int prepare(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, const
         w.phiT = (double *)(ws + lay.phi);
     }
     w.yend = (double *)(ws + lay.yend);
+    w.zbuf = w.yend;  // the forward's chunk offsets share the adjoint's yend region
+    w.qbuf = (double *)(ws + lay.q);
     w.aggf = (double *)(ws + lay.aggf);
     w.inclf = (double *)(ws + lay.inclf);
-    w.flagf = (int *)(ws + lay.flagf);
     w.aggb = (double *)(ws + lay.aggb);
     w.inclb = (double *)(ws + lay.inclb);
-    w.flagb = (int *)(ws + lay.flagb);
-    w.ticketf = (unsigned *)(ws + lay.tickets);
-    w.ticketb = w.ticketf + 2;
     w.status = (int *)(ws + lay.status);
     w.chain = (p->flags & LP_FLAG_CHAINED_CARRY) ? 1 : 0;
     return LP_OK;
@@ -593,7 +609,9 @@ int lp_plan_set_chunk(lp_plan *p, int L) {
     if (int r = check_plan(p)) return r;
     if (L < p->M || L % p->M != 0) return fail(LP_EINVAL, "chunk length %d must be a positive multiple of M = %d", L, p->M);
     // the adjoint emit kernel keeps each of its chunks' s in LDS
-    if (L > kMaxChunk) return fail(LP_EINVAL, "chunk length %d exceeds the maximum %d", L, kMaxChunk);
+    int maxL = 0;
+    dispatch(p->M, [&](auto ops) { maxL = decltype(ops)::max_chunk(); });
+    if (L > maxL) return fail(LP_EINVAL, "chunk length %d exceeds the maximum %d for M = %d", L, maxL, p->M);
     p->L = L;
     return LP_OK;
 }
@@ -647,7 +665,6 @@ int lp_plan_status(lp_plan *p) {
     if (v != 0) {
         const int zero = 0;
         (void)hipMemcpy((char *)p->ws + kStatusOffset, &zero, sizeof(int), hipMemcpyHostToDevice);
-        if (v & 1) return fail(LP_EDEVICE, "a scan wave timed out waiting for a neighbour group (status %d)", v);
         return fail(LP_EINVAL, "segments held more samples than total_bound (status %d)", v);
     }
     return LP_OK;
@@ -700,10 +717,12 @@ int lp_plan_autotune(lp_plan *p, int64_t B, int64_t T, int reps, int *chosen, do
     // the timed batch keeps T and at most ~32 M samples (beyond that every candidate fills the chip)
     const int64_t Bt = std::max<int64_t>(1, std::min<int64_t>(B, (int64_t(1) << 25) / T));
     DeviceGuard dg(p->device);
+    int maxL = 0;
+    dispatch(M, [&](auto ops) { maxL = decltype(ops)::max_chunk(); });
     std::vector<int> cands;
     for (int target : {64, 96, 128, 176, 256, 352, 512, 768, 1024}) {
         const int L = std::max(1, (target + M / 2) / M) * M;
-        if (L <= kMaxChunk && std::find(cands.begin(), cands.end(), L) == cands.end()) cands.push_back(L);
+        if (L <= maxL && std::find(cands.begin(), cands.end(), L) == cands.end()) cands.push_back(L);
     }
     const int oldL = p->L;
     size_t saved_bytes = 0;  // the smallest chunk length needs the most saved state

@@ -1,0 +1,252 @@
+// Carries across chunks (gfx950).
+//
+// Forward.  k_fwd_chain (one wave per sequence) runs the sequence's group maps
+// in order, x(g+1) = P_g x(g) + r_g from x(0) = zi, giving every group's entry
+// state; k_fwd_expand (one wave per group) then applies the group's chunk
+// transitions, x(c+1) = Phi_c x(c) + z_c, and writes every chunk's entry state
+// x_c (the state the reruns start from).
+//
+// Adjoint.  The mirror image, right to left: k_bwd_chain runs the reverse
+// group maps y(g) = Psi_g y(g+1) + w_g from y = 0 at the sequence end;
+// k_bwd_expand applies y(c) = Phi_c^T y(c+1) + q_c inside each group, writing
+// the pending vector entering every chunk from the right, yend[c] = y(c+1),
+// and dL/dzi = y(0).
+//
+// Chained mode: the chain kernels apply every chunk's transition in turn (no
+// group maps, hence no matrix products) and write the per-chunk vectors
+// themselves; no expansion follows.
+//
+// Matrices are staged through LDS in batches with all loads of a batch in
+// flight together, so a serial chain pays about one memory latency per batch;
+// the carried vector lives in LDS and every matrix row is one lane's dot
+// product.
+#pragma once
+
+#include "tvlp_scan.hpp"
+
+namespace tvlp {
+
+// Orders this wave's memory operations for the compiler (a wavefront-scope
+// fence, so values other lanes wrote to LDS are read again, not reused) and
+// keeps the scheduler from moving instructions across.  LDS operations of one
+// wave are executed in order, so no hardware wait is needed between lanes.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Copies n doubles from global to LDS with the 64 lanes of one wave.  Sixteen
+// loads per lane are issued before their LDS writes, so a batch pays about
+// one memory latency per sixteen rounds instead of one per element.
+__device__ __forceinline__ void stage_doubles(double *dst, const double *__restrict__ src, int64_t n, int lane) {
+    constexpr int U = 16;
+    for (int64_t q0 = lane; q0 < n; q0 += (int64_t)U * 64) {
+        double r[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t q = q0 + (int64_t)u * 64;
+            r[u] = q < n ? src[q] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t q = q0 + (int64_t)u * 64;
+            if (q < n) dst[q] = r[u];
+        }
+    }
+    wave_sync();
+}
+
+// v <- A v + z for the M-vector v in LDS; A[i][j] = A_[i * si + j * sj] in LDS,
+// z held by lane i.  One wave; lane i < M computes row i; every lane's reads
+// of v precede the write of the new v.
+template <int M>
+__device__ __forceinline__ void lds_step(const double *A_, int si, int sj, double *v, double z, int lane) {
+    const int i = lane < M ? lane : 0;
+    double acc0 = z, acc1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const double aij = A_[i * si + j * sj];
+        if (j & 1)
+            acc1 = fma(aij, v[j], acc1);
+        else
+            acc0 = fma(aij, v[j], acc0);
+    }
+    wave_sync();
+    if (lane < M) v[lane] = acc0 + acc1;
+    wave_sync();
+}
+
+template <int M>
+struct CarryShape {
+    static constexpr int MM = M * M;
+    static constexpr int CHAIN_DOUBLES = 8192;  // 64 KiB staging for the chain kernels
+    // matrices (each with its offset vector) per chain-kernel batch
+    static constexpr int NB = CHAIN_DOUBLES / (MM + M) > 0 ? CHAIN_DOUBLES / (MM + M) : 1;
+};
+
+// ---------------------------------------------------------------- forward
+
+template <int M>
+__global__ __launch_bounds__(64) void k_fwd_chain(Seqs S, Groups GR, const double *__restrict__ zi,
+                                                  const double *__restrict__ phiT,
+                                                  const double *__restrict__ zbuf,
+                                                  const double *__restrict__ aggbuf, double *__restrict__ ginc,
+                                                  double *__restrict__ xs, int chain) {
+    using CS = CarryShape<M>;
+    constexpr int MM = M * M;
+    __shared__ double lds[CS::CHAIN_DOUBLES + M];
+    double *v = lds + CS::CHAIN_DOUBLES;
+    const int64_t b = blockIdx.x;
+    const SeqView sv = seq_view(S, b);
+    if (sv.C <= 0) return;
+    const int lane = threadIdx.x;
+    if (lane < M) v[lane] = zi ? zi[b * M + lane] : 0.0;
+    wave_sync();
+    // chained: items are chunks (matrix Phi_c, offset z_c; output xs per chunk);
+    // grouped: items are groups (aggregate with its offset; output ginc per group)
+    const int64_t n = chain ? sv.C : groups_of(sv.C, GR.cpw);
+    const int64_t id0 = chain ? sv.cbase : group_id(S, GR, b, 0);
+    double *out = chain ? xs : ginc;
+    for (int64_t k0 = 0; k0 < n; k0 += CS::NB) {
+        const int nb = (int)min((int64_t)CS::NB, n - k0);
+        const int nt = (int)min((int64_t)nb, n - 1 - k0);  // items with a map (not the last)
+        if (chain) {
+            stage_doubles(lds, phiT + (id0 + k0) * MM, (int64_t)nt * MM, lane);
+            stage_doubles(lds + CS::NB * MM, zbuf + (id0 + k0) * M, (int64_t)nt * M, lane);
+        } else {
+            stage_doubles(lds, aggbuf + (id0 + k0) * (MM + M), (int64_t)nt * (MM + M), lane);
+        }
+        for (int k = 0; k < nb; ++k) {
+            if (lane < M) out[(id0 + k0 + k) * M + lane] = v[lane];
+            if (k < nt) {
+                const double *A = chain ? lds + k * MM : lds + k * (MM + M);
+                const double *z = chain ? lds + CS::NB * MM + k * M : A + MM;
+                lds_step<M>(A, 1, M, v, lane < M ? z[lane] : 0.0, lane);
+            }
+        }
+    }
+}
+
+template <int M, int CPW>
+__global__ __launch_bounds__(64) void k_fwd_expand(Seqs S, Groups GR, const double *__restrict__ phiT,
+                                                   const double *__restrict__ zbuf,
+                                                   const double *__restrict__ ginc, double *__restrict__ xs) {
+    constexpr int MM = M * M;
+    __shared__ double lds[CPW * (MM + M) + M];
+    double *v = lds + CPW * (MM + M);
+    const int64_t gid = blockIdx.x;
+    if (gid >= GR.ngroups) return;
+    int64_t b, g;
+    group_at(S, GR, gid, b, g);
+    const SeqView sv = seq_view(S, b);
+    if (g >= groups_of(sv.C, CPW)) return;
+    const int lane = threadIdx.x;
+    const int64_t c0 = g * CPW;
+    const int nk = (int)min((int64_t)CPW, sv.C - c0);
+    const int nt = nk - 1;  // transitions needed inside the group
+    stage_doubles(lds, phiT + (sv.cbase + c0) * MM, (int64_t)nt * MM, lane);
+    stage_doubles(lds + CPW * MM, zbuf + (sv.cbase + c0) * M, (int64_t)nt * M, lane);
+    if (lane < M) v[lane] = ginc[gid * M + lane];
+    wave_sync();
+    for (int k = 0; k < nk; ++k) {
+        if (lane < M) xs[(sv.cbase + c0 + k) * M + lane] = v[lane];
+        if (k < nt) lds_step<M>(lds + k * MM, 1, M, v, lane < M ? lds[CPW * MM + k * M + lane] : 0.0, lane);
+    }
+}
+
+// ---------------------------------------------------------------- adjoint
+
+template <int M>
+__global__ __launch_bounds__(64) void k_bwd_chain(Seqs S, Groups GR, const double *__restrict__ phiT,
+                                                  const double *__restrict__ qbuf,
+                                                  const double *__restrict__ aggbuf, double *__restrict__ ginc,
+                                                  double *__restrict__ yend, double *__restrict__ grad_zi,
+                                                  int chain) {
+    using CS = CarryShape<M>;
+    constexpr int MM = M * M;
+    __shared__ double lds[CS::CHAIN_DOUBLES + M];
+    double *v = lds + CS::CHAIN_DOUBLES;
+    const int64_t b = blockIdx.x;
+    const SeqView sv = seq_view(S, b);
+    const int lane = threadIdx.x;
+    if (sv.C <= 0) {  // no samples: no dependence on the initial state
+        if (grad_zi && lane < M) grad_zi[b * M + lane] = 0.0;
+        return;
+    }
+    if (lane < M) v[lane] = 0.0;
+    wave_sync();
+    // chained: items are chunks (Phi_c^T, q_c; output yend per chunk, the last
+    // chunk has no transition); grouped: items are groups (reverse map with its
+    // offset; output ginc per group, group 0 has no map)
+    const int64_t n = chain ? sv.C : groups_of(sv.C, GR.cpw);
+    const int64_t id0 = chain ? sv.cbase : group_id(S, GR, b, 0);
+    double *out = chain ? yend : ginc;
+    for (int64_t k1 = n; k1 > 0; k1 -= CS::NB) {
+        const int nb = (int)min((int64_t)CS::NB, k1);
+        const int64_t k0 = k1 - nb;  // items [k0, k1) staged, applied from the end
+        if (chain) {
+            stage_doubles(lds, phiT + (id0 + k0) * MM, (int64_t)nb * MM, lane);
+            stage_doubles(lds + CS::NB * MM, qbuf + (id0 + k0) * M, (int64_t)nb * M, lane);
+        } else {
+            stage_doubles(lds, aggbuf + (id0 + k0) * (MM + M), (int64_t)nb * (MM + M), lane);
+        }
+        for (int k = nb - 1; k >= 0; --k) {
+            const int64_t item = k0 + k;
+            if (lane < M) out[(id0 + item) * M + lane] = v[lane];
+            if (chain) {
+                const double q = lane < M ? lds[CS::NB * MM + k * M + lane] : 0.0;
+                if (item == n - 1) {
+                    wave_sync();
+                    if (lane < M) v[lane] = q;  // the last chunk: y = q
+                    wave_sync();
+                } else {
+                    lds_step<M>(lds + k * MM, M, 1, v, q, lane);
+                }
+            } else if (item > 0) {
+                const double *A = lds + k * (MM + M);
+                lds_step<M>(A, M, 1, v, lane < M ? A[MM + lane] : 0.0, lane);
+            }
+        }
+    }
+    if (chain && grad_zi && lane < M) grad_zi[b * M + lane] = v[lane];
+}
+
+template <int M, int CPW>
+__global__ __launch_bounds__(64) void k_bwd_expand(Seqs S, Groups GR, const double *__restrict__ phiT,
+                                                   const double *__restrict__ qbuf,
+                                                   const double *__restrict__ ginc, double *__restrict__ yend,
+                                                   double *__restrict__ grad_zi) {
+    constexpr int MM = M * M;
+    __shared__ double lds[CPW * (MM + M) + M];
+    double *v = lds + CPW * (MM + M);
+    const int64_t gid = blockIdx.x;
+    if (gid >= GR.ngroups) return;
+    int64_t b, g;
+    group_at(S, GR, gid, b, g);
+    const SeqView sv = seq_view(S, b);
+    if (g >= groups_of(sv.C, CPW)) return;
+    const int lane = threadIdx.x;
+    const int64_t c0 = g * CPW;
+    const int nk = (int)min((int64_t)CPW, sv.C - c0);
+    const bool need_first = (g == 0) && grad_zi;  // y(0) is dL/dzi
+    stage_doubles(lds, phiT + (sv.cbase + c0) * MM, (int64_t)nk * MM, lane);
+    stage_doubles(lds + CPW * MM, qbuf + (sv.cbase + c0) * M, (int64_t)nk * M, lane);
+    if (lane < M) v[lane] = ginc[gid * M + lane];
+    wave_sync();
+    for (int k = nk - 1; k >= 0; --k) {
+        const int64_t c = c0 + k;
+        if (lane < M) yend[(sv.cbase + c) * M + lane] = v[lane];
+        if (k == 0 && !need_first) break;  // y at the group start is not needed
+        const double q = lane < M ? lds[CPW * MM + k * M + lane] : 0.0;
+        if (c == sv.C - 1) {  // the sequence's last chunk: y = q
+            wave_sync();
+            if (lane < M) v[lane] = q;
+            wave_sync();
+        } else {
+            lds_step<M>(lds + k * MM, M, 1, v, q, lane);
+        }
+    }
+    if (need_first && lane < M) grad_zi[b * M + lane] = v[lane];
+}
+
+}  // namespace tvlp

@@ -188,8 +188,13 @@ __global__ __launch_bounds__(64) void k_fwd_rerun2(Seqs S, const float *__restri
 
 // Adjoint rerun of each chunk (push form of Eq. 12, descending), from the
 // carried pending vector yend[gc] (p(len-1-j) = yend[j]); writes ghat and
-// -ghat(t) s(t-i).  s of the chunk comes from `s_in` (stored) or is recomputed
-// from the saved entry state xs into LDS by an ascending pass first.
+// -ghat(t) s(t-i) (Eq. 13).  s of the chunk comes from `s_in` (stored) or is
+// recomputed from the saved entry state xs into LDS by an ascending pass
+// first.  The descending pass only leaves ghat in LDS; both gradients are then
+// written by all lanes of the wave with coalesced stores.
+//
+// Dynamic LDS: [CPW][M + L] floats of s (ssh[M + t] = s(t), ssh[M-1-k] =
+// s(-1-k)) followed by [CPW][L] floats of ghat.
 template <int M, int G, bool STORED_S>
 __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restrict__ g,
                                                   const float *__restrict__ a, const float *__restrict__ e,
@@ -204,7 +209,7 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
     using RD = RowRing<M, CPW, true>;
     static_assert(RA::FLOATS == RD::FLOATS, "ring sizes");
     __shared__ __attribute__((aligned(16))) float ring[RA::FLOATS];
-    extern __shared__ float ssh_dyn[];  // [CPW][M + L]: ssh[M + t] = s(t), ssh[M-1-k] = s(-1-k)
+    extern __shared__ float ssh_dyn[];
 
     const int lane = threadIdx.x;
     const int slot = lane / G, r = lane % G;
@@ -224,6 +229,8 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
         }
     }
     float *ssh = ssh_dyn + slot * (M + L);
+    float *gsh_all = ssh_dyn + CPW * (M + L);
+    float *gsh = gsh_all + slot * L;
     for (int k = r; k < M; k += G) ssh[M - 1 - k] = active ? (float)xs[gc * M + k] : 0.f;
     if constexpr (STORED_S) {
         for (int t = r; t < L; t += G) ssh[M + t] = (active && t < len) ? s_in[base + t] : 0.f;
@@ -279,64 +286,54 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
     }
     RD rd;
     rd.init(a, g, lane, base, len, G, goff);
-    // s(t - tap - 1) of the lane's taps at step u (t = len - 1 - u), from LDS
-    auto load_s = [&](int u, float (&sv)[TPL]) {
-        const int t = (int)len - 1 - u;
-#pragma unroll
-        for (int m = 0; m < TPL; ++m) {
-            const int si = M + t - (r * TPL + m + 1);
-            sv[m] = ssh[si >= 0 ? si : 0];
-        }
-    };
     for (int u = 0; u < RD::D; ++u) rd.issue(ring, u);
     RD::wait_next();  // row 0 (sample len - 1)
     double av[TPL], gx;
-    float sv[TPL];
     RD::load(ring, 0, slot, r, av, gx);
-    load_s(0, sv);
     for (int u = 0; u < L; ++u) {
         __builtin_amdgcn_sched_barrier(0);
         rd.issue(ring, u + RD::D);
         RD::wait_next();
         double nav[TPL], ngx;
-        float nsv[TPL];
         RD::load(ring, u + 1, slot, r, nav, ngx);
-        load_s(u + 1, nsv);
-        const int64_t t = len - 1 - u;
+        const int t = (int)len - 1 - u;
         const double gh = gx + P0;
         double np[TPL];
-        float gav[TPL];
 #pragma unroll
-        for (int m = 0; m < TPL; ++m) {
-            np[m] = fma(-av[m], gh, P[m]);
-            gav[m] = (float)(-gh * (double)sv[m]);
-        }
+        for (int m = 0; m < TPL; ++m) np[m] = fma(-av[m], gh, P[m]);
         // cross-lane moves by every lane, then the step is committed where valid
         const double down = dpp_f64<DPP_ROW_SHL1>(np[0]);
         const double b0 = group_bcast0<G>(np[0], r);
         const bool live = u < len;
-        if (live) {
-            if (ga) {
-#pragma unroll
-                for (int m = 0; m < TPL; ++m) {
-                    const int tap = r * TPL + m;
-                    if (tap < M) ga[(base + t) * M + tap] = gav[m];
-                }
-            }
-            if (ge && r == 0) ge[base + t] = (float)gh;
-        }
+        if (live && r == 0) gsh[t] = (float)gh;
         P0 = live ? b0 : P0;
 #pragma unroll
         for (int m = 0; m + 1 < TPL; ++m) P[m] = live ? np[m + 1] : P[m];
         P[TPL - 1] = live ? ((r == G - 1) ? 0.0 : down) : P[TPL - 1];
 #pragma unroll
-        for (int m = 0; m < TPL; ++m) {
-            av[m] = nav[m];
-            sv[m] = nsv[m];
-        }
+        for (int m = 0; m < TPL; ++m) av[m] = nav[m];
         gx = ngx;
     }
     RD::drain();
+    __syncthreads();
+
+    // ---- dL/de(t) = ghat(t), dL/da_i(t) = -ghat(t) s(t-i), chunk by chunk with all lanes
+    for (int k = 0; k < CPW; ++k) {
+        const int kl = (int)__shfl(len, k * G, 64);
+        const int64_t kb = __shfl(base, k * G, 64);
+        const float *sk = ssh_dyn + k * (M + L);
+        const float *gk = gsh_all + k * L;
+        if (ge)
+            for (int t = lane; t < kl; t += 64) ge[kb + t] = gk[t];
+        if (ga) {
+            float *gak = ga + kb * M;
+            const int n = kl * M;
+            for (int f = lane; f < n; f += 64) {
+                const int t = f / M, i = f - t * M;
+                gak[f] = -gk[t] * sk[M + t - 1 - i];
+            }
+        }
+    }
 }
 
 }  // namespace tvlp

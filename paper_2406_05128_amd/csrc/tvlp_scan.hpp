@@ -1,34 +1,23 @@
-// Single-pass chunk scans with decoupled look-back (gfx950, one wave per group).
+// Local (wait-free) passes of the chunked scans (gfx950, one wave per group).
 //
-// Forward (k_fwd_scan).  A wave owns a group of CPW consecutive chunks of one
+// Forward (k_fwd_local).  A wave owns a group of CPW consecutive chunks of one
 // sequence.  It computes each chunk's transition (Phi_c, z_c) with the basis
 // pass (LPC lanes per chunk, CPL float64 columns per lane, coefficient rows
-// staged through LDS), stores Phi_c (column-major, for the adjoint), composes
-// the group's affine map (Phi_G, z_G) in LDS and publishes it.  It then obtains
-// the group's entry state by looking back over the preceding groups of its
-// sequence — taking the first published inclusive state and applying the
-// aggregates after it — publishes its own inclusive state, and writes every
-// chunk's entry state x_c.
+// staged through LDS), stores Phi_c (column-major) and z_c, and composes the
+// group's affine map x(c0 + CPW) = P_G x(c0) + r_G in LDS.
 //
-// Adjoint (k_bwd_scan).  The mirror image, right to left: per chunk the
-// zero-terminal adjoint response q_c (systolic push form of Eq. 12), the
-// group's reverse map y_start = Psi_G y_end + w_G with Psi_G the product of the
-// Phi_c^T, look-back over the following groups, and every chunk's terminal
-// pending vector yend[c] = y_{c+1} (plus dL/dzi = y_0).
+// Adjoint (k_bwd_local).  The mirror image: per chunk the zero-terminal
+// adjoint response q_c (systolic push form of Eq. 12), stored, and the group's
+// reverse map y(c0) = Psi_G y(c0 + nk) + w_G with Psi_G the product of the
+// Phi_c^T.
 //
-// Ordering and progress: the wave's group comes from an atomic ticket taken
-// when the wave starts, in an order where every group a wave may wait on has a
-// smaller ticket, so it has already started and never waits on a later one.
-// Publication is release (agent scope) after the data, consumption acquire.
-// Waits are bounded: on timeout the wave raises status[0] and continues.
+// No wave waits on another; the carries across groups and the per-chunk
+// states are computed afterwards by the carry kernels (tvlp_carry.hpp).
 #pragma once
 
 #include "tvlp_rerun.hpp"
 
 namespace tvlp {
-
-enum : int { FLAG_EMPTY = 0, FLAG_AGG = 1, FLAG_INCL = 2 };
-constexpr unsigned SPIN_LIMIT = 1u << 22;
 
 // Groups of CPW chunks per sequence (uniform batches or varlen prefix gbase).
 struct Groups {
@@ -59,30 +48,6 @@ __device__ __forceinline__ void group_at(const Seqs &S, const Groups &G, int64_t
 __device__ __forceinline__ int64_t group_id(const Seqs &S, const Groups &G, int64_t b, int64_t g) {
     if (!G.gbase) return b * groups_of(nchunks_of(S.T, S.L), G.cpw) + g;
     return G.gbase[b] + g;
-}
-
-__device__ __forceinline__ void publish_flag(int *flags, int64_t gid, int v, int lane) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    if (lane == 0) __hip_atomic_store(flags + gid, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Wait until flags[gid] != 0; returns the flag (wave-uniform).
-__device__ __forceinline__ int wait_flag(const int *flags, int64_t gid, int lane, int *status) {
-    int f = 0;
-    for (unsigned it = 0;; ++it) {
-        int v = 0;
-        if (lane == 0) v = __hip_atomic_load(flags + gid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        f = __builtin_amdgcn_readfirstlane(v);
-        if (f != FLAG_EMPTY) break;
-        if (it >= SPIN_LIMIT) {
-            if (lane == 0) atomicOr(status, 1);
-            f = FLAG_INCL;  // give up: treat as available (result is flagged invalid)
-            break;
-        }
-        __builtin_amdgcn_s_sleep(2);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    return f;
 }
 
 // ---------------------------------------------------------------- small dense helpers in LDS
@@ -184,12 +149,9 @@ struct FwdScanShape {
 constexpr int waitcnt_vm(int n) { return (n & 0xF) | (0x7 << 4) | (0xF << 8) | (((n >> 4) & 0x3) << 14); }
 
 template <int M, int LPC, int CPL, int R>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_fwd_scan(Seqs S, Groups GR, const float *__restrict__ e,
-                                                 const float *__restrict__ a, const double *__restrict__ zi,
-                                                 double *__restrict__ phiT, double *__restrict__ xs,
-                                                 double *__restrict__ aggbuf, double *__restrict__ inclbuf,
-                                                 int *__restrict__ flags, unsigned *__restrict__ ticket,
-                                                 int *__restrict__ status, int chain) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_fwd_local(
+    Seqs S, Groups GR, const float *__restrict__ e, const float *__restrict__ a, double *__restrict__ phiT,
+    double *__restrict__ zbuf, double *__restrict__ aggbuf, int chain) {
     using SH = FwdScanShape<M, LPC, CPL, R>;
     constexpr int CPW = SH::CPW;
     constexpr int MM = M * M;
@@ -200,13 +162,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     double *QT = FT + MM;                              // product scratch
     double *vr = QT + MM;                              // aggregate offset
     double *vz = vr + M;                               // chunk offset
-    double *vx = vz + M;                               // state vector
-    double *vt = vx + M;                               // scratch vector
 
     const int lane = threadIdx.x;
-    unsigned tk = 0;
-    if (lane == 0) tk = atomicAdd(ticket, 1u);
-    const int64_t gid = (int64_t)__builtin_amdgcn_readfirstlane(tk);
+    const int64_t gid = blockIdx.x;
     if (gid >= GR.ngroups) return;
     int64_t b, g;
     group_at(S, GR, gid, b, g);
@@ -214,7 +172,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     if (g >= groups_of(v.C, CPW)) return;  // slot beyond the real group count
     const int L = S.L;
     const int64_t c0 = g * CPW;
-    const int nk = (int)min((int64_t)CPW, v.C - c0);  // chunks in this group
     const int nbasis = (int)min((int64_t)CPW, v.C - 1 - c0);  // chunks carrying a transition
 
     // ---- basis pass
@@ -301,7 +258,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
             });
         }
         __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));  // drain the look-ahead before the ring is reused
-        // Phi_c column-major to global (column j-1 = response to unit state s(cL-j))
+        // Phi_c column-major to global (column j-1 = response to unit state s(cL-j)),
+        // z_c (zero-state response, column 0) alongside
         if (act) {
 #pragma unroll
             for (int m = 0; m < CPL; ++m) {
@@ -309,6 +267,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
                 if (col >= 1 && col <= M) {
 #pragma unroll
                     for (int k = 0; k < M; ++k) phiT[(((v.cbase + c) * M) + (col - 1)) * M + k] = h[m][M - 1 - k];
+                } else if (col == 0) {
+#pragma unroll
+                    for (int k = 0; k < M; ++k) zbuf[(v.cbase + c) * M + k] = h[m][M - 1 - k];
                 }
             }
         }
@@ -352,69 +313,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
             if (lane < M) vr[lane] = rn;
             __syncthreads();
         }
-        // publish the aggregate (column-major matrix, then offset)
+        // the group's map x(c0 + CPW) = P x(c0) + r (column-major matrix, then offset)
         double *ag = aggbuf + gid * (MM + M);
         for (int q = lane; q < MM; q += 64) ag[q] = PT[q];
         if (lane < M) ag[MM + lane] = vr[lane];
-        publish_flag(flags, gid, FLAG_AGG, lane);
-    }
-
-    // ---- look-back: entry state of this group
-    double x = 0.0;
-    if (g == 0) {
-        x = (zi && lane < M) ? zi[b * M + lane] : 0.0;
-    } else {
-        int64_t j = g - 1;
-        int64_t stop = -1;  // index of the group whose inclusive state starts the fold (-1: sequence start)
-        for (;;) {
-            const int64_t jg = group_id(S, GR, b, j);
-            const int f = wait_flag(flags, jg, lane, status);
-            if (f == FLAG_INCL) { stop = j; break; }
-            if (j == 0) { stop = -1; break; }
-            --j;
-        }
-        int64_t first;
-        if (stop >= 0) {
-            x = lane < M ? inclbuf[group_id(S, GR, b, stop) * M + lane] : 0.0;
-            first = stop + 1;
-        } else {
-            x = (zi && lane < M) ? zi[b * M + lane] : 0.0;
-            first = 0;
-        }
-        for (int64_t jj = first; jj < g; ++jj) {
-            const double *ag = aggbuf + group_id(S, GR, b, jj) * (MM + M);
-            if (lane < M) vt[lane] = x;
-            __syncthreads();
-            if (lane < M) x = matvec_cm<M>(ag, vt, ag[MM + lane], lane);
-            __syncthreads();
-        }
-    }
-    // ---- inclusive state for the successors
-    if (!last_group && !chain) {
-        if (lane < M) vx[lane] = x;
-        __syncthreads();
-        double xn = 0.0;
-        if (lane < M) xn = matvec_cm<M>(PT, vx, vr[lane], lane);
-        if (lane < M) inclbuf[gid * M + lane] = xn;
-        publish_flag(flags, gid, FLAG_INCL, lane);
-        __syncthreads();
-    }
-    // ---- chunk entry states
-    for (int k = 0; k < nk; ++k) {
-        if (lane < M) xs[(v.cbase + c0 + k) * M + lane] = x;
-        if (k < nbasis) {
-            stage_chunk(k);
-            if (lane < M) vx[lane] = x;
-            __syncthreads();
-            if (lane < M) x = matvec_cm<M>(FT, vx, vz[lane], lane);
-            __syncthreads();
-        }
-    }
-    // chained mode: x now enters the next group (a non-last group has CPW
-    // transition-carrying chunks)
-    if (chain && !last_group) {
-        if (lane < M) inclbuf[gid * M + lane] = x;
-        publish_flag(flags, gid, FLAG_INCL, lane);
     }
 }
 
@@ -430,12 +332,10 @@ struct BwdScanShape {
 };
 
 template <int M, int G, int R>
-__global__ __launch_bounds__(64) void k_bwd_scan(Seqs S, Groups GR, const float *__restrict__ g_in,
-                                                 const float *__restrict__ a, const double *__restrict__ phiT,
-                                                 double *__restrict__ yend, double *__restrict__ grad_zi,
-                                                 double *__restrict__ aggbuf, double *__restrict__ inclbuf,
-                                                 int *__restrict__ flags, unsigned *__restrict__ ticket,
-                                                 int *__restrict__ status, int chain) {
+__global__ __launch_bounds__(64) void k_bwd_local(Seqs S, Groups GR, const float *__restrict__ g_in,
+                                                  const float *__restrict__ a, const double *__restrict__ phiT,
+                                                  double *__restrict__ qbuf, double *__restrict__ aggbuf,
+                                                  int chain) {
     using SH = BwdScanShape<M, G, R>;
     using RD = typename SH::RD;
     constexpr int CPW = SH::CPW;
@@ -453,11 +353,9 @@ __global__ __launch_bounds__(64) void k_bwd_scan(Seqs S, Groups GR, const float 
     (void)vt;
 
     const int lane = threadIdx.x;
-    unsigned tk = 0;
-    if (lane == 0) tk = atomicAdd(ticket, 1u);
-    const int64_t tid_ = (int64_t)__builtin_amdgcn_readfirstlane(tk);
+    const int64_t tid_ = blockIdx.x;
     if (tid_ >= GR.ngroups) return;
-    // reverse order inside each sequence: the last group gets the first ticket
+    // reverse order inside each sequence (the last group has the lowest index)
     int64_t b, gr;
     group_at(S, GR, tid_, b, gr);
     const SeqView v = seq_view(S, b);
@@ -511,12 +409,15 @@ __global__ __launch_bounds__(64) void k_bwd_scan(Seqs S, Groups GR, const float 
         RD::drain();
     }
     __syncthreads();
-    // q_c[i-1] = p(-i): lane slot (tap i) -> LDS
+    // q_c[i-1] = p(-i): lane slot (tap i) -> LDS and global
     if (act) {
 #pragma unroll
         for (int m = 0; m < TPL; ++m) {
             const int i = r * TPL + m + 1;
-            if (i <= M) vq[slot * M + (i - 1)] = P[m];
+            if (i <= M) {
+                vq[slot * M + (i - 1)] = P[m];
+                qbuf[(v.cbase + c) * M + (i - 1)] = P[m];
+            }
         }
     }
     __syncthreads();
@@ -542,7 +443,6 @@ __global__ __launch_bounds__(64) void k_bwd_scan(Seqs S, Groups GR, const float 
         __syncthreads();
     };
 
-    const bool seq_last_group = (c0 + CPW >= v.C);
     // ---- reverse map of the group: y(c0) = Psi y(c0+nk) + w (not in chained mode)
     if (g > 0 && !chain) {
         // start from the group's last chunk
@@ -569,80 +469,11 @@ __global__ __launch_bounds__(64) void k_bwd_scan(Seqs S, Groups GR, const float 
             if (lane < M) vw[lane] = wn;
             __syncthreads();
         }
+        // the group's reverse map y(c0) = Psi y(c0 + nk) + w (row-major matrix, then offset)
         double *ag = aggbuf + gid * (MM + M);
         for (int q = lane; q < MM; q += 64) ag[q] = PS[q];
         if (lane < M) ag[MM + lane] = vw[lane];
-        publish_flag(flags, gid, FLAG_AGG, lane);
     }
-
-    // ---- look-back over the following groups: y entering this group from the right
-    double y = 0.0;
-    if (!seq_last_group) {
-        int64_t j = g + 1;
-        int64_t stop = ng;  // ng: sequence end (y = 0)
-        for (;;) {
-            const int f = wait_flag(flags, group_id(S, GR, b, j), lane, status);
-            if (f == FLAG_INCL) { stop = j; break; }
-            if (j == ng - 1) { stop = ng; break; }
-            ++j;
-        }
-        int64_t first;
-        if (stop < ng) {
-            y = lane < M ? inclbuf[group_id(S, GR, b, stop) * M + lane] : 0.0;
-            first = stop - 1;
-        } else {
-            y = 0.0;
-            first = ng - 1;
-        }
-        for (int64_t jj = first; jj > g; --jj) {
-            const double *ag = aggbuf + group_id(S, GR, b, jj) * (MM + M);
-            if (lane < M) vy[lane] = y;
-            __syncthreads();
-            if (lane < M) y = matvec_rm<M>(ag, vy, ag[MM + lane], lane);
-            __syncthreads();
-        }
-    }
-    if (g > 0 && !chain) {
-        if (lane < M) vy[lane] = y;
-        __syncthreads();
-        double yn = 0.0;
-        if (lane < M) yn = matvec_rm<M>(PS, vy, vw[lane], lane);
-        if (lane < M) inclbuf[gid * M + lane] = yn;
-        publish_flag(flags, gid, FLAG_INCL, lane);
-        __syncthreads();
-    }
-    // ---- per-chunk terminal pending vectors, right to left
-    if (c0 + nk - 1 < v.C - 1) fetch_phi(nk - 1);
-    for (int k = nk - 1; k >= 0; --k) {
-        const int64_t cc = c0 + k;
-        if (lane < M) yend[(v.cbase + cc) * M + lane] = y;
-        if (cc == 0 && !grad_zi) break;
-        const bool has_phi = cc < v.C - 1;
-        if (has_phi) commit_phi();
-        if (k > 0) fetch_phi(k - 1);  // chunk k-1 < C-1 always carries a transition
-        if (lane < M) vy[lane] = y;
-        __syncthreads();
-        if (lane < M) y = (has_phi ? matvec_rm<M>(FT, vy, 0.0, lane) : 0.0) + vq[k * M + lane];
-        __syncthreads();
-    }
-    // chained mode: y is now the pending vector at the group's first sample
-    if (chain && g > 0) {
-        if (lane < M) inclbuf[gid * M + lane] = y;
-        publish_flag(flags, gid, FLAG_INCL, lane);
-    }
-    if (g == 0 && grad_zi && lane < M) grad_zi[b * M + lane] = y;
-}
-
-// Reset tickets and flags before a scan (a kernel, so it can be captured in graphs).
-__global__ void k_scan_reset(int *__restrict__ flags, int64_t n, unsigned *__restrict__ ticket,
-                             int *__restrict__ status) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) flags[i] = 0;
-    if (i == 0) {
-        ticket[0] = 0u;
-        ticket[1] = 0u;
-    }
-    (void)status;
 }
 
 }  // namespace tvlp

@@ -106,8 +106,8 @@ class Plan:
         _lib.check(_lib.load().lp_plan_set_timing(self._h, 1 if on else 0))
 
     def check_status(self):
-        """Synchronise; raise if a scan wave timed out waiting for a neighbour group (LP_EDEVICE) or a
-        segment table held more samples than its total_bound (LP_EINVAL).  Clears the flag."""
+        """Synchronise; raise if a segment table held more samples than its total_bound (LP_EINVAL,
+        clears the flag) or the device reports an error (LP_EDEVICE)."""
         _lib.check(_lib.load().lp_plan_status(self._h))
 
     def reset_timings(self):
