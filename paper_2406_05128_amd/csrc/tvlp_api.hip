@@ -336,11 +336,12 @@ struct Ops {
                            w.S, w.gf, e, a, w.phiT, w.zbuf, w.aggf, w.chain);
         tm.end();
         tm.begin("fwd_carry");
-        hipLaunchKernelGGL((k_fwd_chain<M>), dim3((unsigned)w.S.n), dim3(64), 0, st, w.S, w.gf, zi, w.phiT, w.zbuf,
-                           w.aggf, w.inclf, w.xs, w.chain);
+        const dim3 ct(CarryShape<M>::THREADS);
+        hipLaunchKernelGGL((k_fwd_chain<M>), dim3((unsigned)w.S.n), ct, 0, st, w.S, w.gf, zi, w.phiT, w.zbuf, w.aggf,
+                           w.inclf, w.xs, w.chain);
         if (!w.chain)
-            hipLaunchKernelGGL((k_fwd_expand<M, FS::CPW>), dim3((unsigned)w.gf.ngroups), dim3(64), 0, st, w.S, w.gf,
-                               w.phiT, w.zbuf, w.inclf, w.xs);
+            hipLaunchKernelGGL((k_fwd_expand<M, FS::CPW>), dim3((unsigned)w.gf.ngroups), ct, 0, st, w.S, w.gf, w.phiT,
+                               w.zbuf, w.inclf, w.xs);
         tm.end();
         tm.begin("fwd_emit");
         hipLaunchKernelGGL((k_fwd_rerun2<M, RS::G>), dim3((unsigned)ceil_div(w.nch, RS::CPW)), dim3(64), 0, st,
@@ -356,11 +357,12 @@ struct Ops {
                            w.gb, g, a, w.phiT, w.qbuf, w.aggb, w.chain);
         tm.end();
         tm.begin("bwd_carry");
-        hipLaunchKernelGGL((k_bwd_chain<M>), dim3((unsigned)w.S.n), dim3(64), 0, st, w.S, w.gb, w.phiT, w.qbuf,
-                           w.aggb, w.inclb, w.yend, gzi, w.chain);
+        const dim3 ct(CarryShape<M>::THREADS);
+        hipLaunchKernelGGL((k_bwd_chain<M>), dim3((unsigned)w.S.n), ct, 0, st, w.S, w.gb, w.phiT, w.qbuf, w.aggb,
+                           w.inclb, w.yend, gzi, w.chain);
         if (!w.chain)
-            hipLaunchKernelGGL((k_bwd_expand<M, RS::CPW>), dim3((unsigned)w.gb.ngroups), dim3(64), 0, st, w.S, w.gb,
-                               w.phiT, w.qbuf, w.inclb, w.yend, gzi);
+            hipLaunchKernelGGL((k_bwd_expand<M, RS::CPW>), dim3((unsigned)w.gb.ngroups), ct, 0, st, w.S, w.gb, w.phiT,
+                               w.qbuf, w.inclb, w.yend, gzi);
         tm.end();
         if (ge || ga) {
             const unsigned grid = (unsigned)ceil_div(w.nch, RS::CPW);

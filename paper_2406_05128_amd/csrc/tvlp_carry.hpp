@@ -16,10 +16,10 @@
 // group maps, hence no matrix products) and write the per-chunk vectors
 // themselves; no expansion follows.
 //
-// Matrices are staged through LDS in batches with all loads of a batch in
-// flight together, so a serial chain pays about one memory latency per batch;
-// the carried vector lives in LDS and every matrix row is one lane's dot
-// product.
+// Matrices are staged through LDS in batches by several waves with many loads
+// in flight; in the chain kernels three waves stage the next batch while the
+// first wave runs the current one.  The carried vector lives in LDS and every
+// matrix row is one lane's dot product.
 #pragma once
 
 #include "tvlp_scan.hpp"
@@ -35,25 +35,24 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// Copies n doubles from global to LDS with the 64 lanes of one wave.  Sixteen
-// loads per lane are issued before their LDS writes, so a batch pays about
-// one memory latency per sixteen rounds instead of one per element.
-__device__ __forceinline__ void stage_doubles(double *dst, const double *__restrict__ src, int64_t n, int lane) {
+// Copies n doubles from global to LDS; thread t of nt cooperating threads.
+// Sixteen loads per thread are issued before their LDS writes, so a batch pays
+// about one memory latency per sixteen rounds instead of one per element.
+__device__ __forceinline__ void stage_doubles(double *dst, const double *__restrict__ src, int64_t n, int t, int nt) {
     constexpr int U = 16;
-    for (int64_t q0 = lane; q0 < n; q0 += (int64_t)U * 64) {
+    for (int64_t q0 = t; q0 < n; q0 += (int64_t)U * nt) {
         double r[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t q = q0 + (int64_t)u * 64;
+            const int64_t q = q0 + (int64_t)u * nt;
             r[u] = q < n ? src[q] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t q = q0 + (int64_t)u * 64;
+            const int64_t q = q0 + (int64_t)u * nt;
             if (q < n) dst[q] = r[u];
         }
     }
-    wave_sync();
 }
 
 // v <- A v + z for the M-vector v in LDS; A[i][j] = A_[i * si + j * sj] in LDS,
@@ -76,61 +75,84 @@ __device__ __forceinline__ void lds_step(const double *A_, int si, int sj, doubl
     wave_sync();
 }
 
+// v <- z (lane i < M holds z_i).
+template <int M>
+__device__ __forceinline__ void lds_set(double *v, double z, int lane) {
+    wave_sync();
+    if (lane < M) v[lane] = z;
+    wave_sync();
+}
+
 template <int M>
 struct CarryShape {
     static constexpr int MM = M * M;
-    static constexpr int CHAIN_DOUBLES = 8192;  // 64 KiB staging for the chain kernels
+    static constexpr int THREADS = 256;         // chain and expand kernels: four waves
+    static constexpr int BUF_DOUBLES = 8000;    // one chain-kernel staging buffer (62.5 KiB)
     // matrices (each with its offset vector) per chain-kernel batch
-    static constexpr int NB = CHAIN_DOUBLES / (MM + M) > 0 ? CHAIN_DOUBLES / (MM + M) : 1;
+    static constexpr int NB = BUF_DOUBLES / (MM + M) > 0 ? BUF_DOUBLES / (MM + M) : 1;
 };
 
 // ---------------------------------------------------------------- forward
 
+// Chained: items are chunks (matrix Phi_c, offset z_c; output xs per chunk);
+// grouped: items are groups (map with its offset; output ginc per group).
+// The last item has no map.
 template <int M>
-__global__ __launch_bounds__(64) void k_fwd_chain(Seqs S, Groups GR, const double *__restrict__ zi,
-                                                  const double *__restrict__ phiT,
-                                                  const double *__restrict__ zbuf,
-                                                  const double *__restrict__ aggbuf, double *__restrict__ ginc,
-                                                  double *__restrict__ xs, int chain) {
+__global__ __launch_bounds__(256) void k_fwd_chain(Seqs S, Groups GR, const double *__restrict__ zi,
+                                                   const double *__restrict__ phiT,
+                                                   const double *__restrict__ zbuf,
+                                                   const double *__restrict__ aggbuf, double *__restrict__ ginc,
+                                                   double *__restrict__ xs, int chain) {
     using CS = CarryShape<M>;
     constexpr int MM = M * M;
-    __shared__ double lds[CS::CHAIN_DOUBLES + M];
-    double *v = lds + CS::CHAIN_DOUBLES;
+    __shared__ double lds[2 * CS::BUF_DOUBLES + M];
+    double *v = lds + 2 * CS::BUF_DOUBLES;
     const int64_t b = blockIdx.x;
     const SeqView sv = seq_view(S, b);
     if (sv.C <= 0) return;
-    const int lane = threadIdx.x;
-    if (lane < M) v[lane] = zi ? zi[b * M + lane] : 0.0;
-    wave_sync();
-    // chained: items are chunks (matrix Phi_c, offset z_c; output xs per chunk);
-    // grouped: items are groups (aggregate with its offset; output ginc per group)
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t n = chain ? sv.C : groups_of(sv.C, GR.cpw);
     const int64_t id0 = chain ? sv.cbase : group_id(S, GR, b, 0);
     double *out = chain ? xs : ginc;
-    for (int64_t k0 = 0; k0 < n; k0 += CS::NB) {
-        const int nb = (int)min((int64_t)CS::NB, n - k0);
-        const int nt = (int)min((int64_t)nb, n - 1 - k0);  // items with a map (not the last)
+    const int64_t nbatch = (n + CS::NB - 1) / CS::NB;
+    auto stage = [&](int64_t bi, int t, int nt) {
+        double *buf = lds + (bi & 1) * CS::BUF_DOUBLES;
+        const int64_t k0 = bi * CS::NB;
+        const int64_t nm = min((int64_t)CS::NB, n - 1 - k0);  // items with a map
         if (chain) {
-            stage_doubles(lds, phiT + (id0 + k0) * MM, (int64_t)nt * MM, lane);
-            stage_doubles(lds + CS::NB * MM, zbuf + (id0 + k0) * M, (int64_t)nt * M, lane);
+            stage_doubles(buf, phiT + (id0 + k0) * MM, nm * MM, t, nt);
+            stage_doubles(buf + CS::NB * MM, zbuf + (id0 + k0) * M, nm * M, t, nt);
         } else {
-            stage_doubles(lds, aggbuf + (id0 + k0) * (MM + M), (int64_t)nt * (MM + M), lane);
+            stage_doubles(buf, aggbuf + (id0 + k0) * (MM + M), nm * (MM + M), t, nt);
         }
-        for (int k = 0; k < nb; ++k) {
-            if (lane < M) out[(id0 + k0 + k) * M + lane] = v[lane];
-            if (k < nt) {
-                const double *A = chain ? lds + k * MM : lds + k * (MM + M);
-                const double *z = chain ? lds + CS::NB * MM + k * M : A + MM;
-                lds_step<M>(A, 1, M, v, lane < M ? z[lane] : 0.0, lane);
+    };
+    if (wv == 0 && lane < M) v[lane] = zi ? zi[b * M + lane] : 0.0;
+    stage(0, tid, CS::THREADS);
+    __syncthreads();
+    for (int64_t bi = 0; bi < nbatch; ++bi) {
+        if (wv == 0) {
+            const double *buf = lds + (bi & 1) * CS::BUF_DOUBLES;
+            const int64_t k0 = bi * CS::NB;
+            const int nb = (int)min((int64_t)CS::NB, n - k0);
+            for (int k = 0; k < nb; ++k) {
+                if (lane < M) out[(id0 + k0 + k) * M + lane] = v[lane];
+                if (k0 + k + 1 < n) {
+                    const double *A = chain ? buf + k * MM : buf + k * (MM + M);
+                    const double *z = chain ? buf + CS::NB * MM + k * M : A + MM;
+                    lds_step<M>(A, 1, M, v, lane < M ? z[lane] : 0.0, lane);
+                }
             }
+        } else if (bi + 1 < nbatch) {
+            stage(bi + 1, tid - 64, CS::THREADS - 64);
         }
+        __syncthreads();
     }
 }
 
 template <int M, int CPW>
-__global__ __launch_bounds__(64) void k_fwd_expand(Seqs S, Groups GR, const double *__restrict__ phiT,
-                                                   const double *__restrict__ zbuf,
-                                                   const double *__restrict__ ginc, double *__restrict__ xs) {
+__global__ __launch_bounds__(256) void k_fwd_expand(Seqs S, Groups GR, const double *__restrict__ phiT,
+                                                    const double *__restrict__ zbuf,
+                                                    const double *__restrict__ ginc, double *__restrict__ xs) {
     constexpr int MM = M * M;
     __shared__ double lds[CPW * (MM + M) + M];
     double *v = lds + CPW * (MM + M);
@@ -140,14 +162,15 @@ __global__ __launch_bounds__(64) void k_fwd_expand(Seqs S, Groups GR, const doub
     group_at(S, GR, gid, b, g);
     const SeqView sv = seq_view(S, b);
     if (g >= groups_of(sv.C, CPW)) return;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
     const int64_t c0 = g * CPW;
     const int nk = (int)min((int64_t)CPW, sv.C - c0);
     const int nt = nk - 1;  // transitions needed inside the group
-    stage_doubles(lds, phiT + (sv.cbase + c0) * MM, (int64_t)nt * MM, lane);
-    stage_doubles(lds + CPW * MM, zbuf + (sv.cbase + c0) * M, (int64_t)nt * M, lane);
-    if (lane < M) v[lane] = ginc[gid * M + lane];
-    wave_sync();
+    stage_doubles(lds, phiT + (sv.cbase + c0) * MM, (int64_t)nt * MM, tid, blockDim.x);
+    stage_doubles(lds + CPW * MM, zbuf + (sv.cbase + c0) * M, (int64_t)nt * M, tid, blockDim.x);
+    if (tid < M) v[tid] = ginc[gid * M + tid];
+    __syncthreads();
+    if (tid >= 64) return;
     for (int k = 0; k < nk; ++k) {
         if (lane < M) xs[(sv.cbase + c0 + k) * M + lane] = v[lane];
         if (k < nt) lds_step<M>(lds + k * MM, 1, M, v, lane < M ? lds[CPW * MM + k * M + lane] : 0.0, lane);
@@ -156,66 +179,85 @@ __global__ __launch_bounds__(64) void k_fwd_expand(Seqs S, Groups GR, const doub
 
 // ---------------------------------------------------------------- adjoint
 
+// Chained: items are chunks (Phi_c^T, q_c; output yend per chunk; the last
+// chunk has no transition, y = q there); grouped: items are groups (reverse
+// map with its offset; output ginc per group; group 0 has no map).  Items are
+// visited from the last one down.
 template <int M>
-__global__ __launch_bounds__(64) void k_bwd_chain(Seqs S, Groups GR, const double *__restrict__ phiT,
-                                                  const double *__restrict__ qbuf,
-                                                  const double *__restrict__ aggbuf, double *__restrict__ ginc,
-                                                  double *__restrict__ yend, double *__restrict__ grad_zi,
-                                                  int chain) {
+__global__ __launch_bounds__(256) void k_bwd_chain(Seqs S, Groups GR, const double *__restrict__ phiT,
+                                                   const double *__restrict__ qbuf,
+                                                   const double *__restrict__ aggbuf, double *__restrict__ ginc,
+                                                   double *__restrict__ yend, double *__restrict__ grad_zi,
+                                                   int chain) {
     using CS = CarryShape<M>;
     constexpr int MM = M * M;
-    __shared__ double lds[CS::CHAIN_DOUBLES + M];
-    double *v = lds + CS::CHAIN_DOUBLES;
+    __shared__ double lds[2 * CS::BUF_DOUBLES + M];
+    double *v = lds + 2 * CS::BUF_DOUBLES;
     const int64_t b = blockIdx.x;
     const SeqView sv = seq_view(S, b);
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (sv.C <= 0) {  // no samples: no dependence on the initial state
-        if (grad_zi && lane < M) grad_zi[b * M + lane] = 0.0;
+        if (grad_zi && tid < M) grad_zi[b * M + tid] = 0.0;
         return;
     }
-    if (lane < M) v[lane] = 0.0;
-    wave_sync();
-    // chained: items are chunks (Phi_c^T, q_c; output yend per chunk, the last
-    // chunk has no transition); grouped: items are groups (reverse map with its
-    // offset; output ginc per group, group 0 has no map)
     const int64_t n = chain ? sv.C : groups_of(sv.C, GR.cpw);
     const int64_t id0 = chain ? sv.cbase : group_id(S, GR, b, 0);
     double *out = chain ? yend : ginc;
-    for (int64_t k1 = n; k1 > 0; k1 -= CS::NB) {
-        const int nb = (int)min((int64_t)CS::NB, k1);
-        const int64_t k0 = k1 - nb;  // items [k0, k1) staged, applied from the end
+    const int64_t nbatch = (n + CS::NB - 1) / CS::NB;
+    // batch bi holds items [k0, k0 + nb) with k0 + nb = n - bi * NB
+    auto range = [&](int64_t bi, int64_t &k0, int &nb) {
+        const int64_t k1 = n - bi * CS::NB;
+        nb = (int)min((int64_t)CS::NB, k1);
+        k0 = k1 - nb;
+    };
+    auto stage = [&](int64_t bi, int t, int nt) {
+        double *buf = lds + (bi & 1) * CS::BUF_DOUBLES;
+        int64_t k0;
+        int nb;
+        range(bi, k0, nb);
         if (chain) {
-            stage_doubles(lds, phiT + (id0 + k0) * MM, (int64_t)nb * MM, lane);
-            stage_doubles(lds + CS::NB * MM, qbuf + (id0 + k0) * M, (int64_t)nb * M, lane);
+            stage_doubles(buf, phiT + (id0 + k0) * MM, (int64_t)nb * MM, t, nt);
+            stage_doubles(buf + CS::NB * MM, qbuf + (id0 + k0) * M, (int64_t)nb * M, t, nt);
         } else {
-            stage_doubles(lds, aggbuf + (id0 + k0) * (MM + M), (int64_t)nb * (MM + M), lane);
+            stage_doubles(buf, aggbuf + (id0 + k0) * (MM + M), (int64_t)nb * (MM + M), t, nt);
         }
-        for (int k = nb - 1; k >= 0; --k) {
-            const int64_t item = k0 + k;
-            if (lane < M) out[(id0 + item) * M + lane] = v[lane];
-            if (chain) {
-                const double q = lane < M ? lds[CS::NB * MM + k * M + lane] : 0.0;
-                if (item == n - 1) {
-                    wave_sync();
-                    if (lane < M) v[lane] = q;  // the last chunk: y = q
-                    wave_sync();
-                } else {
-                    lds_step<M>(lds + k * MM, M, 1, v, q, lane);
+    };
+    if (wv == 0 && lane < M) v[lane] = 0.0;
+    stage(0, tid, CS::THREADS);
+    __syncthreads();
+    for (int64_t bi = 0; bi < nbatch; ++bi) {
+        if (wv == 0) {
+            const double *buf = lds + (bi & 1) * CS::BUF_DOUBLES;
+            int64_t k0;
+            int nb;
+            range(bi, k0, nb);
+            for (int k = nb - 1; k >= 0; --k) {
+                const int64_t item = k0 + k;
+                if (lane < M) out[(id0 + item) * M + lane] = v[lane];
+                if (chain) {
+                    const double q = lane < M ? buf[CS::NB * MM + k * M + lane] : 0.0;
+                    if (item == n - 1)
+                        lds_set<M>(v, q, lane);
+                    else
+                        lds_step<M>(buf + k * MM, M, 1, v, q, lane);
+                } else if (item > 0) {
+                    const double *A = buf + k * (MM + M);
+                    lds_step<M>(A, M, 1, v, lane < M ? A[MM + lane] : 0.0, lane);
                 }
-            } else if (item > 0) {
-                const double *A = lds + k * (MM + M);
-                lds_step<M>(A, M, 1, v, lane < M ? A[MM + lane] : 0.0, lane);
             }
+            if (chain && bi + 1 == nbatch && grad_zi && lane < M) grad_zi[b * M + lane] = v[lane];
+        } else if (bi + 1 < nbatch) {
+            stage(bi + 1, tid - 64, CS::THREADS - 64);
         }
+        __syncthreads();
     }
-    if (chain && grad_zi && lane < M) grad_zi[b * M + lane] = v[lane];
 }
 
 template <int M, int CPW>
-__global__ __launch_bounds__(64) void k_bwd_expand(Seqs S, Groups GR, const double *__restrict__ phiT,
-                                                   const double *__restrict__ qbuf,
-                                                   const double *__restrict__ ginc, double *__restrict__ yend,
-                                                   double *__restrict__ grad_zi) {
+__global__ __launch_bounds__(256) void k_bwd_expand(Seqs S, Groups GR, const double *__restrict__ phiT,
+                                                    const double *__restrict__ qbuf,
+                                                    const double *__restrict__ ginc, double *__restrict__ yend,
+                                                    double *__restrict__ grad_zi) {
     constexpr int MM = M * M;
     __shared__ double lds[CPW * (MM + M) + M];
     double *v = lds + CPW * (MM + M);
@@ -225,26 +267,24 @@ __global__ __launch_bounds__(64) void k_bwd_expand(Seqs S, Groups GR, const doub
     group_at(S, GR, gid, b, g);
     const SeqView sv = seq_view(S, b);
     if (g >= groups_of(sv.C, CPW)) return;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
     const int64_t c0 = g * CPW;
     const int nk = (int)min((int64_t)CPW, sv.C - c0);
     const bool need_first = (g == 0) && grad_zi;  // y(0) is dL/dzi
-    stage_doubles(lds, phiT + (sv.cbase + c0) * MM, (int64_t)nk * MM, lane);
-    stage_doubles(lds + CPW * MM, qbuf + (sv.cbase + c0) * M, (int64_t)nk * M, lane);
-    if (lane < M) v[lane] = ginc[gid * M + lane];
-    wave_sync();
+    stage_doubles(lds, phiT + (sv.cbase + c0) * MM, (int64_t)nk * MM, tid, blockDim.x);
+    stage_doubles(lds + CPW * MM, qbuf + (sv.cbase + c0) * M, (int64_t)nk * M, tid, blockDim.x);
+    if (tid < M) v[tid] = ginc[gid * M + tid];
+    __syncthreads();
+    if (tid >= 64) return;
     for (int k = nk - 1; k >= 0; --k) {
         const int64_t c = c0 + k;
         if (lane < M) yend[(sv.cbase + c) * M + lane] = v[lane];
         if (k == 0 && !need_first) break;  // y at the group start is not needed
         const double q = lane < M ? lds[CPW * MM + k * M + lane] : 0.0;
-        if (c == sv.C - 1) {  // the sequence's last chunk: y = q
-            wave_sync();
-            if (lane < M) v[lane] = q;
-            wave_sync();
-        } else {
+        if (c == sv.C - 1)  // the sequence's last chunk: y = q
+            lds_set<M>(v, q, lane);
+        else
             lds_step<M>(lds + k * MM, M, 1, v, q, lane);
-        }
     }
     if (need_first && lane < M) grad_zi[b * M + lane] = v[lane];
 }
