@@ -149,7 +149,7 @@ struct FwdScanShape {
 constexpr int waitcnt_vm(int n) { return (n & 0xF) | (0x7 << 4) | (0xF << 8) | (((n >> 4) & 0x3) << 14); }
 
 template <int M, int LPC, int CPL, int R>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_fwd_local(
+__global__ __launch_bounds__(64) void k_fwd_local(
     Seqs S, Groups GR, const float *__restrict__ e, const float *__restrict__ a, double *__restrict__ phiT,
     double *__restrict__ zbuf, double *__restrict__ aggbuf, int chain) {
     using SH = FwdScanShape<M, LPC, CPL, R>;
@@ -230,17 +230,27 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
                 off[i] = min(off[i] + step[i], lim[i]);
             }
         };
+        // row t's coefficients and excitation, read from the ring during step t-1
+        auto load_row = [&](int t, float (&rv)[M], float &ex) {
+            const float *slotp = ring + (t % SH::NS) * (SH::DMA_N * 64);
+            const float *row = slotp + (slot < CPW ? slot : 0) * M;
+#pragma unroll
+            for (int i = 0; i < M; ++i) rv[i] = row[i];
+            ex = slotp[CPW * M + (slot < CPW ? slot : 0)];
+        };
         for (int t = 0; t < SH::D; ++t) issue(t);
+        __builtin_amdgcn_s_waitcnt(waitcnt_vm(SH::DMA_N * (SH::D - 1)));  // row 0 has landed
+        float rv[M], ex;
+        load_row(0, rv, ex);
         for (int t0 = 0; t0 < L; t0 += M) {
             Unroll<M, 0>::run([&](auto kc) {
                 constexpr int K = decltype(kc)::value;
                 const int t = t0 + K;
                 __builtin_amdgcn_sched_barrier(0);  // no DMA above the previous step's LDS reads
-                issue(t + SH::D);
-                __builtin_amdgcn_s_waitcnt(waitcnt_vm(SH::DMA_N * SH::D));  // row t has landed
-                const float *slotp = ring + (t % SH::NS) * (SH::DMA_N * 64);
-                const float *row = slotp + slot * M;
-                const float ex = slotp[CPW * M + (slot < CPW ? slot : 0)];
+                issue(t + SH::D);  // overwrites the slot of row t-1, consumed in step t-1
+                __builtin_amdgcn_s_waitcnt(waitcnt_vm(SH::DMA_N * (SH::D - 1)));  // row t+1 has landed
+                float nrv[M], nex;
+                load_row(t + 1, nrv, nex);
                 double acc[CPL][2];
 #pragma unroll
                 for (int m = 0; m < CPL; ++m) {
@@ -249,12 +259,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
                 }
 #pragma unroll
                 for (int i = 1; i <= M; ++i) {
-                    const double ai = (double)row[i - 1];
+                    const double ai = (double)rv[i - 1];
 #pragma unroll
                     for (int m = 0; m < CPL; ++m) acc[m][i & 1] = fma(-ai, h[m][wrap<M>(K - i)], acc[m][i & 1]);
                 }
 #pragma unroll
                 for (int m = 0; m < CPL; ++m) h[m][K] = acc[m][0] + acc[m][1];
+#pragma unroll
+                for (int i = 0; i < M; ++i) rv[i] = nrv[i];
+                ex = nex;
             });
         }
         __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));  // drain the look-ahead before the ring is reused
