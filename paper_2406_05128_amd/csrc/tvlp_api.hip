@@ -138,7 +138,7 @@ constexpr size_t kStatusOffset = 256;  // byte offset of the scan status word in
 
 // Workspace layout for one call with nch chunks and n samples over B sequences.
 struct WsLayout {
-    size_t xs, phi, yend, q, cbase, gbf, gbb, aggf, inclf, aggb, inclb, status, total;
+    size_t zero, xs, phi, yend, q, cbase, gbf, gbb, aggf, inclf, aggb, inclb, status, total;
 };
 
 // ngf / ngb: group slots of the forward / adjoint scans.
@@ -146,7 +146,7 @@ WsLayout ws_layout(int M, int64_t nch, int64_t B, int64_t ngf, int64_t ngb) {
     WsLayout w{};
     size_t off = 0;
     const size_t agg = (size_t)(M * M + M) * sizeof(double);
-    off += 256;                  // reserved
+    w.zero = off;  off += 256;   // stays zero (the ring DMAs' spare lanes read it)
     w.status = off;  off += 256;  // status word at a fixed offset
     w.xs = off;    off += align_up(bytes_state(M, nch));
     w.phi = off;   off += align_up(bytes_phi(M, nch));
@@ -295,7 +295,11 @@ TVLP_FWD_SHAPE(32, 17, 2, 2)
 // Lanes per chunk of the systolic reruns and rows per LDS slab.
 template <int M>
 struct RerunShape {
+#ifdef TVLP_RERUN_G
+    static constexpr int G = TVLP_RERUN_G;
+#else
     static constexpr int G = M >= 8 ? 8 : 4;
+#endif
     static constexpr int R = 16;
     static constexpr int CPW = 64 / G;
 };
@@ -325,6 +329,7 @@ struct Ops {
         double *xs, *phiT, *yend, *zbuf, *qbuf;
         double *aggf, *inclf, *aggb, *inclb;  // group maps and group carries
         int *status;
+        const float *zero;  // 64 floats of 0 in device memory
         int chain;  // chained carry: no matrix products between chunk transitions
     };
 
@@ -345,7 +350,7 @@ struct Ops {
         tm.end();
         tm.begin("fwd_emit");
         hipLaunchKernelGGL((k_fwd_rerun2<M, RS::G>), dim3((unsigned)ceil_div(w.nch, RS::CPW)), dim3(64), 0, st,
-                           w.S, e, a, w.xs, s, zf, w.nch);
+                           w.S, e, a, w.xs, s, zf, w.zero, w.nch);
         tm.end();
     }
 
@@ -354,7 +359,7 @@ struct Ops {
         if (w.nch <= 0) return;
         tm.begin("bwd_scan");
         hipLaunchKernelGGL((k_bwd_local<M, RS::G, RS::R>), dim3((unsigned)w.gb.ngroups), dim3(64), 0, st, w.S,
-                           w.gb, g, a, w.phiT, w.qbuf, w.aggb, w.chain);
+                           w.gb, g, a, w.phiT, w.qbuf, w.aggb, w.zero, w.chain);
         tm.end();
         tm.begin("bwd_carry");
         const dim3 ct(CarryShape<M>::THREADS);
@@ -370,10 +375,10 @@ struct Ops {
             tm.begin("bwd_emit");
             if (s_in)
                 hipLaunchKernelGGL((k_adj_emit2<M, RS::G, true>), dim3(grid), dim3(64), dyn, st, w.S, g, a, e, s_in,
-                                   w.xs, w.yend, ge, ga, w.nch);
+                                   w.xs, w.yend, ge, ga, w.zero, w.nch);
             else
                 hipLaunchKernelGGL((k_adj_emit2<M, RS::G, false>), dim3(grid), dim3(64), dyn, st, w.S, g, a, e,
-                                   s_in, w.xs, w.yend, ge, ga, w.nch);
+                                   s_in, w.xs, w.yend, ge, ga, w.zero, w.nch);
             tm.end();
         }
     }
@@ -505,6 +510,7 @@ int prepare(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, const
     w.aggb = (double *)(ws + lay.aggb);
     w.inclb = (double *)(ws + lay.inclb);
     w.status = (int *)(ws + lay.status);
+    w.zero = (const float *)(ws + lay.zero);
     w.chain = (p->flags & LP_FLAG_CHAINED_CARRY) ? 1 : 0;
     return LP_OK;
 }

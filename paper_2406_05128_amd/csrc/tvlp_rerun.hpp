@@ -3,16 +3,28 @@
 // RowRing streams, for the CPW chunks of a wave, one coefficient row (M floats)
 // plus one per-sample scalar (e or g) per step into an LDS ring slot with
 // global_load_lds (no VGPRs held for prefetch).  D steps are kept in flight;
-// before reading slot u the wave waits until at most DMA_N*D vector-memory
+// before reading slot u the wave waits until at most DMA_N*(D-1) vector-memory
 // operations are outstanding, which is only reached once row u has landed
 // (the ring loads are issued unconditionally, one group per step, in order).
-// Rows outside a chunk are replaced by a read of a valid dummy address.
+//
+// Every slot ends with at least one spare DMA lane that reads a zero word from
+// device memory, so LDS float ZERO of every slot holds 0: taps beyond M read
+// it instead of being masked.
+//
+// Two kinds of steps share the ring.  While every row a step issues lies
+// inside its chunk (the first U steps, U a multiple of NS, below the shortest
+// chunk of the wave minus D), each lane's DMA address is advanced by one 64-bit
+// add and the ring slot is a compile-time constant of an unrolled block.  The
+// remaining steps clamp each lane's row into its chunk (rows outside a chunk are
+// never used) and read the slot index at run time.
 //
 // The compiler models a global_load_lds as a 4-byte LDS store at its pointer,
 // not as the 256-byte wave-wide write it is, so it may move the next step's
 // DMA above this step's reads of the slot that DMA overwrites.  Every loop over
 // ring steps therefore starts each step with a scheduling barrier.
 #pragma once
+
+#include <type_traits>
 
 #include "tvlp_systolic.hpp"
 
@@ -26,28 +38,31 @@ typedef __attribute__((address_space(3))) void lds_void_t;
 template <int M, int CPW, bool DESC>
 struct RowRing {
     static constexpr int ROWF = CPW * M + CPW;      // floats per step actually used
-    static constexpr int DMA_N = (ROWF + 63) / 64;  // dword DMA instructions per step
+    static constexpr int DMA_N = ROWF / 64 + 1;     // dword DMA instructions per step (>= 1 spare lane)
     static constexpr int D = (63 / DMA_N) < 15 ? (63 / DMA_N) : 15;
     static constexpr int NS = D + 1;
     static constexpr int SLOT = DMA_N * 64;  // floats per ring slot
     static constexpr int FLOATS = NS * SLOT;
+    static constexpr int ZERO = ROWF;  // slot float that always holds 0
 
     typedef __attribute__((address_space(1))) const char gchar;
     typedef __attribute__((address_space(3))) float lfloat;
 
     // Per DMA instruction: the lane's row-0 address, its current byte offset,
-    // the per-step byte increment and the last valid offset.  Steps walk the
-    // rows 0 .. len-1 (descending: len-1 .. 0) and then repeat the last row
-    // reached, so every address stays inside the lane's chunk; a lane with
-    // no rows reads the first element of `a` throughout.
+    // the per-step byte increment and the last valid offset (clamped steps),
+    // and the running address (unclamped steps).  Steps walk the rows
+    // 0 .. len-1 (descending: len-1 .. 0) and then repeat the last row reached,
+    // so every address stays inside the lane's chunk; a lane with no rows, and
+    // a spare lane, reads the zero word throughout.
     gchar *base[DMA_N];
+    gchar *ptr[DMA_N];
     int off[DMA_N], step[DMA_N], lim[DMA_N];
 
     // my_base: element index of row 0 of this lane's chunk; my_len: its rows
-    // (0 if the lane's chunk is inactive); G: lanes per chunk; my_xoff: offset
-    // added to my_base for the scalar stream x.
-    __device__ __forceinline__ void init(const float *a, const float *x, int lane, int64_t my_base,
-                                         int64_t my_len, int G, int64_t my_xoff = 0) {
+    // (0 if the lane's chunk is inactive); G: lanes per chunk; zero: a device
+    // float holding 0; my_xoff: offset added to my_base for the scalar stream x.
+    __device__ __forceinline__ void init(const float *a, const float *x, const float *zero, int lane,
+                                         int64_t my_base, int64_t my_len, int G, int64_t my_xoff = 0) {
 #pragma unroll
         for (int i = 0; i < DMA_N; ++i) {
             const int j = 64 * i + lane;
@@ -66,7 +81,7 @@ struct RowRing {
             const int64_t kl = __shfl(my_len, k * G, 64);
             const int64_t kx = __shfl(my_xoff, k * G, 64);
             const bool live = valid && kl > 0;
-            const float *p0 = !live ? a : (coef ? a + kb * M + f : x + kb + kx);
+            const float *p0 = !live ? zero : (coef ? a + kb * M + f : x + kb + kx);
             const int st = live ? (coef ? 4 * M : 4) : 0;
             base[i] = (gchar *)p0;
             step[i] = st;
@@ -75,6 +90,7 @@ struct RowRing {
         }
     }
 
+    // Clamped step: row u into slot u % NS.
     __device__ __forceinline__ void issue(float *ring, int u) {
         lfloat *dst = (lfloat *)ring + (u % NS) * SLOT;
 #pragma unroll
@@ -84,6 +100,26 @@ struct RowRing {
             off[i] = DESC ? max(off[i] - step[i], 0) : min(off[i] + step[i], lim[i]);
         }
     }
+    // Switch to unclamped steps (every row until the switch back lies inside its chunk).
+    __device__ __forceinline__ void begin_fast() {
+#pragma unroll
+        for (int i = 0; i < DMA_N; ++i) ptr[i] = base[i] + off[i];
+    }
+    // Unclamped step into slot KS.
+    template <int KS>
+    __device__ __forceinline__ void issue_fast(float *ring) {
+        lfloat *dst = (lfloat *)ring + KS * SLOT;
+#pragma unroll
+        for (int i = 0; i < DMA_N; ++i) {
+            __builtin_amdgcn_global_load_lds((const void *)ptr[i], (lds_void_t *)(dst + 64 * i), 4, 0, 0);
+            ptr[i] += DESC ? -(int64_t)step[i] : (int64_t)step[i];
+        }
+    }
+    // Back to clamped steps, the next row issued being row n.
+    __device__ __forceinline__ void end_fast(int n) {
+#pragma unroll
+        for (int i = 0; i < DMA_N; ++i) off[i] = DESC ? max(lim[i] - n * step[i], 0) : min(n * step[i], lim[i]);
+    }
 
     __device__ __forceinline__ static void wait() { __builtin_amdgcn_s_waitcnt(waitcnt_vm_only(DMA_N * D)); }
     // After issue(u + D): row u + 1 has landed (rows u+2 .. u+D may still be in flight).
@@ -91,24 +127,74 @@ struct RowRing {
         __builtin_amdgcn_s_waitcnt(waitcnt_vm_only(DMA_N * (D - 1)));
     }
     __device__ __forceinline__ static void drain() { __builtin_amdgcn_s_waitcnt(waitcnt_vm_only(0)); }
-    __device__ __forceinline__ static const float *slot_ptr(const float *ring, int u) {
-        return ring + (u % NS) * SLOT;
-    }
-    // The taps r*TPL .. r*TPL+TPL-1 of this lane's chunk row (0 beyond M) and
-    // the chunk's scalar, from ring slot u, as float64.
+
+    // LDS float indices (within a slot) of the lane's taps r*TPL .. r*TPL+TPL-1
+    // (ZERO beyond M) and of its chunk's scalar.
     template <int TPL>
-    __device__ __forceinline__ static void load(const float *ring, int u, int slot, int r, double (&av)[TPL],
-                                                double &x) {
-        const float *sp = slot_ptr(ring, u);
+    struct Lanes {
+        int tap[TPL];
+        int x;
+        __device__ __forceinline__ Lanes(int slot, int r) {
 #pragma unroll
-        for (int m = 0; m < TPL; ++m) {
-            const int tap = r * TPL + m;
-            const float v = sp[slot * M + (tap < M ? tap : 0)];
-            av[m] = tap < M ? (double)v : 0.0;
+            for (int m = 0; m < TPL; ++m) {
+                const int t = r * TPL + m;
+                tap[m] = t < M ? slot * M + t : ZERO;
+            }
+            x = CPW * M + slot;
         }
-        x = (double)sp[CPW * M + slot];
+    };
+    // The lane's taps and scalar from ring slot ks (run-time or compile-time), as float64.
+    template <int TPL, class KS, class LN>
+    __device__ __forceinline__ static void load(const float *ring, KS ks, const LN &ln, double (&av)[TPL],
+                                                double &x) {
+        static_assert(sizeof(ln.tap) == TPL * sizeof(int), "lane table of another tap count");
+        const float *sp = ring + (int)ks * SLOT;
+#pragma unroll
+        for (int m = 0; m < TPL; ++m) av[m] = (double)sp[ln.tap[m]];
+        x = (double)sp[ln.x];
     }
 };
+
+// Number of leading steps (a multiple of NS) whose issued rows all lie inside
+// their chunks: every chunk slot of the wave must be active with at least
+// U + D rows.  my_len: the lane's chunk rows (0 if inactive).
+template <class RR, int G, int CPW>
+__device__ __forceinline__ int fast_steps(int64_t my_len) {
+    int mn = 0x7fffffff;
+#pragma unroll
+    for (int k = 0; k < CPW; ++k) mn = min(mn, __builtin_amdgcn_readlane((int)my_len, k * G));
+    const int u = mn - RR::D;
+    return u > 0 ? u / RR::NS * RR::NS : 0;
+}
+
+// Drives steps u = 0 .. L-1 of a ring loop whose D-row prologue has been
+// issued and whose step-0 operands are loaded.  body(u, ks, fast) runs step u;
+// ks is the slot of step u + 1 (an integral_constant on unclamped steps) and
+// fast is std::true_type on unclamped steps (every chunk of the wave live).
+template <class RR, class Body>
+__device__ __forceinline__ void ring_loop(RR &rr, float *ring, int L, int U, Body &&body) {
+    constexpr int NS = RR::NS, D = RR::D;
+    if (U > 0) {
+        rr.begin_fast();
+        for (int ub = 0; ub < U; ub += NS) {
+            Unroll<NS, 0>::run([&](auto kc) {
+                constexpr int K = decltype(kc)::value;
+                __builtin_amdgcn_sched_barrier(0);  // no DMA above the previous step's LDS reads
+                rr.template issue_fast<(K + D) % NS>(ring);
+                RR::wait_next();
+                body(ub + K, std::integral_constant<int, (K + 1) % NS>{}, std::true_type{});
+            });
+        }
+        rr.end_fast(U + D);
+    }
+    for (int u = U; u < L; ++u) {
+        __builtin_amdgcn_sched_barrier(0);
+        rr.issue(ring, u + D);
+        RR::wait_next();
+        body(u, (u + 1) % NS, std::false_type{});
+    }
+    RR::drain();
+}
 
 // Forward rerun of each chunk from its saved entry state: writes s and, for a
 // sequence's last chunk, zf.  Also recomputes s for the adjoint.
@@ -117,7 +203,7 @@ __global__ __launch_bounds__(64) void k_fwd_rerun2(Seqs S, const float *__restri
                                                    const float *__restrict__ a,
                                                    const double *__restrict__ xs,
                                                    float *__restrict__ s, double *__restrict__ zf,
-                                                   int64_t nch) {
+                                                   const float *__restrict__ zero, int64_t nch) {
     constexpr int CPW = 64 / G;
     constexpr int TPL = (M + G - 1) / G;
     using RR = RowRing<M, CPW, false>;
@@ -145,35 +231,40 @@ __global__ __launch_bounds__(64) void k_fwd_rerun2(Seqs S, const float *__restri
         hist[m] = (active && k < M) ? xs[gc * M + k] : 0.0;
     }
     RR rr;
-    rr.init(a, e, lane, base, len, G);
+    rr.init(a, e, zero, lane, base, len, G);
+    const typename RR::template Lanes<TPL> ln(slot, r);
     const int L = S.L;
     for (int u = 0; u < RR::D; ++u) rr.issue(ring, u);
     RR::wait_next();  // row 0
     // step u's operands are read from LDS during step u-1
     double av[TPL], ex;
-    RR::load(ring, 0, slot, r, av, ex);
-    for (int u = 0; u < L; ++u) {
-        __builtin_amdgcn_sched_barrier(0);  // see RowRing: no DMA above the previous step's LDS reads
-        rr.issue(ring, u + RR::D);
-        RR::wait_next();
+    RR::load(ring, 0, ln, av, ex);
+    float *so = s + base;
+    ring_loop(rr, ring, L, fast_steps<RR, G, CPW>(len), [&](int u, auto ks, auto fast) {
         double nav[TPL], nex;
-        RR::load(ring, u + 1, slot, r, nav, nex);
+        RR::load(ring, ks, ln, nav, nex);
         double part = 0.0;
 #pragma unroll
         for (int m = 0; m < TPL; ++m) part = fma(av[m], hist[m], part);
-        const double tot = group_sum<G>(part);
+        const double tot = group_sum<G>(part);  // in every lane of the group
         const double y = ex - tot;
         const double up = dpp_f64<DPP_ROW_SHR1>(hist[TPL - 1]);
-        const bool live = u < len;
-        if (live && r == 0) s[base + u] = (float)y;
+        if constexpr (decltype(fast)::value) {
+            so[u] = (float)y;
 #pragma unroll
-        for (int m = TPL - 1; m > 0; --m) hist[m] = live ? hist[m - 1] : hist[m];
-        hist[0] = live ? ((r == 0) ? y : up) : hist[0];
+            for (int m = TPL - 1; m > 0; --m) hist[m] = hist[m - 1];
+            hist[0] = (r == 0) ? y : up;
+        } else {
+            const bool live = u < len;
+            if (live && r == 0) so[u] = (float)y;
+#pragma unroll
+            for (int m = TPL - 1; m > 0; --m) hist[m] = live ? hist[m - 1] : hist[m];
+            hist[0] = live ? ((r == 0) ? y : up) : hist[0];
+        }
 #pragma unroll
         for (int m = 0; m < TPL; ++m) av[m] = nav[m];
         ex = nex;
-    }
-    RR::drain();
+    });
     if (zf && active) {
         const SeqView v = seq_view(S, b);
         if (c == v.C - 1) {
@@ -202,7 +293,7 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
                                                   const double *__restrict__ xs,
                                                   const double *__restrict__ yend,
                                                   float *__restrict__ ge, float *__restrict__ ga,
-                                                  int64_t nch) {
+                                                  const float *__restrict__ zero, int64_t nch) {
     constexpr int CPW = 64 / G;
     constexpr int TPL = (M + G - 1) / G;
     using RA = RowRing<M, CPW, false>;
@@ -231,6 +322,8 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
     float *ssh = ssh_dyn + slot * (M + L);
     float *gsh_all = ssh_dyn + CPW * (M + L);
     float *gsh = gsh_all + slot * L;
+    const typename RA::template Lanes<TPL> ln(slot, r);
+    const int U = fast_steps<RA, G, CPW>(len);
     for (int k = r; k < M; k += G) ssh[M - 1 - k] = active ? (float)xs[gc * M + k] : 0.f;
     if constexpr (STORED_S) {
         for (int t = r; t < L; t += G) ssh[M + t] = (active && t < len) ? s_in[base + t] : 0.f;
@@ -242,33 +335,36 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
             hist[m] = (active && k < M) ? xs[gc * M + k] : 0.0;
         }
         RA ra;
-        ra.init(a, e, lane, base, len, G);
+        ra.init(a, e, zero, lane, base, len, G);
         for (int u = 0; u < RA::D; ++u) ra.issue(ring, u);
         RA::wait_next();  // row 0
         double av[TPL], ex;
-        RA::load(ring, 0, slot, r, av, ex);
-        for (int u = 0; u < L; ++u) {
-            __builtin_amdgcn_sched_barrier(0);
-            ra.issue(ring, u + RA::D);
-            RA::wait_next();
+        RA::load(ring, 0, ln, av, ex);
+        float *sw = ssh + M;
+        ring_loop(ra, ring, L, U, [&](int u, auto ks, auto fast) {
             double nav[TPL], nex;
-            RA::load(ring, u + 1, slot, r, nav, nex);
+            RA::load(ring, ks, ln, nav, nex);
             double part = 0.0;
 #pragma unroll
             for (int m = 0; m < TPL; ++m) part = fma(av[m], hist[m], part);
             const double tot = group_sum<G>(part);
             const double y = ex - tot;
             const double up = dpp_f64<DPP_ROW_SHR1>(hist[TPL - 1]);
-            if (r == 0) ssh[M + u] = (float)y;  // entries at u >= len are never read
-            const bool live = u < len;
+            if (r == 0) sw[u] = (float)y;  // entries at u >= len are never read
+            if constexpr (decltype(fast)::value) {
 #pragma unroll
-            for (int m = TPL - 1; m > 0; --m) hist[m] = live ? hist[m - 1] : hist[m];
-            hist[0] = live ? ((r == 0) ? y : up) : hist[0];
+                for (int m = TPL - 1; m > 0; --m) hist[m] = hist[m - 1];
+                hist[0] = (r == 0) ? y : up;
+            } else {
+                const bool live = u < len;
+#pragma unroll
+                for (int m = TPL - 1; m > 0; --m) hist[m] = live ? hist[m - 1] : hist[m];
+                hist[0] = live ? ((r == 0) ? y : up) : hist[0];
+            }
 #pragma unroll
             for (int m = 0; m < TPL; ++m) av[m] = nav[m];
             ex = nex;
-        }
-        RA::drain();
+        });
     }
     __syncthreads();
 
@@ -285,18 +381,15 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
         }
     }
     RD rd;
-    rd.init(a, g, lane, base, len, G, goff);
+    rd.init(a, g, zero, lane, base, len, G, goff);
     for (int u = 0; u < RD::D; ++u) rd.issue(ring, u);
     RD::wait_next();  // row 0 (sample len - 1)
     double av[TPL], gx;
-    RD::load(ring, 0, slot, r, av, gx);
-    for (int u = 0; u < L; ++u) {
-        __builtin_amdgcn_sched_barrier(0);
-        rd.issue(ring, u + RD::D);
-        RD::wait_next();
+    RD::load(ring, 0, ln, av, gx);
+    float *gw = gsh + (len - 1);  // gw[-u] = ghat(len - 1 - u)
+    ring_loop(rd, ring, L, U, [&](int u, auto ks, auto fast) {
         double nav[TPL], ngx;
-        RD::load(ring, u + 1, slot, r, nav, ngx);
-        const int t = (int)len - 1 - u;
+        RD::load(ring, ks, ln, nav, ngx);
         const double gh = gx + P0;
         double np[TPL];
 #pragma unroll
@@ -304,17 +397,24 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
         // cross-lane moves by every lane, then the step is committed where valid
         const double down = dpp_f64<DPP_ROW_SHL1>(np[0]);
         const double b0 = group_bcast0<G>(np[0], r);
-        const bool live = u < len;
-        if (live && r == 0) gsh[t] = (float)gh;
-        P0 = live ? b0 : P0;
+        if constexpr (decltype(fast)::value) {
+            if (r == 0) gw[-u] = (float)gh;
+            P0 = b0;
 #pragma unroll
-        for (int m = 0; m + 1 < TPL; ++m) P[m] = live ? np[m + 1] : P[m];
-        P[TPL - 1] = live ? ((r == G - 1) ? 0.0 : down) : P[TPL - 1];
+            for (int m = 0; m + 1 < TPL; ++m) P[m] = np[m + 1];
+            P[TPL - 1] = (r == G - 1) ? 0.0 : down;
+        } else {
+            const bool live = u < len;
+            if (live && r == 0) gw[-u] = (float)gh;
+            P0 = live ? b0 : P0;
+#pragma unroll
+            for (int m = 0; m + 1 < TPL; ++m) P[m] = live ? np[m + 1] : P[m];
+            P[TPL - 1] = live ? ((r == G - 1) ? 0.0 : down) : P[TPL - 1];
+        }
 #pragma unroll
         for (int m = 0; m < TPL; ++m) av[m] = nav[m];
         gx = ngx;
-    }
-    RD::drain();
+    });
     __syncthreads();
 
     // ---- dL/de(t) = ghat(t), dL/da_i(t) = -ghat(t) s(t-i), chunk by chunk with all lanes

@@ -348,7 +348,7 @@ template <int M, int G, int R>
 __global__ __launch_bounds__(64) void k_bwd_local(Seqs S, Groups GR, const float *__restrict__ g_in,
                                                   const float *__restrict__ a, const double *__restrict__ phiT,
                                                   double *__restrict__ qbuf, double *__restrict__ aggbuf,
-                                                  int chain) {
+                                                  const float *__restrict__ zero, int chain) {
     using SH = BwdScanShape<M, G, R>;
     using RD = typename SH::RD;
     constexpr int CPW = SH::CPW;
@@ -391,35 +391,40 @@ __global__ __launch_bounds__(64) void k_bwd_local(Seqs S, Groups GR, const float
     for (int m = 0; m < TPL; ++m) P[m] = 0.0;
     {
         RD rd;
-        rd.init(a, g_in, lane, base, len, G, gshare_offset(S, b));
+        rd.init(a, g_in, zero, lane, base, len, G, gshare_offset(S, b));
+        const typename RD::template Lanes<TPL> ln(slot, r);
         for (int u = 0; u < RD::D; ++u) rd.issue(ring, u);
         RD::wait_next();  // row 0 (the chunk's last sample)
         double av[TPL], gx;
-        RD::load(ring, 0, slot, r, av, gx);
-        for (int u = 0; u < L; ++u) {
-            __builtin_amdgcn_sched_barrier(0);
-            rd.issue(ring, u + RD::D);
-            RD::wait_next();
+        RD::load(ring, 0, ln, av, gx);
+        ring_loop(rd, ring, L, fast_steps<RD, G, CPW>(len), [&](int u, auto ks, auto fast) {
             double nav[TPL], ngx;
-            RD::load(ring, u + 1, slot, r, nav, ngx);
+            RD::load(ring, ks, ln, nav, ngx);
             const double gh = gx + P0;
             double np[TPL];
 #pragma unroll
             for (int m = 0; m < TPL; ++m) np[m] = fma(-av[m], gh, P[m]);
             const double down = dpp_f64<DPP_ROW_SHL1>(np[0]);
             const double b0 = group_bcast0<G>(np[0], r);
-            // a step inside the chunk shifts the pendings one tap down; the
-            // chunk's first sample (u = len - 1) keeps the un-shifted p(-i)
-            const bool shift = u + 1 < len, last = u + 1 == len;
-            P0 = shift ? b0 : P0;
+            if constexpr (decltype(fast)::value) {
+                // unclamped steps end before the chunk's first sample
+                P0 = b0;
 #pragma unroll
-            for (int m = 0; m + 1 < TPL; ++m) P[m] = shift ? np[m + 1] : (last ? np[m] : P[m]);
-            P[TPL - 1] = shift ? ((r == G - 1) ? 0.0 : down) : (last ? np[TPL - 1] : P[TPL - 1]);
+                for (int m = 0; m + 1 < TPL; ++m) P[m] = np[m + 1];
+                P[TPL - 1] = (r == G - 1) ? 0.0 : down;
+            } else {
+                // a step inside the chunk shifts the pendings one tap down; the
+                // chunk's first sample (u = len - 1) keeps the un-shifted p(-i)
+                const bool shift = u + 1 < len, last = u + 1 == len;
+                P0 = shift ? b0 : P0;
+#pragma unroll
+                for (int m = 0; m + 1 < TPL; ++m) P[m] = shift ? np[m + 1] : (last ? np[m] : P[m]);
+                P[TPL - 1] = shift ? ((r == G - 1) ? 0.0 : down) : (last ? np[TPL - 1] : P[TPL - 1]);
+            }
 #pragma unroll
             for (int m = 0; m < TPL; ++m) av[m] = nav[m];
             gx = ngx;
-        }
-        RD::drain();
+        });
     }
     __syncthreads();
     // q_c[i-1] = p(-i): lane slot (tap i) -> LDS and global
