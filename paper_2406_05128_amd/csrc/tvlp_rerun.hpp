@@ -160,11 +160,13 @@ struct RowRing {
 // U + D rows.  my_len: the lane's chunk rows (0 if inactive).
 template <class RR, int G, int CPW>
 __device__ __forceinline__ int fast_steps(int64_t my_len) {
+    // a multiple of NS and of G (the unclamped steps end on a G-step boundary)
+    constexpr int Q = RR::NS % G == 0 ? RR::NS : (G % RR::NS == 0 ? G : RR::NS * G);
     int mn = 0x7fffffff;
 #pragma unroll
     for (int k = 0; k < CPW; ++k) mn = min(mn, __builtin_amdgcn_readlane((int)my_len, k * G));
     const int u = mn - RR::D;
-    return u > 0 ? u / RR::NS * RR::NS : 0;
+    return u > 0 ? u / Q * Q : 0;
 }
 
 // Drives steps u = 0 .. L-1 of a ring loop whose D-row prologue has been
@@ -240,6 +242,7 @@ __global__ __launch_bounds__(64) void k_fwd_rerun2(Seqs S, const float *__restri
     double av[TPL], ex;
     RR::load(ring, 0, ln, av, ex);
     float *so = s + base;
+    float yk = 0.f;  // unclamped steps: lane r keeps y of the steps u = r (mod G)
     ring_loop(rr, ring, L, fast_steps<RR, G, CPW>(len), [&](int u, auto ks, auto fast) {
         double nav[TPL], nex;
         RR::load(ring, ks, ln, nav, nex);
@@ -250,7 +253,10 @@ __global__ __launch_bounds__(64) void k_fwd_rerun2(Seqs S, const float *__restri
         const double y = ex - tot;
         const double up = dpp_f64<DPP_ROW_SHR1>(hist[TPL - 1]);
         if constexpr (decltype(fast)::value) {
-            so[u] = (float)y;
+            // one store of G consecutive outputs per chunk every G steps
+            const int uk = u & (G - 1);
+            yk = (r == uk) ? (float)y : yk;
+            if (uk == G - 1) so[u - (G - 1) + r] = yk;
 #pragma unroll
             for (int m = TPL - 1; m > 0; --m) hist[m] = hist[m - 1];
             hist[0] = (r == 0) ? y : up;
@@ -427,10 +433,30 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
             for (int t = lane; t < kl; t += 64) ge[kb + t] = gk[t];
         if (ga) {
             float *gak = ga + kb * M;
-            const int n = kl * M;
-            for (int f = lane; f < n; f += 64) {
-                const int t = f / M, i = f - t * M;
-                gak[f] = -gk[t] * sk[M + t - 1 - i];
+            if (M % 2 == 0 && (reinterpret_cast<uintptr_t>(ga) & 7) == 0) {
+                // pairs of taps (i, i+1) of one row per lane, float2 stores (8-byte aligned: M even)
+                constexpr int SQ = 128 / M, SR = 128 % M;  // lane stride of 64 pairs in rows and taps
+                const int n2 = kl * (M / 2);
+                int t = (2 * lane) / M, i = 2 * lane - t * M;
+                for (int j = lane; j < n2; j += 64) {
+                    const float gt = -gk[t];
+                    float2 v;
+                    v.x = gt * sk[M + t - 1 - i];
+                    v.y = gt * sk[M + t - 2 - i];
+                    *reinterpret_cast<float2 *>(gak + 2 * j) = v;
+                    t += SQ;
+                    i += SR;
+                    if (i >= M) {
+                        i -= M;
+                        ++t;
+                    }
+                }
+            } else {
+                const int n = kl * M;
+                for (int f = lane; f < n; f += 64) {
+                    const int t = f / M, i = f - t * M;
+                    gak[f] = -gk[t] * sk[M + t - 1 - i];
+                }
             }
         }
     }
