@@ -138,11 +138,12 @@ constexpr size_t kStatusOffset = 256;  // byte offset of the scan status word in
 
 // Workspace layout for one call with nch chunks and n samples over B sequences.
 struct WsLayout {
-    size_t zero, xs, phi, yend, q, cbase, gbf, gbb, aggf, inclf, aggb, inclb, status, total;
+    size_t zero, xs, phi, yend, q, cbase, gbf, gbb, aggf, inclf, aggb, inclb, sbuf, status, total;
 };
 
-// ngf / ngb: group slots of the forward / adjoint scans.
-WsLayout ws_layout(int M, int64_t nch, int64_t B, int64_t ngf, int64_t ngb) {
+// ngf / ngb: group slots of the forward / adjoint scans; nsamp: sample slots
+// of the sequence layout (B*T, or N), for s recomputed by the adjoint.
+WsLayout ws_layout(int M, int64_t nch, int64_t B, int64_t ngf, int64_t ngb, int64_t nsamp) {
     WsLayout w{};
     size_t off = 0;
     const size_t agg = (size_t)(M * M + M) * sizeof(double);
@@ -159,6 +160,7 @@ WsLayout ws_layout(int M, int64_t nch, int64_t B, int64_t ngf, int64_t ngb) {
     w.inclf = off; off += align_up((size_t)ngf * M * sizeof(double));
     w.aggb = off;  off += align_up((size_t)ngb * agg);
     w.inclb = off; off += align_up((size_t)ngb * M * sizeof(double));
+    w.sbuf = off;  off += align_up((size_t)nsamp * sizeof(float));
     w.total = off;
     return w;
 }
@@ -330,6 +332,7 @@ struct Ops {
         double *aggf, *inclf, *aggb, *inclb;  // group maps and group carries
         int *status;
         const float *zero;  // 64 floats of 0 in device memory
+        float *sbuf;        // s recomputed by the adjoint (one float per sample slot)
         int chain;  // chained carry: no matrix products between chunk transitions
     };
 
@@ -357,9 +360,19 @@ struct Ops {
     static void backward(const Bufs &w, const float *g, const float *a, const float *e, const float *s_in,
                          float *ge, float *ga, double *gzi, hipStream_t st, Timer &tm) {
         if (w.nch <= 0) return;
+        // without a stored s the emit kernel reads s recomputed alongside the local scan
+        const bool emit = ge || ga;
+        const float *s_use = s_in ? s_in : w.sbuf;
         tm.begin("bwd_scan");
-        hipLaunchKernelGGL((k_bwd_local<M, RS::G, RS::R>), dim3((unsigned)w.gb.ngroups), dim3(64), 0, st, w.S,
-                           w.gb, g, a, w.phiT, w.qbuf, w.aggb, w.zero, w.chain);
+        if (emit && !s_in) {
+            const int64_t nrun = ceil_div(w.nch, RS::CPW);
+            hipLaunchKernelGGL((k_bwd_front<M, RS::G, RS::R>), dim3((unsigned)(w.gb.ngroups + nrun)), dim3(64), 0,
+                               st, w.S, w.gb, g, a, w.phiT, w.qbuf, w.aggb, w.zero, w.chain, e, w.xs, w.sbuf,
+                               w.nch);
+        } else {
+            hipLaunchKernelGGL((k_bwd_local<M, RS::G, RS::R>), dim3((unsigned)w.gb.ngroups), dim3(64), 0, st, w.S,
+                               w.gb, g, a, w.phiT, w.qbuf, w.aggb, w.zero, w.chain);
+        }
         tm.end();
         tm.begin("bwd_carry");
         const dim3 ct(CarryShape<M>::THREADS);
@@ -369,16 +382,12 @@ struct Ops {
             hipLaunchKernelGGL((k_bwd_expand<M, RS::CPW>), dim3((unsigned)w.gb.ngroups), ct, 0, st, w.S, w.gb, w.phiT,
                                w.qbuf, w.inclb, w.yend, gzi);
         tm.end();
-        if (ge || ga) {
+        if (emit) {
             const unsigned grid = (unsigned)ceil_div(w.nch, RS::CPW);
             const size_t dyn = emit_lds_bytes(w.S.L);
             tm.begin("bwd_emit");
-            if (s_in)
-                hipLaunchKernelGGL((k_adj_emit2<M, RS::G, true>), dim3(grid), dim3(64), dyn, st, w.S, g, a, e, s_in,
-                                   w.xs, w.yend, ge, ga, w.zero, w.nch);
-            else
-                hipLaunchKernelGGL((k_adj_emit2<M, RS::G, false>), dim3(grid), dim3(64), dyn, st, w.S, g, a, e,
-                                   s_in, w.xs, w.yend, ge, ga, w.zero, w.nch);
+            hipLaunchKernelGGL((k_adj_emit2<M, RS::G, true>), dim3(grid), dim3(64), dyn, st, w.S, g, a, e, s_use,
+                               w.xs, w.yend, ge, ga, w.zero, w.nch);
             tm.end();
         }
     }
@@ -475,7 +484,7 @@ int prepare(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, const
         ngf = B * ceil_div(C, cpwf);
         ngb = B * ceil_div(C, cpwb);
     }
-    WsLayout lay = ws_layout(M, nch, B, ngf, ngb);
+    WsLayout lay = ws_layout(M, nch, B, ngf, ngb, tabled ? T_or_N : B * T_or_N);
     if (int r = ensure_ws(p, lay.total, st)) return r;
     char *ws = (char *)p->ws;
     w.nch = nch;
@@ -511,6 +520,7 @@ int prepare(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, const
     w.inclb = (double *)(ws + lay.inclb);
     w.status = (int *)(ws + lay.status);
     w.zero = (const float *)(ws + lay.zero);
+    w.sbuf = (float *)(ws + lay.sbuf);
     w.chain = (p->flags & LP_FLAG_CHAINED_CARRY) ? 1 : 0;
     return LP_OK;
 }
@@ -691,7 +701,7 @@ int lp_plan_reserve(lp_plan *p, int64_t B, int64_t T) {
     DeviceGuard dg(p->device);
     const int64_t nch = uniform_nchunks(B, T, p->L) + B;
     const int cf = scan_cpw(p->M, true), cb = scan_cpw(p->M, false);
-    WsLayout w = ws_layout(p->M, nch, B, ceil_div(nch, cf) + B, ceil_div(nch, cb) + B);
+    WsLayout w = ws_layout(p->M, nch, B, ceil_div(nch, cf) + B, ceil_div(nch, cb) + B, B * T);
     return ensure_ws(p, w.total, nullptr);
 }
 

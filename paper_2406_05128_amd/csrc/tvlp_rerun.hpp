@@ -200,20 +200,25 @@ __device__ __forceinline__ void ring_loop(RR &rr, float *ring, int L, int U, Bod
 
 // Forward rerun of each chunk from its saved entry state: writes s and, for a
 // sequence's last chunk, zf.  Also recomputes s for the adjoint.
+// One wave (block `blk`) reruns chunks blk*CPW .. blk*CPW+CPW-1; `ring`: LDS
+// of RerunLds<M, G>::BYTES bytes.
 template <int M, int G>
-__global__ __launch_bounds__(64) void k_fwd_rerun2(Seqs S, const float *__restrict__ e,
-                                                   const float *__restrict__ a,
-                                                   const double *__restrict__ xs,
-                                                   float *__restrict__ s, double *__restrict__ zf,
-                                                   const float *__restrict__ zero, int64_t nch) {
+struct RerunLds {
+    static constexpr int BYTES = RowRing<M, 64 / G, false>::FLOATS * 4;
+};
+
+template <int M, int G>
+__device__ __forceinline__ void rerun_chunks(Seqs S, const float *__restrict__ e, const float *__restrict__ a,
+                                             const double *__restrict__ xs, float *__restrict__ s,
+                                             double *__restrict__ zf, const float *__restrict__ zero,
+                                             int64_t nch, int64_t blk, float *ring) {
     constexpr int CPW = 64 / G;
     constexpr int TPL = (M + G - 1) / G;
     using RR = RowRing<M, CPW, false>;
-    __shared__ __attribute__((aligned(16))) float ring[RR::FLOATS];
 
     const int lane = threadIdx.x;
     const int slot = lane / G, r = lane % G;
-    const int64_t gc = (int64_t)blockIdx.x * CPW + slot;
+    const int64_t gc = blk * CPW + slot;
     bool active = gc < nch;
     int64_t b = 0, c = 0, len = 0, base = 0;
     if (active) {
@@ -281,6 +286,16 @@ __global__ __launch_bounds__(64) void k_fwd_rerun2(Seqs S, const float *__restri
             }
         }
     }
+}
+
+template <int M, int G>
+__global__ __launch_bounds__(64) void k_fwd_rerun2(Seqs S, const float *__restrict__ e,
+                                                   const float *__restrict__ a,
+                                                   const double *__restrict__ xs,
+                                                   float *__restrict__ s, double *__restrict__ zf,
+                                                   const float *__restrict__ zero, int64_t nch) {
+    __shared__ __attribute__((aligned(16))) float ring[RerunLds<M, G>::BYTES / 4];
+    rerun_chunks<M, G>(S, e, a, xs, s, zf, zero, nch, blockIdx.x, ring);
 }
 
 // Adjoint rerun of each chunk (push form of Eq. 12, descending), from the

@@ -344,17 +344,18 @@ struct BwdScanShape {
     static constexpr int LDS_BYTES = RING_BYTES > MAT_BYTES ? RING_BYTES : MAT_BYTES;
 };
 
+// One wave handles adjoint group tid_; lds_raw: SH::LDS_BYTES bytes of LDS.
 template <int M, int G, int R>
-__global__ __launch_bounds__(64) void k_bwd_local(Seqs S, Groups GR, const float *__restrict__ g_in,
-                                                  const float *__restrict__ a, const double *__restrict__ phiT,
-                                                  double *__restrict__ qbuf, double *__restrict__ aggbuf,
-                                                  const float *__restrict__ zero, int chain) {
+__device__ __forceinline__ void bwd_local_group(Seqs S, Groups GR, const float *__restrict__ g_in,
+                                                const float *__restrict__ a, const double *__restrict__ phiT,
+                                                double *__restrict__ qbuf, double *__restrict__ aggbuf,
+                                                const float *__restrict__ zero, int chain, int64_t tid_,
+                                                unsigned char *lds_raw) {
     using SH = BwdScanShape<M, G, R>;
     using RD = typename SH::RD;
     constexpr int CPW = SH::CPW;
     constexpr int TPL = (M + G - 1) / G;
     constexpr int MM = M * M;
-    __shared__ __attribute__((aligned(16))) unsigned char lds_raw[SH::LDS_BYTES];
     float *ring = reinterpret_cast<float *>(lds_raw);
     double *PS = reinterpret_cast<double *>(lds_raw);  // aggregate Psi, row-major
     double *FT = PS + MM;                              // Phi_k^T row-major (= Phi_k column-major)
@@ -366,7 +367,6 @@ __global__ __launch_bounds__(64) void k_bwd_local(Seqs S, Groups GR, const float
     (void)vt;
 
     const int lane = threadIdx.x;
-    const int64_t tid_ = blockIdx.x;
     if (tid_ >= GR.ngroups) return;
     // reverse order inside each sequence (the last group has the lowest index)
     int64_t b, gr;
@@ -492,6 +492,46 @@ __global__ __launch_bounds__(64) void k_bwd_local(Seqs S, Groups GR, const float
         for (int q = lane; q < MM; q += 64) ag[q] = PS[q];
         if (lane < M) ag[MM + lane] = vw[lane];
     }
+}
+
+template <int M, int G, int R>
+__global__ __launch_bounds__(64) void k_bwd_local(Seqs S, Groups GR, const float *__restrict__ g_in,
+                                                  const float *__restrict__ a, const double *__restrict__ phiT,
+                                                  double *__restrict__ qbuf, double *__restrict__ aggbuf,
+                                                  const float *__restrict__ zero, int chain) {
+    __shared__ __attribute__((aligned(16))) unsigned char lds_raw[BwdScanShape<M, G, R>::LDS_BYTES];
+    bwd_local_group<M, G, R>(S, GR, g_in, a, phiT, qbuf, aggbuf, zero, chain, blockIdx.x, lds_raw);
+}
+
+// The adjoint's local scan together with the recompute of s from the saved
+// chunk entry states (into s_out), in one launch: neither needs the other, and
+// interleaving their blocks gives every SIMD two independent waves whose
+// latencies overlap.  Blocks alternate (scan, rerun) while both kinds remain.
+template <int M, int G, int R>
+__global__ __launch_bounds__(64) void k_bwd_front(Seqs S, Groups GR, const float *__restrict__ g_in,
+                                                  const float *__restrict__ a, const double *__restrict__ phiT,
+                                                  double *__restrict__ qbuf, double *__restrict__ aggbuf,
+                                                  const float *__restrict__ zero, int chain,
+                                                  const float *__restrict__ e, const double *__restrict__ xs,
+                                                  float *__restrict__ s_out, int64_t nch) {
+    constexpr int B1 = BwdScanShape<M, G, R>::LDS_BYTES, B2 = RerunLds<M, G>::BYTES;
+    __shared__ __attribute__((aligned(16))) unsigned char lds_raw[B1 > B2 ? B1 : B2];
+    const int64_t nscan = GR.ngroups, nrun = (nch + 64 / G - 1) / (64 / G);
+    const int64_t both = nscan < nrun ? nscan : nrun;
+    const int64_t i = blockIdx.x;
+    bool scan;
+    int64_t j;
+    if (i < 2 * both) {
+        scan = (i & 1) == 0;
+        j = i >> 1;
+    } else {
+        scan = nscan > nrun;
+        j = i - both;
+    }
+    if (scan)
+        bwd_local_group<M, G, R>(S, GR, g_in, a, phiT, qbuf, aggbuf, zero, chain, j, lds_raw);
+    else
+        rerun_chunks<M, G>(S, e, a, xs, s_out, nullptr, zero, nch, j, reinterpret_cast<float *>(lds_raw));
 }
 
 }  // namespace tvlp
