@@ -31,9 +31,9 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector, published
 # plain 256 MiB device copy) for the training workload; valid only for the kernel sources
 # (hash below) and chunk length they were measured with, otherwise reported as null.
 TRAFFIC = {
-    "sources_sha256": "c61c02a95b56ce89fa92751b2c2a9de9b3bf6d1765a9e8d17597e430c134ab9d",
+    "sources_sha256": "7099fe4cdaf1eba0119ed8794bb99c6c398b93b8cbcc291dddb2b1650224d9d8",
     "chunk": 506,
-    "bytes": {"fwd_scan": 315116890, "fwd_emit": 297670285, "bwd_scan": 318707246, "bwd_emit": 835413650},
+    "bytes": {"fwd_scan": 311234880, "fwd_emit": 297901203, "bwd_scan": 610774324, "bwd_emit": 581754817},
 }
 
 
@@ -74,8 +74,9 @@ def kernel_bytes(name: str, B: int, T: int, M: int, L: int) -> float:
     table = {
         "fwd_scan": n_full * (4 + row),           # read e, a (transition-carrying chunks)
         "fwd_emit": n * (4 + row + 4),            # read e, a; write s
-        "bwd_scan": n * (4 + row),                # read g, a
-        "bwd_emit": n * (4 + 4 + row + 4 + row),  # read g, e, a; write grad_e, grad_a
+        # adjoint local scan (read g, a) and, in the same launch, s recomputed (read e, a; write s)
+        "bwd_scan": n * (4 + row) + n * (4 + row + 4),
+        "bwd_emit": n * (4 + 4 + row + 4 + row),  # read g, s, a; write grad_e, grad_a
     }
     return float(table.get(name, 0.0))
 
@@ -88,8 +89,8 @@ def kernel_flops(name: str, B: int, T: int, M: int, L: int) -> float:
     table = {
         "fwd_scan": n_full * (M + 1) * 2 * M,  # zero-state + M basis recursions
         "fwd_emit": n * 2 * M,
-        "bwd_scan": n * 2 * M,
-        "bwd_emit": n * (2 * M + 2 * M + M),   # recompute s, adjoint, coefficient gradient
+        "bwd_scan": n * 2 * M + n * 2 * M,     # adjoint local scan + recompute of s
+        "bwd_emit": n * (2 * M + M),           # adjoint, coefficient gradient
     }
     return float(table.get(name, 0.0))
 
