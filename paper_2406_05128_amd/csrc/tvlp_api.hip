@@ -297,11 +297,7 @@ TVLP_FWD_SHAPE(32, 17, 2, 2)
 // Lanes per chunk of the systolic reruns and rows per LDS slab.
 template <int M>
 struct RerunShape {
-#ifdef TVLP_RERUN_G
-    static constexpr int G = TVLP_RERUN_G;
-#else
     static constexpr int G = M >= 8 ? 8 : 4;
-#endif
     static constexpr int R = 16;
     static constexpr int CPW = 64 / G;
 };
@@ -737,9 +733,12 @@ int lp_plan_autotune(lp_plan *p, int64_t B, int64_t T, int reps, int *chosen, do
     DeviceGuard dg(p->device);
     int maxL = 0;
     dispatch(M, [&](auto ops) { maxL = decltype(ops)::max_chunk(); });
+    // candidates about 6 % apart from 64 to 1024 samples, as multiples of M: step
+    // time is not smooth in L (the chunk stride meets the memory interleave
+    // differently at neighbouring lengths), so the grid is dense
     std::vector<int> cands;
-    for (int target : {64, 96, 128, 176, 256, 352, 512, 768, 1024}) {
-        const int L = std::max(1, (target + M / 2) / M) * M;
+    for (double target = 64.0; target <= 1024.0 * 1.001; target *= 1.06) {
+        const int L = std::max(1, (int(target) + M / 2) / M) * M;
         if (L <= maxL && std::find(cands.begin(), cands.end(), L) == cands.end()) cands.push_back(L);
     }
     const int oldL = p->L;

@@ -131,7 +131,10 @@ struct FwdScanShape {
     static constexpr int ROWF = CPW * M + CPW;           // floats per step slot actually used
     static constexpr int DMA_N = (ROWF + 63) / 64;       // dword DMA instructions per step
     static constexpr int D = (63 / DMA_N) < 15 ? (63 / DMA_N) : 15;  // steps in flight (vmcnt <= 63)
-    static constexpr int NS = D + 1;                     // ring slots
+    // ring slots: M when that suffices, so that the slot of row t0 + K in the
+    // M-step unrolled loop (t0 a multiple of M) is the constant K
+    static constexpr int NS = M >= D + 1 ? M : D + 1;
+    static constexpr bool CONST_SLOTS = NS == M;
     static constexpr int RING_BYTES = NS * DMA_N * 64 * 4;
     static constexpr int RM = R * M;
     static constexpr bool VEC2 = (M % 2 == 0);
@@ -191,8 +194,9 @@ __global__ __launch_bounds__(64) void k_fwd_local(
         // which is coefficient (k, f) = (j / M, j % M) for j < CPW*M and the
         // excitation value of chunk j - CPW*M above that.  Rows advance by M floats.
         typedef __attribute__((address_space(1))) const char gchar;
+        // per instruction: base address, byte offset of the next row, row step, last valid offset
         gchar *src[SH::DMA_N];
-        unsigned off[SH::DMA_N], step[SH::DMA_N], lim[SH::DMA_N];  // bytes
+        int off[SH::DMA_N], step[SH::DMA_N], lim[SH::DMA_N];
 #pragma unroll
         for (int i = 0; i < SH::DMA_N; ++i) {
             const int j = 64 * i + lane;
@@ -213,16 +217,17 @@ __global__ __launch_bounds__(64) void k_fwd_local(
             }
             src[i] = (gchar *)p;
             off[i] = 0;
-            step[i] = 4u * (unsigned)st;
-            lim[i] = 4u * (unsigned)st * (unsigned)(L - 1);
+            step[i] = 4 * st;
+            lim[i] = 4 * st * (L - 1);
         }
         float *ring = reinterpret_cast<float *>(lds_raw);
         typedef __attribute__((address_space(3))) float lfloat;
         lfloat *ring_l = (lfloat *)lds_raw;
+        constexpr int SLOTF = SH::DMA_N * 64;  // floats per ring slot
         // Rows are issued in order t = 0, 1, ...; every chunk of the basis pass
         // has exactly L rows, and look-ahead issues past row L-1 repeat that row.
-        auto issue = [&](int t) {  // row min(t, L-1) of every chunk into ring slot t % NS
-            lfloat *dst = ring_l + (t % SH::NS) * (SH::DMA_N * 64);
+        auto issue = [&](int t, int slotn) {  // row min(t, L-1) of every chunk into ring slot slotn
+            lfloat *dst = ring_l + slotn * SLOTF;
 #pragma unroll
             for (int i = 0; i < SH::DMA_N; ++i) {
                 __builtin_amdgcn_global_load_lds((const void *)(src[i] + off[i]), (lds_void *)(dst + 64 * i), 4,
@@ -230,27 +235,45 @@ __global__ __launch_bounds__(64) void k_fwd_local(
                 off[i] = min(off[i] + step[i], lim[i]);
             }
         };
-        // row t's coefficients and excitation, read from the ring during step t-1
-        auto load_row = [&](int t, float (&rv)[M], float &ex) {
-            const float *slotp = ring + (t % SH::NS) * (SH::DMA_N * 64);
+        // unclamped issue (the row lies inside the chunk): src itself walks the
+        // rows, one 64-bit add per instruction
+        auto issue_fast = [&](int slotn) {
+            lfloat *dst = ring_l + slotn * SLOTF;
+#pragma unroll
+            for (int i = 0; i < SH::DMA_N; ++i) {
+                __builtin_amdgcn_global_load_lds((const void *)src[i], (lds_void *)(dst + 64 * i), 4, 0, 0);
+                src[i] += step[i];
+            }
+        };
+        // row t's coefficients and excitation (ring slot slotn), read during step t-1
+        auto load_row = [&](int slotn, float (&rv)[M], float &ex) {
+            const float *slotp = ring + slotn * SLOTF;
             const float *row = slotp + (slot < CPW ? slot : 0) * M;
 #pragma unroll
             for (int i = 0; i < M; ++i) rv[i] = row[i];
             ex = slotp[CPW * M + (slot < CPW ? slot : 0)];
         };
-        for (int t = 0; t < SH::D; ++t) issue(t);
+        for (int t = 0; t < SH::D; ++t) issue(t, t % SH::NS);
         __builtin_amdgcn_s_waitcnt(waitcnt_vm(SH::DMA_N * (SH::D - 1)));  // row 0 has landed
         float rv[M], ex;
         load_row(0, rv, ex);
-        for (int t0 = 0; t0 < L; t0 += M) {
+        // blocks of M steps whose issued rows (up to t0 + M - 1 + D) all lie inside the chunk
+        const int Lfast = SH::CONST_SLOTS && L > SH::D ? (L - SH::D) / M * M : 0;
+        int t0 = 0;
+        auto block = [&](auto fastc) {
+            constexpr bool F = decltype(fastc)::value;
             Unroll<M, 0>::run([&](auto kc) {
                 constexpr int K = decltype(kc)::value;
                 const int t = t0 + K;
                 __builtin_amdgcn_sched_barrier(0);  // no DMA above the previous step's LDS reads
-                issue(t + SH::D);  // overwrites the slot of row t-1, consumed in step t-1
+                // overwrites the slot of row t+D-NS <= t-1, consumed in step t-1
+                if constexpr (F)
+                    issue_fast((K + SH::D) % SH::NS);
+                else
+                    issue(t + SH::D, SH::CONST_SLOTS ? (K + SH::D) % SH::NS : (t + SH::D) % SH::NS);
                 __builtin_amdgcn_s_waitcnt(waitcnt_vm(SH::DMA_N * (SH::D - 1)));  // row t+1 has landed
                 float nrv[M], nex;
-                load_row(t + 1, nrv, nex);
+                load_row(SH::CONST_SLOTS ? (K + 1) % SH::NS : (t + 1) % SH::NS, nrv, nex);
                 double acc[CPL][2];
 #pragma unroll
                 for (int m = 0; m < CPL; ++m) {
@@ -269,7 +292,23 @@ __global__ __launch_bounds__(64) void k_fwd_local(
                 for (int i = 0; i < M; ++i) rv[i] = nrv[i];
                 ex = nex;
             });
+        };
+        if (Lfast > 0) {
+            // src moves to the next row to issue (row D: no clamping happened, L > D)
+#pragma unroll
+            for (int i = 0; i < SH::DMA_N; ++i) {
+                src[i] += off[i];
+                off[i] = 0;
+            }
+            for (; t0 < Lfast; t0 += M) block(std::true_type{});
+            // src is at row Lfast + D (<= L); offsets relative to it, clamped to row L - 1
+#pragma unroll
+            for (int i = 0; i < SH::DMA_N; ++i) {
+                lim[i] = step[i] * (L - 1 - Lfast - SH::D);
+                off[i] = min(0, lim[i]);
+            }
         }
+        for (; t0 < L; t0 += M) block(std::false_type{});
         __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));  // drain the look-ahead before the ring is reused
         // Phi_c column-major to global (column j-1 = response to unit state s(cL-j)),
         // z_c (zero-state response, column 0) alongside
