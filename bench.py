@@ -28,12 +28,15 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector, published
 
 
 # HBM bytes per launch (rocprofv3 FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, factors from a
-# plain 256 MiB device copy) for the training workload; valid only for the kernel sources
-# (hash below) and chunk length they were measured with, otherwise reported as null.
+# plain 256 MiB device copy) for the training workload, per chunk length; valid only for the
+# kernel sources (hash below) they were measured with, otherwise reported as null.
 TRAFFIC = {
-    "sources_sha256": "7099fe4cdaf1eba0119ed8794bb99c6c398b93b8cbcc291dddb2b1650224d9d8",
-    "chunk": 506,
-    "bytes": {"fwd_scan": 311234880, "fwd_emit": 297901203, "bwd_scan": 610774324, "bwd_emit": 581754817},
+    "sources_sha256": "c083fee96996928f1a0ae46f71ff856c5fd81f3f58dd8b05b9e7a73587b8cda6",
+    "bytes_by_chunk": {
+        396: {"fwd_scan": 324841740, "fwd_emit": 298715453, "bwd_scan": 622970957, "bwd_emit": 582624512},
+        418: {"fwd_scan": 320205684, "fwd_emit": 298737720, "bwd_scan": 620976118, "bwd_emit": 582566235},
+        528: {"fwd_scan": 309382265, "fwd_emit": 296562725, "bwd_scan": 605860911, "bwd_emit": 580378799},
+    },
 }
 
 
@@ -51,9 +54,9 @@ def kernel_sources_sha256() -> str:
 
 
 def measured_traffic(kernel: str, chunk: int):
-    if chunk != TRAFFIC["chunk"] or kernel_sources_sha256() != TRAFFIC["sources_sha256"]:
+    if kernel_sources_sha256() != TRAFFIC["sources_sha256"]:
         return None
-    return TRAFFIC["bytes"].get(kernel)
+    return TRAFFIC["bytes_by_chunk"].get(chunk, {}).get(kernel)
 
 
 def log(*a):
