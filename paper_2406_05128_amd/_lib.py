@@ -89,6 +89,10 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                           "(the filter has no non-HIP implementation)")
+    # torch first: its HIP runtime must be the one libtvlp.so binds to.  Loading
+    # the library first would bring in a second HIP runtime, and whichever
+    # initialises second cannot open the device.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

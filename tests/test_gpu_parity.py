@@ -311,3 +311,41 @@ def test_chained_and_grouped_carry_agree(tv):
         out.append((host(s), host(ge), host(ga)))
     for x, y in zip(*out):
         assert per_seq_err(x, y.astype(np.float64)) <= 1e-6
+
+
+@pytest.mark.parametrize("M,L", [(22, 22), (22, 44), (22, 66), (22, 88), (32, 128), (32, 256), (6, 48)])
+def test_unrolled_ring_region_boundaries(tv, M, L):
+    """Chunk lengths around the point where the rerun and scan loops switch from
+    unclamped unrolled steps to clamped ones (none, a few, most steps), with a
+    ragged last chunk and both carry modes."""
+    T = 3 * L + 5
+    e, a, g = inputs(3, T, M, seed=M * 1000 + L)
+    check_all(tv, e, a, g, chunk=L)
+    check_all(tv, e, a, g, chunk=L, chained=True)
+
+
+def test_misaligned_grad_a_matches_aligned(tv):
+    """grad_a written through a pointer that is only 4-byte aligned takes the
+    scalar store path; it must equal the (float2) aligned result bit for bit."""
+    import ctypes
+    from paper_2406_05128_amd import _lib
+    B, T, M = 2, 3000, 22
+    e, a, g = inputs(B, T, M, seed=77)
+    e_d, a_d, g_d = to_dev(e), to_dev(a), to_dev(g)
+    plan = tv.Plan(M, dev(), 264)
+    _, _, saved = plan.forward(e_d, a_d)
+    ge0, ga0, _ = plan.backward(g_d, a_d, e_d, saved)
+    ge1 = torch.empty_like(g_d)
+    raw = torch.empty(B * T * M + 2, dtype=torch.float32, device=dev())
+    ga1 = raw[1:1 + B * T * M]  # data pointer 4 bytes past an aligned allocation
+    assert ga1.data_ptr() % 8 == 4
+    lib = _lib.load()
+    st = torch.cuda.current_stream(dev()).cuda_stream
+    rc = lib.lp_backward(plan._h, B, T, ctypes.c_void_p(g_d.data_ptr()), ctypes.c_void_p(a_d.data_ptr()),
+                         ctypes.c_void_p(e_d.data_ptr()), None, None, ctypes.c_void_p(saved.data_ptr()),
+                         ctypes.c_void_p(ge1.data_ptr()), ctypes.c_void_p(ga1.data_ptr()), None,
+                         ctypes.c_void_p(st))
+    assert rc == 0, lib.lp_last_error()
+    torch.cuda.synchronize()
+    assert torch.equal(ge0, ge1)
+    assert torch.equal(ga0.reshape(-1), ga1)
