@@ -382,7 +382,7 @@ struct Ops {
             const unsigned grid = (unsigned)ceil_div(w.nch, RS::CPW);
             const size_t dyn = emit_lds_bytes(w.S.L);
             tm.begin("bwd_emit");
-            hipLaunchKernelGGL((k_adj_emit2<M, RS::G, true>), dim3(grid), dim3(64), dyn, st, w.S, g, a, e, s_use,
+            hipLaunchKernelGGL((k_adj_emit2<M, RS::G>), dim3(grid), dim3(64), dyn, st, w.S, g, a, s_use,
                                w.xs, w.yend, ge, ga, w.zero, w.nch);
             tm.end();
         }

@@ -194,124 +194,6 @@ __device__ __forceinline__ void run_forward(const float *__restrict__ e, const f
 // Column 0 is the zero-state response (input e), column j >= 1 the response
 // to the unit state s(cL-j) = 1.  Produces Phi_c[k][j-1] = y_j(L-1-k) and
 // z_c[k] = y_0(L-1-k) (k = 0..M-1) for every chunk except a sequence's last.
-template <int M, int LPC, int CPL>
-__global__ __launch_bounds__(64) void k_fwd_basis(Seqs S, const float *__restrict__ e,
-                                                  const float *__restrict__ a,
-                                                  double *__restrict__ phi,
-                                                  double *__restrict__ zc, int64_t nchunks) {
-    constexpr int CPW = 64 / LPC;
-    const int lane = threadIdx.x;
-    const int slot = lane / LPC;
-    const int sub = lane % LPC;
-    const int64_t gc = (int64_t)blockIdx.x * CPW + slot;
-    const int L = S.L;
-    bool active = slot < CPW && gc < nchunks;
-    int64_t row0 = 0;
-    if (active) {
-        SeqView v = seq_view(S, seq_of_chunk(S, gc));
-        int64_t c = gc - v.cbase;
-        active = c < v.C - 1;  // the last chunk of a sequence needs no transition
-        row0 = v.start + c * L;
-    }
-    double h[CPL][M];
-#pragma unroll
-    for (int m = 0; m < CPL; ++m) {
-        const int col = sub * CPL + m;
-#pragma unroll
-        for (int p = 0; p < M; ++p) h[m][p] = (col >= 1 && p == M - col) ? 1.0 : 0.0;
-    }
-    if (active) {
-        const float *ap = a + row0 * M;
-        const float *ep = e + row0;
-        for (int t0 = 0; t0 < L; t0 += M) {
-            Unroll<M, 0>::run([&](auto kc) {
-                constexpr int K = decltype(kc)::value;
-                const int t = t0 + K;
-                double ad[M];
-                load_row<M>(ap + (int64_t)t * M, ad);
-                const double ein = (sub == 0) ? (double)ep[t] : 0.0;
-#pragma unroll
-                for (int m = 0; m < CPL; ++m) lp_step<M, K>(h[m], ad, m == 0 ? ein : 0.0);
-            });
-        }
-        // L % M == 0, so y(L-1-k) sits at slot M-1-k.
-#pragma unroll
-        for (int m = 0; m < CPL; ++m) {
-            const int col = sub * CPL + m;
-            if (col > M) continue;
-            if (col == 0) {
-#pragma unroll
-                for (int k = 0; k < M; ++k) zc[gc * M + k] = h[m][M - 1 - k];
-            } else {
-#pragma unroll
-                for (int k = 0; k < M; ++k) phi[(gc * M + k) * M + (col - 1)] = h[m][M - 1 - k];
-            }
-        }
-    }
-}
-
-// Carry over chunks, one wave per sequence: x_0 = zi (or 0), x_{c+1} = Phi_c x_c + z_c.
-// Lane k < M owns x[k]; the vector is exchanged through LDS each step.
-template <int M>
-__global__ __launch_bounds__(64) void k_fwd_chain(Seqs S, const double *__restrict__ phi,
-                                                  const double *__restrict__ zc,
-                                                  const double *__restrict__ zi,
-                                                  double *__restrict__ xs) {
-    __shared__ double xsh[M];
-    const int k = threadIdx.x;
-    const int64_t b = blockIdx.x;
-    const SeqView v = seq_view(S, b);
-    if (v.C == 0) return;  // uniform over the block
-    double x = 0.0;
-    if (k < M) {
-        x = zi ? zi[b * M + k] : 0.0;
-        xs[v.cbase * M + k] = x;
-    }
-    for (int64_t c = 0; c + 1 < v.C; ++c) {
-        const int64_t gc = v.cbase + c;
-        if (k < M) xsh[k] = x;
-        __syncthreads();
-        if (k < M) {
-            const double *pr = phi + (gc * M + k) * M;
-            double acc0 = zc[gc * M + k], acc1 = 0.0;
-#pragma unroll
-            for (int j = 0; j < M; ++j) {
-                if (j & 1) acc1 = fma(pr[j], xsh[j], acc1);
-                else       acc0 = fma(pr[j], xsh[j], acc0);
-            }
-            x = acc0 + acc1;
-            xs[(gc + 1) * M + k] = x;
-        }
-        __syncthreads();
-    }
-}
-
-// Emit: rerun every chunk from its entry state, one lane per chunk.
-template <int M>
-__global__ __launch_bounds__(64) void k_fwd_emit(Seqs S, const float *__restrict__ e,
-                                                 const float *__restrict__ a,
-                                                 const double *__restrict__ xs,
-                                                 float *__restrict__ s, double *__restrict__ zf,
-                                                 int64_t nchunks) {
-    const int64_t gc = (int64_t)blockIdx.x * 64 + threadIdx.x;
-    if (gc >= nchunks) return;
-    const int64_t b = seq_of_chunk(S, gc);
-    const SeqView v = seq_view(S, b);
-    const int64_t c = gc - v.cbase;
-    if (c >= v.C) return;
-    const int64_t t0 = c * S.L;
-    const int64_t len = min((int64_t)S.L, v.len - t0);
-    double x[M], xf[M];
-#pragma unroll
-    for (int k = 0; k < M; ++k) x[k] = xs[gc * M + k];
-    const int64_t r0 = v.start + t0;
-    run_forward<M>(e + r0, a + r0 * M, s + r0, len, x, xf);
-    if (zf && c == v.C - 1) {
-#pragma unroll
-        for (int j = 0; j < M; ++j) zf[b * M + j] = xf[j];
-    }
-}
-
 // ---------------------------------------------------------------- adjoint
 
 // Push form of Eq. 12 over one segment, backwards in time.  Pending
@@ -367,111 +249,6 @@ __device__ __forceinline__ void run_adjoint(const float *__restrict__ g, const f
 }
 
 // q_c: zero-terminal adjoint response of each chunk, one lane per chunk.
-template <int M>
-__global__ __launch_bounds__(64) void k_bwd_zs(Seqs S, const float *__restrict__ g,
-                                               const float *__restrict__ a,
-                                               double *__restrict__ q, int64_t nchunks,
-                                               int need_first) {
-    const int64_t gc = (int64_t)blockIdx.x * 64 + threadIdx.x;
-    if (gc >= nchunks) return;
-    const SeqView v = seq_view(S, seq_of_chunk(S, gc));
-    const int64_t c = gc - v.cbase;
-    if (c >= v.C || (c == 0 && !need_first)) return;
-    const int64_t t0 = c * S.L;
-    const int64_t len = min((int64_t)S.L, v.len - t0);
-    const int64_t r0 = v.start + t0;
-    double pin[M], pout[M], sx[M];
-#pragma unroll
-    for (int j = 0; j < M; ++j) { pin[j] = 0.0; sx[j] = 0.0; }
-    run_adjoint<M, false>(g + r0, a + r0 * M, len, pin, pout, nullptr, sx, nullptr, nullptr);
-#pragma unroll
-    for (int j = 0; j < M; ++j) q[gc * M + j] = pout[j];
-}
-
-// Reverse carry, one wave per sequence: y_C = 0, y_c = Phi_c^T y_{c+1} + q_c.
-// Stores yend[gc] = y_{c+1} (the pending vector entering chunk c from the
-// right) and, if requested, grad_zi = y_0.
-template <int M>
-__global__ __launch_bounds__(64) void k_bwd_chain(Seqs S, const double *__restrict__ phi,
-                                                  const double *__restrict__ q,
-                                                  double *__restrict__ yend,
-                                                  double *__restrict__ grad_zi) {
-    __shared__ double ysh[M];
-    const int j = threadIdx.x;
-    const int64_t b = blockIdx.x;
-    const SeqView v = seq_view(S, b);
-    if (v.C == 0) {
-        if (grad_zi && j < M) grad_zi[b * M + j] = 0.0;
-        return;
-    }
-    double y = 0.0;
-    for (int64_t c = v.C - 1; c >= 0; --c) {
-        const int64_t gc = v.cbase + c;
-        if (j < M) yend[gc * M + j] = y;
-        if (c == 0 && !grad_zi) break;
-        if (j < M) ysh[j] = y;
-        __syncthreads();
-        if (j < M) {
-            double acc0 = q[gc * M + j], acc1 = 0.0;
-            if (c + 1 < v.C) {
-#pragma unroll
-                for (int k = 0; k < M; ++k) {
-                    const double pk = phi[(gc * M + k) * M + j];
-                    if (k & 1) acc1 = fma(pk, ysh[k], acc1);
-                    else       acc0 = fma(pk, ysh[k], acc0);
-                }
-            }
-            y = acc0 + acc1;
-        }
-        __syncthreads();
-    }
-    if (grad_zi && j < M) grad_zi[b * M + j] = y;
-}
-
-// Recompute s chunk by chunk from the saved entry states (into sbuf).
-template <int M>
-__global__ __launch_bounds__(64) void k_recompute_s(Seqs S, const float *__restrict__ e,
-                                                    const float *__restrict__ a,
-                                                    const double *__restrict__ xs,
-                                                    float *__restrict__ sbuf, int64_t nchunks) {
-    const int64_t gc = (int64_t)blockIdx.x * 64 + threadIdx.x;
-    if (gc >= nchunks) return;
-    const SeqView v = seq_view(S, seq_of_chunk(S, gc));
-    const int64_t c = gc - v.cbase;
-    if (c >= v.C) return;
-    const int64_t t0 = c * S.L;
-    const int64_t len = min((int64_t)S.L, v.len - t0);
-    double x[M], xf[M];
-#pragma unroll
-    for (int k = 0; k < M; ++k) x[k] = xs[gc * M + k];
-    const int64_t r0 = v.start + t0;
-    run_forward<M>(e + r0, a + r0 * M, sbuf + r0, len, x, xf);
-}
-
-// Emit the adjoint: rerun each chunk's push recursion from yend, one lane per chunk.
-template <int M, bool GA>
-__global__ __launch_bounds__(64) void k_bwd_emit(Seqs S, const float *__restrict__ g,
-                                                 const float *__restrict__ a,
-                                                 const float *__restrict__ s,
-                                                 const double *__restrict__ xs,
-                                                 const double *__restrict__ yend,
-                                                 float *__restrict__ ge, float *__restrict__ ga,
-                                                 int64_t nchunks) {
-    const int64_t gc = (int64_t)blockIdx.x * 64 + threadIdx.x;
-    if (gc >= nchunks) return;
-    const SeqView v = seq_view(S, seq_of_chunk(S, gc));
-    const int64_t c = gc - v.cbase;
-    if (c >= v.C) return;
-    const int64_t t0 = c * S.L;
-    const int64_t len = min((int64_t)S.L, v.len - t0);
-    const int64_t r0 = v.start + t0;
-    double pin[M], pout[M], sx[M];
-#pragma unroll
-    for (int j = 0; j < M; ++j) { pin[j] = yend[gc * M + j]; sx[j] = xs[gc * M + j]; }
-    run_adjoint<M, GA>(g + r0, a + r0 * M, len, pin, pout, GA ? s + r0 : nullptr, sx,
-                       ge ? ge + r0 : nullptr, GA ? ga + r0 * M : nullptr);
-}
-
 // ---------------------------------------------------------------- sequential baseline
 
 template <int M>

@@ -300,27 +300,25 @@ __global__ __launch_bounds__(64) void k_fwd_rerun2(Seqs S, const float *__restri
 
 // Adjoint rerun of each chunk (push form of Eq. 12, descending), from the
 // carried pending vector yend[gc] (p(len-1-j) = yend[j]); writes ghat and
-// -ghat(t) s(t-i) (Eq. 13).  s of the chunk comes from `s_in` (stored) or is
-// recomputed from the saved entry state xs into LDS by an ascending pass
-// first.  The descending pass only leaves ghat in LDS; both gradients are then
-// written by all lanes of the wave with coalesced stores.
+// -ghat(t) s(t-i) (Eq. 13).  s of the chunk is read from `s_in` (the stored
+// output, or s rerun from the saved entry states by the adjoint's front launch)
+// and its M predecessors from the saved entry state xs.  The descending pass
+// only leaves ghat in LDS; both gradients are then written by all lanes of the
+// wave with coalesced stores.
 //
 // Dynamic LDS: [CPW][M + L] floats of s (ssh[M + t] = s(t), ssh[M-1-k] =
 // s(-1-k)) followed by [CPW][L] floats of ghat.
-template <int M, int G, bool STORED_S>
+template <int M, int G>
 __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restrict__ g,
-                                                  const float *__restrict__ a, const float *__restrict__ e,
-                                                  const float *__restrict__ s_in,
+                                                  const float *__restrict__ a, const float *__restrict__ s_in,
                                                   const double *__restrict__ xs,
                                                   const double *__restrict__ yend,
                                                   float *__restrict__ ge, float *__restrict__ ga,
                                                   const float *__restrict__ zero, int64_t nch) {
     constexpr int CPW = 64 / G;
     constexpr int TPL = (M + G - 1) / G;
-    using RA = RowRing<M, CPW, false>;
     using RD = RowRing<M, CPW, true>;
-    static_assert(RA::FLOATS == RD::FLOATS, "ring sizes");
-    __shared__ __attribute__((aligned(16))) float ring[RA::FLOATS];
+    __shared__ __attribute__((aligned(16))) float ring[RD::FLOATS];
     extern __shared__ float ssh_dyn[];
 
     const int lane = threadIdx.x;
@@ -343,50 +341,10 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
     float *ssh = ssh_dyn + slot * (M + L);
     float *gsh_all = ssh_dyn + CPW * (M + L);
     float *gsh = gsh_all + slot * L;
-    const typename RA::template Lanes<TPL> ln(slot, r);
-    const int U = fast_steps<RA, G, CPW>(len);
+    const typename RD::template Lanes<TPL> ln(slot, r);
+    const int U = fast_steps<RD, G, CPW>(len);
     for (int k = r; k < M; k += G) ssh[M - 1 - k] = active ? (float)xs[gc * M + k] : 0.f;
-    if constexpr (STORED_S) {
-        for (int t = r; t < L; t += G) ssh[M + t] = (active && t < len) ? s_in[base + t] : 0.f;
-    } else {
-        double hist[TPL];
-#pragma unroll
-        for (int m = 0; m < TPL; ++m) {
-            const int k = r * TPL + m;
-            hist[m] = (active && k < M) ? xs[gc * M + k] : 0.0;
-        }
-        RA ra;
-        ra.init(a, e, zero, lane, base, len, G);
-        for (int u = 0; u < RA::D; ++u) ra.issue(ring, u);
-        RA::wait_next();  // row 0
-        double av[TPL], ex;
-        RA::load(ring, 0, ln, av, ex);
-        float *sw = ssh + M;
-        ring_loop(ra, ring, L, U, [&](int u, auto ks, auto fast) {
-            double nav[TPL], nex;
-            RA::load(ring, ks, ln, nav, nex);
-            double part = 0.0;
-#pragma unroll
-            for (int m = 0; m < TPL; ++m) part = fma(av[m], hist[m], part);
-            const double tot = group_sum<G>(part);
-            const double y = ex - tot;
-            const double up = dpp_f64<DPP_ROW_SHR1>(hist[TPL - 1]);
-            if (r == 0) sw[u] = (float)y;  // entries at u >= len are never read
-            if constexpr (decltype(fast)::value) {
-#pragma unroll
-                for (int m = TPL - 1; m > 0; --m) hist[m] = hist[m - 1];
-                hist[0] = (r == 0) ? y : up;
-            } else {
-                const bool live = u < len;
-#pragma unroll
-                for (int m = TPL - 1; m > 0; --m) hist[m] = live ? hist[m - 1] : hist[m];
-                hist[0] = live ? ((r == 0) ? y : up) : hist[0];
-            }
-#pragma unroll
-            for (int m = 0; m < TPL; ++m) av[m] = nav[m];
-            ex = nex;
-        });
-    }
+    for (int t = r; t < L; t += G) ssh[M + t] = (active && t < len) ? s_in[base + t] : 0.f;
     __syncthreads();
 
     // ---- descending adjoint pass
