@@ -31,11 +31,12 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector, published
 # plain 256 MiB device copy) for the training workload, per chunk length; valid only for the
 # kernel sources (hash below) they were measured with, otherwise reported as null.
 TRAFFIC = {
-    "sources_sha256": "c083fee96996928f1a0ae46f71ff856c5fd81f3f58dd8b05b9e7a73587b8cda6",
+    "sources_sha256": "3976a13ded95666247ff86f5722a647f334f9157a9a5e3c5686acc1a610cee5d",
     "bytes_by_chunk": {
-        396: {"fwd_scan": 324841740, "fwd_emit": 298715453, "bwd_scan": 622970957, "bwd_emit": 582624512},
-        418: {"fwd_scan": 320205684, "fwd_emit": 298737720, "bwd_scan": 620976118, "bwd_emit": 582566235},
-        528: {"fwd_scan": 309382265, "fwd_emit": 296562725, "bwd_scan": 605860911, "bwd_emit": 580378799},
+        396: {"fwd_scan": 324476935, "fwd_emit": 298696819, "bwd_scan": 622981753, "bwd_emit": 582609963},
+        418: {"fwd_scan": 320100974, "fwd_emit": 298726447, "bwd_scan": 621068486, "bwd_emit": 582554600},
+        506: {"fwd_scan": 311526080, "fwd_emit": 297890535, "bwd_scan": 610846377, "bwd_emit": 581742878},
+        528: {"fwd_scan": 309513037, "fwd_emit": 296560274, "bwd_scan": 605864684, "bwd_emit": 580364104},
     },
 }
 
