@@ -147,6 +147,24 @@ int lp_backward(lp_plan *p, int64_t B, int64_t T,
                 const float *s, const void *saved,
                 float *grad_e, float *grad_a, double *grad_zi, void *stream);
 
+/*
+ * Time-invariant coefficients (the all-pole filter of Sec. 2.2, Eqs. 2-4, with
+ * one coefficient row per sequence): the same chunked forward and adjoint, with
+ * a [B,M] (row b used at every sample of sequence b) instead of [B,T,M].
+ * Everything else as for lp_forward / lp_backward: the saved buffer, zi, zf,
+ * stored or recomputed s, grad_e [B,T], grad_zi [B,M].  grad_a is [B,M]:
+ * dL/da_i = -sum_t ghat(t) s(t-i) (Eq. 4, from the single backward filter of
+ * Sec. 3.2), accumulated per chunk in float64 and summed per sequence.
+ * Uniform batches only.  Error behaviour as for lp_forward / lp_backward.
+ */
+int lp_forward_ti(lp_plan *p, int64_t B, int64_t T,
+                  const float *e, const float *a, const double *zi,
+                  float *s, double *zf, void *saved, void *stream);
+int lp_backward_ti(lp_plan *p, int64_t B, int64_t T,
+                   const float *g, const float *a, const float *e,
+                   const double *zi, const float *s, const void *saved,
+                   float *grad_e, float *grad_a, double *grad_zi, void *stream);
+
 /* Variable-length batches: sequence b occupies samples [offsets[b], offsets[b+1])
  * of the packed arrays e [N], a [N,M], s [N] (N = offsets[B]).  `offsets` is a
  * device array; `N` must equal offsets[B].  Chunk boundaries are relative to

@@ -110,6 +110,26 @@ def lp_backward(g: np.ndarray, a: np.ndarray, s: np.ndarray, zi: Optional[np.nda
     return ge, ga, gz
 
 
+def lp_forward_ti(e: np.ndarray, a: np.ndarray, zi: Optional[np.ndarray] = None):
+    """Time-invariant filter (Sec. 2.2, Eq. 2): one coefficient row a [B,M] used at
+    every sample, i.e. Eq. 6 with a_i(t) = a_i.  Returns (s, zf) as lp_forward."""
+    B, M = a.shape
+    T = e.shape[1]
+    return lp_forward(e, np.broadcast_to(_f64(a)[:, None, :], (B, T, M)), zi)
+
+
+def lp_backward_ti(g: np.ndarray, a: np.ndarray, s: np.ndarray, zi: Optional[np.ndarray] = None,
+                   need_grad_zi: bool = False):
+    """Adjoint of lp_forward_ti: grad_e and grad_zi as lp_backward; the coefficient
+    gradient is dL/da_i = sum_t dL/da_i(t) (the row is shared by every sample;
+    Eq. 4).  Returns (grad_e [B,T], grad_a [B,M], grad_zi [B,M] or None)."""
+    B, M = a.shape
+    T = g.shape[1]
+    ge, ga, gz = lp_backward(g, np.broadcast_to(_f64(a)[:, None, :], (B, T, M)), s, zi,
+                             need_grad_zi=need_grad_zi)
+    return ge, ga.sum(axis=1), gz
+
+
 def lp_forward_varlen(e: np.ndarray, a: np.ndarray, offsets: np.ndarray):
     """Packed variable-length batch: sequence b spans [offsets[b], offsets[b+1])."""
     s = np.empty(e.shape, np.float64)

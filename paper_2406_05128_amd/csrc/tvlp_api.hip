@@ -382,8 +382,13 @@ struct Ops {
             const unsigned grid = (unsigned)ceil_div(w.nch, RS::CPW);
             const size_t dyn = emit_lds_bytes(w.S.L);
             tm.begin("bwd_emit");
+            // time-invariant coefficients: per-chunk shares of dL/da (in the q buffer, free
+            // once the carry has run) instead of per-sample rows, then a sum per sequence
+            const bool ti = w.S.ti && ga;
             hipLaunchKernelGGL((k_adj_emit2<M, RS::G>), dim3(grid), dim3(64), dyn, st, w.S, g, a, s_use,
-                               w.xs, w.yend, ge, ga, w.zero, w.nch);
+                               w.xs, w.yend, ge, w.S.ti ? nullptr : ga, ti ? w.qbuf : nullptr, w.zero, w.nch);
+            if (ti)
+                hipLaunchKernelGGL((k_ti_reduce<M>), dim3((unsigned)w.S.n), dim3(64), 0, st, w.S, w.qbuf, ga);
             tm.end();
         }
     }
@@ -524,7 +529,8 @@ int prepare(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, const
 // Common driver of the uniform and varlen forward.
 int forward_impl(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, const float *e, const float *a,
                  const double *zi, float *s, double *zf, void *saved, void *stream,
-                 const int64_t *starts = nullptr, const int64_t *lens = nullptr, int64_t bound = 0) {
+                 const int64_t *starts = nullptr, const int64_t *lens = nullptr, int64_t bound = 0,
+                 bool ti = false) {
     if (int r = check_plan(p)) return r;
     if (B < 1) return fail(LP_EINVAL, "B must be >= 1 (got %lld)", (long long)B);
     if (T_or_N < 1) return fail(LP_EINVAL, "T (or N) must be >= 1 (got %lld)", (long long)T_or_N);
@@ -538,6 +544,7 @@ int forward_impl(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, 
         using O = decltype(ops);
         typename O::Bufs w;
         rc = prepare<O>(p, B, offsets, T_or_N, saved, st, w, starts, lens, bound);
+        w.S.ti = ti ? 1 : 0;
         if (rc == LP_OK) O::forward(w, e, a, zi, s, zf, st, tm);
     });
     if (rc != LP_OK) return rc;
@@ -546,7 +553,7 @@ int forward_impl(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, 
 
 int backward_impl(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, const float *g, const float *a,
                   const float *e, const double *zi, const float *s, const void *saved, float *ge, float *ga,
-                  double *gzi, void *stream, int64_t gshare = 0) {
+                  double *gzi, void *stream, int64_t gshare = 0, bool ti = false) {
     if (int r = check_plan(p)) return r;
     if (B < 1) return fail(LP_EINVAL, "B must be >= 1 (got %lld)", (long long)B);
     if (T_or_N < 1) return fail(LP_EINVAL, "T (or N) must be >= 1 (got %lld)", (long long)T_or_N);
@@ -564,6 +571,7 @@ int backward_impl(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N,
         typename O::Bufs w;
         rc = prepare<O>(p, B, offsets, T_or_N, saved, st, w);
         w.S.gshare = gshare;
+        w.S.ti = ti ? 1 : 0;
         if (rc == LP_OK) O::backward(w, g, a, e, s, ge, ga, gzi, st, tm);
     });
     if (rc != LP_OK) return rc;
@@ -721,6 +729,17 @@ int lp_forward(lp_plan *p, int64_t B, int64_t T, const float *e, const float *a,
 int lp_backward(lp_plan *p, int64_t B, int64_t T, const float *g, const float *a, const float *e, const double *zi,
                 const float *s, const void *saved, float *grad_e, float *grad_a, double *grad_zi, void *stream) {
     return backward_impl(p, B, nullptr, T, g, a, e, zi, s, saved, grad_e, grad_a, grad_zi, stream);
+}
+
+int lp_forward_ti(lp_plan *p, int64_t B, int64_t T, const float *e, const float *a, const double *zi, float *s,
+                  double *zf, void *saved, void *stream) {
+    return forward_impl(p, B, nullptr, T, e, a, zi, s, zf, saved, stream, nullptr, nullptr, 0, true);
+}
+
+int lp_backward_ti(lp_plan *p, int64_t B, int64_t T, const float *g, const float *a, const float *e,
+                   const double *zi, const float *s, const void *saved, float *grad_e, float *grad_a,
+                   double *grad_zi, void *stream) {
+    return backward_impl(p, B, nullptr, T, g, a, e, zi, s, saved, grad_e, grad_a, grad_zi, stream, 0, true);
 }
 
 int lp_plan_autotune(lp_plan *p, int64_t B, int64_t T, int reps, int *chosen, double *best_ms) {

@@ -52,7 +52,16 @@ struct Seqs {
     // uniform batches only: when > 0, sequences b and b + gshare read the same
     // upstream-gradient row (a filter pair sharing dL/dy)
     int64_t gshare;
+    // time-invariant coefficients: one row a[b][0..M-1] per sequence, used at
+    // every sample of sequence b (uniform batches only)
+    int ti;
 };
+
+// Coefficient row (in rows of M floats) of the first sample of a chunk of
+// sequence b starting at element `start`, and whether rows advance per sample.
+__device__ __forceinline__ int64_t coef_row(const Seqs &S, int64_t b, int64_t start) {
+    return S.ti ? b : start;
+}
 
 // Element offset to add to a sequence's own row index when reading the shared
 // upstream-gradient stream (0 unless the batch is a stacked filter pair).

@@ -60,9 +60,12 @@ struct RowRing {
 
     // my_base: element index of row 0 of this lane's chunk; my_len: its rows
     // (0 if the lane's chunk is inactive); G: lanes per chunk; zero: a device
-    // float holding 0; my_xoff: offset added to my_base for the scalar stream x.
+    // float holding 0; my_xoff: offset added to my_base for the scalar stream x;
+    // my_arow: coefficient row of the chunk's row 0, which advances one row per
+    // step unless the coefficients are time-invariant (ti).
     __device__ __forceinline__ void init(const float *a, const float *x, const float *zero, int lane,
-                                         int64_t my_base, int64_t my_len, int G, int64_t my_xoff = 0) {
+                                         int64_t my_base, int64_t my_len, int G, int64_t my_xoff,
+                                         int64_t my_arow, bool ti) {
 #pragma unroll
         for (int i = 0; i < DMA_N; ++i) {
             const int j = 64 * i + lane;
@@ -80,9 +83,10 @@ struct RowRing {
             const int64_t kb = __shfl(my_base, k * G, 64);
             const int64_t kl = __shfl(my_len, k * G, 64);
             const int64_t kx = __shfl(my_xoff, k * G, 64);
+            const int64_t ka = __shfl(my_arow, k * G, 64);
             const bool live = valid && kl > 0;
-            const float *p0 = !live ? zero : (coef ? a + kb * M + f : x + kb + kx);
-            const int st = live ? (coef ? 4 * M : 4) : 0;
+            const float *p0 = !live ? zero : (coef ? a + ka * M + f : x + kb + kx);
+            const int st = live ? (coef ? (ti ? 0 : 4 * M) : 4) : 0;
             base[i] = (gchar *)p0;
             step[i] = st;
             lim[i] = live ? st * (int)(kl - 1) : 0;
@@ -238,7 +242,7 @@ __device__ __forceinline__ void rerun_chunks(Seqs S, const float *__restrict__ e
         hist[m] = (active && k < M) ? xs[gc * M + k] : 0.0;
     }
     RR rr;
-    rr.init(a, e, zero, lane, base, len, G);
+    rr.init(a, e, zero, lane, base, len, G, 0, coef_row(S, b, base), S.ti);
     const typename RR::template Lanes<TPL> ln(slot, r);
     const int L = S.L;
     for (int u = 0; u < RR::D; ++u) rr.issue(ring, u);
@@ -314,6 +318,7 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
                                                   const double *__restrict__ xs,
                                                   const double *__restrict__ yend,
                                                   float *__restrict__ ge, float *__restrict__ ga,
+                                                  double *__restrict__ tipart,
                                                   const float *__restrict__ zero, int64_t nch) {
     constexpr int CPW = 64 / G;
     constexpr int TPL = (M + G - 1) / G;
@@ -326,9 +331,9 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
     const int L = S.L;
     const int64_t gc = (int64_t)blockIdx.x * CPW + slot;
     bool active = gc < nch;
-    int64_t len = 0, base = 0, goff = 0;
+    int64_t len = 0, base = 0, goff = 0, b = 0;
     if (active) {
-        const int64_t b = seq_of_chunk(S, gc);
+        b = seq_of_chunk(S, gc);
         const SeqView v = seq_view(S, b);
         const int64_t c = gc - v.cbase;
         active = c < v.C;
@@ -360,7 +365,7 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
         }
     }
     RD rd;
-    rd.init(a, g, zero, lane, base, len, G, goff);
+    rd.init(a, g, zero, lane, base, len, G, goff, coef_row(S, b, base), S.ti);
     for (int u = 0; u < RD::D; ++u) rd.issue(ring, u);
     RD::wait_next();  // row 0 (sample len - 1)
     double av[TPL], gx;
@@ -395,6 +400,28 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
         gx = ngx;
     });
     __syncthreads();
+
+    // ---- time-invariant coefficients: the chunk's share of dL/da_i = -sum_t ghat(t) s(t-i)
+    if (tipart) {
+        double acc[TPL];
+#pragma unroll
+        for (int m = 0; m < TPL; ++m) acc[m] = 0.0;
+        for (int t = 0; t < (int)len; ++t) {
+            const double gt = (double)gsh[t];
+#pragma unroll
+            for (int m = 0; m < TPL; ++m) {
+                const int i = r * TPL + m;  // tap i + 1
+                acc[m] = fma(-gt, (double)ssh[M + t - 1 - (i < M ? i : 0)], acc[m]);
+            }
+        }
+        if (active) {
+#pragma unroll
+            for (int m = 0; m < TPL; ++m) {
+                const int i = r * TPL + m;
+                if (i < M) tipart[gc * M + i] = acc[m];
+            }
+        }
+    }
 
     // ---- dL/de(t) = ghat(t), dL/da_i(t) = -ghat(t) s(t-i), chunk by chunk with all lanes
     for (int k = 0; k < CPW; ++k) {
@@ -433,6 +460,20 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
             }
         }
     }
+}
+
+// dL/da[b][i] for time-invariant coefficients: the per-chunk shares summed over
+// the chunks of sequence b (float64), one block per sequence.
+template <int M>
+__global__ __launch_bounds__(64) void k_ti_reduce(Seqs S, const double *__restrict__ tipart,
+                                                  float *__restrict__ ga) {
+    const int64_t b = blockIdx.x;
+    const int i = threadIdx.x;
+    if (b >= S.n || i >= M) return;
+    const SeqView v = seq_view(S, b);
+    double sum = 0.0;
+    for (int64_t c = 0; c < v.C; ++c) sum += tipart[(v.cbase + c) * M + i];
+    ga[b * M + i] = (float)sum;
 }
 
 }  // namespace tvlp

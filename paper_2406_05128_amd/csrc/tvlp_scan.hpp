@@ -205,8 +205,8 @@ __global__ __launch_bounds__(64) void k_fwd_local(
             if (j < CPW * M) {
                 const int k = j / M, f = j % M;
                 if (k < nbasis) {
-                    p = a + (v.start + (c0 + k) * L) * M + f;
-                    st = M;
+                    p = a + coef_row(S, b, v.start + (c0 + k) * L) * M + f;
+                    st = S.ti ? 0 : M;
                 }
             } else if (j < SH::ROWF) {
                 const int k = j - CPW * M;
@@ -430,7 +430,7 @@ __device__ __forceinline__ void bwd_local_group(Seqs S, Groups GR, const float *
     for (int m = 0; m < TPL; ++m) P[m] = 0.0;
     {
         RD rd;
-        rd.init(a, g_in, zero, lane, base, len, G, gshare_offset(S, b));
+        rd.init(a, g_in, zero, lane, base, len, G, gshare_offset(S, b), coef_row(S, b, base), S.ti);
         const typename RD::template Lanes<TPL> ln(slot, r);
         for (int u = 0; u < RD::D; ++u) rd.issue(ring, u);
         RD::wait_next();  // row 0 (the chunk's last sample)

@@ -164,6 +164,39 @@ class Plan:
                                           _ptr(saved), _stream(e.device)))
         return s, zf, saved
 
+    def forward_ti(self, e: torch.Tensor, a: torch.Tensor, zi: Optional[torch.Tensor] = None,
+                   want_zf: bool = False, save: bool = True):
+        """Time-invariant coefficients: e [B,T], a [B,M] -> (s, zf or None, saved or None)."""
+        _need(e, "e", torch.float32, 2)
+        _need(a, "a", torch.float32, 2)
+        B, T = e.shape
+        if a.shape != (B, self.M):
+            raise ValueError(f"a must have shape {(B, self.M)}, got {tuple(a.shape)}")
+        if zi is not None:
+            _need(zi, "zi", torch.float64, 2)
+        s = torch.empty_like(e)
+        zf = torch.empty((B, self.M), dtype=torch.float64, device=e.device) if want_zf else None
+        saved = torch.empty(self.saved_bytes(B, T), dtype=torch.uint8, device=e.device) if save else None
+        _lib.check(_lib.load().lp_forward_ti(self._h, B, T, _ptr(e), _ptr(a), _ptr(zi), _ptr(s), _ptr(zf),
+                                             _ptr(saved), _stream(e.device)))
+        return s, zf, saved
+
+    def backward_ti(self, g: torch.Tensor, a: torch.Tensor, e: Optional[torch.Tensor], saved: torch.Tensor,
+                    s: Optional[torch.Tensor] = None, zi: Optional[torch.Tensor] = None,
+                    need_e: bool = True, need_a: bool = True, need_zi: bool = False):
+        """Time-invariant coefficients: returns (grad_e [B,T], grad_a [B,M], grad_zi [B,M])."""
+        _need(g, "g", torch.float32, 2)
+        _need(a, "a", torch.float32, 2)
+        B, T = g.shape
+        if a.shape != (B, self.M):
+            raise ValueError(f"a must have shape {(B, self.M)}, got {tuple(a.shape)}")
+        ge = torch.empty_like(g) if need_e else None
+        ga = torch.empty_like(a) if need_a else None
+        gz = torch.empty((B, self.M), dtype=torch.float64, device=g.device) if need_zi else None
+        _lib.check(_lib.load().lp_backward_ti(self._h, B, T, _ptr(g), _ptr(a), _ptr(e), _ptr(zi), _ptr(s),
+                                              _ptr(saved), _ptr(ge), _ptr(ga), _ptr(gz), _stream(g.device)))
+        return ge, ga, gz
+
     def backward(self, g: torch.Tensor, a: torch.Tensor, e: Optional[torch.Tensor], saved: torch.Tensor,
                  s: Optional[torch.Tensor] = None, zi: Optional[torch.Tensor] = None,
                  need_e: bool = True, need_a: bool = True, need_zi: bool = False):

@@ -369,3 +369,58 @@ def test_misaligned_grad_a_matches_aligned(tv):
     torch.cuda.synchronize()
     assert torch.equal(ge0, ge1)
     assert torch.equal(ga0.reshape(-1), ga1)
+
+
+def _ti_inputs(B, T, M, seed, radius=0.95):
+    from tests.pins import stable_ti_coeffs
+    rng = np.random.default_rng(seed)
+    a = np.stack([stable_ti_coeffs(rng, M, radius) for _ in range(B)]).astype(np.float32)
+    return make_excitation(rng, B, T), a, make_upstream_grad(rng, B, T)
+
+
+@pytest.mark.parametrize("B,T,M,L,with_zi,store_s,chained", [
+    (3, 5000, 22, 264, False, False, False),
+    (2, 3001, 22, 88, True, False, False),
+    (2, 4000, 16, 256, True, True, False),
+    (3, 2500, 32, 128, False, False, True),
+    (4, 777, 6, 48, True, False, False),
+])
+def test_time_invariant_matches_oracle(tv, B, T, M, L, with_zi, store_s, chained):
+    """Time-invariant coefficients a [B,M]: s, grad_e, grad_a [B,M] (summed over
+    time) and grad_zi against the oracle."""
+    e, a, g = _ti_inputs(B, T, M, seed=B * 100 + M)
+    zi = np.random.default_rng(9).standard_normal((B, M)) if with_zi else None
+    s_ref, zf_ref = oracle.lp_forward_ti(e, a, zi)
+    ge_ref, ga_ref, gz_ref = oracle.lp_backward_ti(g, a, s_ref, zi, need_grad_zi=with_zi)
+    plan = tv.Plan(M, dev(), L, chained=chained)
+    e_d, a_d, g_d, zi_d = to_dev(e), to_dev(a), to_dev(g), to_dev(zi)
+    s, zf, saved = plan.forward_ti(e_d, a_d, zi_d, want_zf=True)
+    ge, ga, gz = plan.backward_ti(g_d, a_d, e_d, saved, s=s if store_s else None, zi=zi_d, need_zi=with_zi)
+    plan.check_status()
+    torch.cuda.synchronize()
+    assert per_seq_err(host(s), s_ref) <= TOL
+    assert rms_rel(host(zf), zf_ref) <= TOL
+    assert per_seq_err(host(ge), ge_ref) <= TOL
+    for b in range(B):
+        assert rms_rel(host(ga)[b], ga_ref[b]) <= TOL, b
+    if with_zi:
+        assert rms_rel(host(gz), gz_ref) <= TOL
+
+
+def test_time_invariant_training_shape_sampled(tv):
+    """B=64, T=48000, M=22 with one coefficient row per sequence, recompute adjoint;
+    sampled sequences against the oracle."""
+    B, T, M = 64, 48000, 22
+    e, a, g = _ti_inputs(B, T, M, seed=4242)
+    plan = tv.Plan(M, dev())
+    e_d, a_d, g_d = to_dev(e), to_dev(a), to_dev(g)
+    s, _, saved = plan.forward_ti(e_d, a_d)
+    ge, ga, _ = plan.backward_ti(g_d, a_d, e_d, saved)
+    plan.check_status()
+    torch.cuda.synchronize()
+    for b in (0, 31, 63):
+        s_ref, _ = oracle.lp_forward_ti(e[b:b + 1], a[b:b + 1])
+        ge_ref, ga_ref, _ = oracle.lp_backward_ti(g[b:b + 1], a[b:b + 1], s_ref)
+        assert rms_rel(host(s[b]), s_ref[0]) <= TOL, b
+        assert rms_rel(host(ge[b]), ge_ref[0]) <= TOL, b
+        assert rms_rel(host(ga[b]), ga_ref[0]) <= TOL, b

@@ -91,3 +91,36 @@ def test_planted_mistake_is_caught(name):
         except (AssertionError, ValueError, IndexError, FloatingPointError):
             caught.append(pin.__name__)
     assert caught, f"no pin caught the planted mistake {name}"
+
+
+def test_oracle_time_invariant_entry_points():
+    """lp_forward_ti / lp_backward_ti against scipy.signal.lfilter (Eq. 2) and the
+    time-invariant coefficient gradient of Eq. 4, with a nonzero initial state."""
+    import scipy.signal
+    rng = np.random.default_rng(31)
+    B, T, M = 2, 400, 6
+    a = np.stack([pins.stable_ti_coeffs(rng, M) for _ in range(B)])
+    e = rng.standard_normal((B, T)); g = rng.standard_normal((B, T))
+    zi = rng.standard_normal((B, M))
+    s, zf = oracle.lp_forward_ti(e, a, zi)
+    ge, ga, gz = oracle.lp_backward_ti(g, a, s, zi, need_grad_zi=True)
+    for b in range(B):
+        den = np.concatenate([[1.0], a[b]])
+        # the initial state s(-1..-M) = zi expressed as lfilter's direct-form-II-transposed state
+        zi_lf = scipy.signal.lfiltic([1.0], den, y=zi[b])
+        ref_s, _ = scipy.signal.lfilter([1.0], den, e[b], zi=zi_lf)
+        assert pins.rms_rel(s[b], ref_s) < 1e-12
+        assert pins.rms_rel(zf[b], s[b, ::-1][:M]) < 1e-15
+        # Eq. 4: dL/da_i = sum_t g(t) LP_a(-s(t-i)), the history before t = 0 being zi
+        ext = np.concatenate([zi[b][::-1], s[b]])  # ext[M + t] = s(t), ext[M - 1 - k] = s(-1-k)
+        for i in range(1, M + 1):
+            shifted = -ext[M - i:M - i + T]
+            ref = float(np.dot(g[b], scipy.signal.lfilter([1.0], den, shifted)))
+            assert abs(float(ga[b, i - 1]) - ref) <= 1e-10 * (abs(ref) + 1.0), (b, i)
+    # dL/dzi by central differences of L = <g, s>
+    h = 1e-6
+    for j in range(M):
+        zp = zi.copy(); zp[0, j] += h
+        zm = zi.copy(); zm[0, j] -= h
+        fd = (np.dot(g[0], oracle.lp_forward_ti(e, a, zp)[0][0]) - np.dot(g[0], oracle.lp_forward_ti(e, a, zm)[0][0])) / (2 * h)
+        assert abs(fd - gz[0, j]) <= 1e-6 * (abs(fd) + 1.0)
