@@ -181,6 +181,55 @@ def serve_bench(tv, n_req: int, seed: int, slots: int, budget_gib: float, batch:
     return res
 
 
+def time_invariant_bench(tv, B: int, T: int, M: int, L: int, steps: int, warmup: int):
+    """Training shape with one coefficient row per sequence (a [B,M], Sec. 2.2):
+    forward + recompute adjoint through lp_forward_ti / lp_backward_ti.
+
+    Algorithmic bytes per sample: e, s (forward), g, e, grad_e (adjoint) = 20 B;
+    the coefficient rows and their gradient are B*M floats each.
+    """
+    import numpy as np
+    import torch
+    from synth import make_excitation, make_upstream_grad, reflection_to_lpc
+
+    dev = torch.device("cuda", 0)
+    rng = np.random.default_rng(77)
+    a = np.stack([reflection_to_lpc(rng.uniform(-0.95, 0.95, size=M)) for _ in range(B)]).astype(np.float32)
+    e = torch.from_numpy(make_excitation(rng, B, T)).to(dev)
+    g = torch.from_numpy(make_upstream_grad(rng, B, T)).to(dev)
+    a = torch.from_numpy(a).to(dev)
+    plan = tv.Plan(M, dev, L)
+    plan.reserve(B, T)
+
+    def step():
+        s, _, saved = plan.forward_ti(e, a)
+        return plan.backward_ti(g, a, e, saved)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    plan.set_timing(True)
+    plan.reset_timings()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    kern = {k: round(1e3 * v[0] / max(v[1], 1), 2) for k, v in plan.timings().items()}
+    plan.set_timing(False)
+    plan.check_status()
+    alg = B * T * 20 + 2 * B * M * 4
+    return {"workload": f"time_invariant_b{B}_t{T}_m{M}", "chunk": L, "ms_per_step": round(ms, 4),
+            "samples_per_s": round(B * T / (ms * 1e-3), 1),
+            "step_hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "kernels_us": kern,
+            "note": "coefficient rows read with step 0 by the same chunked kernels; the basis pass still "
+                    "runs per chunk (every chunk of a sequence has the same transition)"}
+
+
 def stress_bench(tv, steps: int):
     """Long high-resonance workload (512 x 240000, M = 32, |k| <= 0.995, gamma 0.995).
 
@@ -251,6 +300,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-stress", action="store_true")
+    ap.add_argument("--no-ti", action="store_true", help="skip the time-invariant coefficient section")
     ap.add_argument("--serve-requests", type=int, default=100)
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-batch", type=int, default=8)
@@ -411,6 +461,13 @@ def main():
         log(f"copy probe: 3 copies of {args.copy_probe_mb} MiB")
         del src, dst
 
+    ti = None
+    if not args.no_ti:
+        log("time-invariant coefficients (a [B,M])")
+        ti = time_invariant_bench(tv, B, T, M, L, args.steps, args.warmup)
+        log(f"time-invariant: {ti['ms_per_step']:.3f} ms/step")
+        torch.cuda.empty_cache()
+
     stress = None
     if not args.no_stress:
         stress = stress_bench(tv, 3)
@@ -436,6 +493,7 @@ def main():
         "cpu_baseline": cpu,
         "serve": serve,
         "stress": stress,
+        "time_invariant": ti,
     }
     print(json.dumps(out), flush=True)
 
