@@ -226,8 +226,9 @@ def time_invariant_bench(tv, B: int, T: int, M: int, L: int, steps: int, warmup:
             "samples_per_s": round(B * T / (ms * 1e-3), 1),
             "step_hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "kernels_us": kern,
-            "note": "coefficient rows read with step 0 by the same chunked kernels; the basis pass still "
-                    "runs per chunk (every chunk of a sequence has the same transition)"}
+            "note": "one transition per sequence (companion-matrix power by repeated squaring), zero-state "
+                    "chunk offsets by a rerun, chained carry; coefficient rows read with step 0 by the same "
+                    "chunked rerun and adjoint kernels"}
 
 
 def stress_bench(tv, steps: int):

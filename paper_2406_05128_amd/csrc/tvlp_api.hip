@@ -335,15 +335,24 @@ struct Ops {
     static void forward(const Bufs &w, const float *e, const float *a, const double *zi, float *s, double *zf,
                         hipStream_t st, Timer &tm) {
         if (w.nch <= 0) return;
+        // time-invariant coefficients: one transition per sequence (a matrix power)
+        // and the chunks' zero-state offsets; the carry then runs chained
+        const int chain = w.S.ti ? 1 : w.chain;
         tm.begin("fwd_scan");
-        hipLaunchKernelGGL((k_fwd_local<M, FS::LPC, FS::CPL, FS::R>), dim3((unsigned)w.gf.ngroups), dim3(64), 0, st,
-                           w.S, w.gf, e, a, w.phiT, w.zbuf, w.aggf, w.chain);
+        if (w.S.ti) {
+            hipLaunchKernelGGL((k_ti_zs<M, RS::G>), dim3((unsigned)ceil_div(w.nch, RS::CPW)), dim3(64), 0, st, w.S, e,
+                               a, w.zbuf, w.zero, w.nch);
+            hipLaunchKernelGGL((k_ti_phi<M>), dim3((unsigned)w.S.n), dim3(256), 0, st, w.S, a, w.phiT);
+        } else {
+            hipLaunchKernelGGL((k_fwd_local<M, FS::LPC, FS::CPL, FS::R>), dim3((unsigned)w.gf.ngroups), dim3(64), 0,
+                               st, w.S, w.gf, e, a, w.phiT, w.zbuf, w.aggf, w.chain);
+        }
         tm.end();
         tm.begin("fwd_carry");
         const dim3 ct(CarryShape<M>::THREADS);
         hipLaunchKernelGGL((k_fwd_chain<M>), dim3((unsigned)w.S.n), ct, 0, st, w.S, w.gf, zi, w.phiT, w.zbuf, w.aggf,
-                           w.inclf, w.xs, w.chain);
-        if (!w.chain)
+                           w.inclf, w.xs, chain);
+        if (!chain)
             hipLaunchKernelGGL((k_fwd_expand<M, FS::CPW>), dim3((unsigned)w.gf.ngroups), ct, 0, st, w.S, w.gf, w.phiT,
                                w.zbuf, w.inclf, w.xs);
         tm.end();

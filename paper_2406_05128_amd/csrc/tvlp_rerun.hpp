@@ -205,7 +205,9 @@ __device__ __forceinline__ void ring_loop(RR &rr, float *ring, int L, int U, Bod
 // Forward rerun of each chunk from its saved entry state: writes s and, for a
 // sequence's last chunk, zf.  Also recomputes s for the adjoint.
 // One wave (block `blk`) reruns chunks blk*CPW .. blk*CPW+CPW-1; `ring`: LDS
-// of RerunLds<M, G>::BYTES bytes.
+// of RerunLds<M, G>::BYTES bytes.  xs == nullptr: from the zero state; s ==
+// nullptr: no output samples; zall: every chunk's final state, zall[c][k] =
+// s(end - 1 - k) (the chunk's zero-state offset z_c when run from zero).
 template <int M, int G>
 struct RerunLds {
     static constexpr int BYTES = RowRing<M, 64 / G, false>::FLOATS * 4;
@@ -215,7 +217,8 @@ template <int M, int G>
 __device__ __forceinline__ void rerun_chunks(Seqs S, const float *__restrict__ e, const float *__restrict__ a,
                                              const double *__restrict__ xs, float *__restrict__ s,
                                              double *__restrict__ zf, const float *__restrict__ zero,
-                                             int64_t nch, int64_t blk, float *ring) {
+                                             int64_t nch, int64_t blk, float *ring,
+                                             double *__restrict__ zall = nullptr) {
     constexpr int CPW = 64 / G;
     constexpr int TPL = (M + G - 1) / G;
     using RR = RowRing<M, CPW, false>;
@@ -239,7 +242,7 @@ __device__ __forceinline__ void rerun_chunks(Seqs S, const float *__restrict__ e
 #pragma unroll
     for (int m = 0; m < TPL; ++m) {
         const int k = r * TPL + m;
-        hist[m] = (active && k < M) ? xs[gc * M + k] : 0.0;
+        hist[m] = (active && k < M && xs) ? xs[gc * M + k] : 0.0;
     }
     RR rr;
     rr.init(a, e, zero, lane, base, len, G, 0, coef_row(S, b, base), S.ti);
@@ -250,7 +253,7 @@ __device__ __forceinline__ void rerun_chunks(Seqs S, const float *__restrict__ e
     // step u's operands are read from LDS during step u-1
     double av[TPL], ex;
     RR::load(ring, 0, ln, av, ex);
-    float *so = s + base;
+    float *so = s ? s + base : nullptr;
     float yk = 0.f;  // unclamped steps: lane r keeps y of the steps u = r (mod G)
     ring_loop(rr, ring, L, fast_steps<RR, G, CPW>(len), [&](int u, auto ks, auto fast) {
         double nav[TPL], nex;
@@ -265,13 +268,13 @@ __device__ __forceinline__ void rerun_chunks(Seqs S, const float *__restrict__ e
             // one store of G consecutive outputs per chunk every G steps
             const int uk = u & (G - 1);
             yk = (r == uk) ? (float)y : yk;
-            if (uk == G - 1) so[u - (G - 1) + r] = yk;
+            if (so && uk == G - 1) so[u - (G - 1) + r] = yk;
 #pragma unroll
             for (int m = TPL - 1; m > 0; --m) hist[m] = hist[m - 1];
             hist[0] = (r == 0) ? y : up;
         } else {
             const bool live = u < len;
-            if (live && r == 0) so[u] = (float)y;
+            if (so && live && r == 0) so[u] = (float)y;
 #pragma unroll
             for (int m = TPL - 1; m > 0; --m) hist[m] = live ? hist[m - 1] : hist[m];
             hist[0] = live ? ((r == 0) ? y : up) : hist[0];
@@ -280,6 +283,13 @@ __device__ __forceinline__ void rerun_chunks(Seqs S, const float *__restrict__ e
         for (int m = 0; m < TPL; ++m) av[m] = nav[m];
         ex = nex;
     });
+    if (zall && active) {
+#pragma unroll
+        for (int m = 0; m < TPL; ++m) {
+            const int k = r * TPL + m;
+            if (k < M) zall[gc * M + k] = hist[m];
+        }
+    }
     if (zf && active) {
         const SeqView v = seq_view(S, b);
         if (c == v.C - 1) {
@@ -474,6 +484,58 @@ __global__ __launch_bounds__(64) void k_ti_reduce(Seqs S, const double *__restri
     double sum = 0.0;
     for (int64_t c = 0; c < v.C; ++c) sum += tipart[(v.cbase + c) * M + i];
     ga[b * M + i] = (float)sum;
+}
+
+// Time-invariant coefficients: every full chunk of sequence b has the same
+// transition, Phi = C^L with C the zero-input step on the state
+// x = [s(t-1) .. s(t-M)] (x'[0] = -sum_i a_i x[i-1], x'[k] = x[k-1]).  One
+// block per sequence computes it by repeated squaring (float64, in LDS) and
+// writes it, column-major, into the slot of every chunk that carries a
+// transition.
+template <int M>
+__global__ __launch_bounds__(256) void k_ti_phi(Seqs S, const float *__restrict__ a, double *__restrict__ phiT) {
+    constexpr int MM = M * M;
+    __shared__ double R[MM], P[MM], Q[MM];  // column-major: X[j * M + k] = X[k][j]
+    const int64_t b = blockIdx.x;
+    if (b >= S.n) return;
+    const SeqView v = seq_view(S, b);
+    const int64_t nt = v.C - 1;  // chunks with a transition
+    if (nt <= 0) return;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    for (int q = tid; q < MM; q += nth) {
+        const int j = q / M, k = q % M;
+        P[q] = (k == 0) ? -(double)a[b * M + j] : (k == j + 1 ? 1.0 : 0.0);
+        R[q] = (k == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    auto mul_into = [&](double *X, const double *Y) {  // X <- X Y
+        for (int q = tid; q < MM; q += nth) {
+            const int j = q / M, k = q % M;
+            double acc = 0.0;
+#pragma unroll 2
+            for (int i = 0; i < M; ++i) acc = fma(X[i * M + k], Y[j * M + i], acc);
+            Q[q] = acc;
+        }
+        __syncthreads();
+        for (int q = tid; q < MM; q += nth) X[q] = Q[q];
+        __syncthreads();
+    };
+    for (int n = S.L; n > 0; n >>= 1) {
+        if (n & 1) mul_into(R, P);
+        if (n > 1) mul_into(P, P);
+    }
+    double *dst = phiT + v.cbase * MM;
+    for (int64_t q = tid; q < nt * MM; q += nth) dst[q] = R[q % MM];
+}
+
+// Zero-state offsets z_c of every chunk (time-invariant forward): the rerun from
+// the zero state, keeping only each chunk's final state.
+template <int M, int G>
+__global__ __launch_bounds__(64) void k_ti_zs(Seqs S, const float *__restrict__ e, const float *__restrict__ a,
+                                              double *__restrict__ zbuf, const float *__restrict__ zero,
+                                              int64_t nch) {
+    __shared__ __attribute__((aligned(16))) float ring[RerunLds<M, G>::BYTES / 4];
+    rerun_chunks<M, G>(S, e, a, nullptr, nullptr, nullptr, zero, nch, blockIdx.x, ring, zbuf);
 }
 
 }  // namespace tvlp
