@@ -130,6 +130,76 @@ def lp_backward_ti(g: np.ndarray, a: np.ndarray, s: np.ndarray, zi: Optional[np.
     return ge, ga.sum(axis=1), gz
 
 
+def framewise_geometry(T: int, hop: int):
+    """Frames of the frame-wise approximation: length W = 4 hop (75 % overlap),
+    frame f starting at sample (f - 3) hop, F = ceil(T / hop) + 3 frames, so that
+    every sample lies in exactly four frames.  Returns (W, F)."""
+    return 4 * hop, -(-T // hop) + 3
+
+
+def hann_periodic(W: int) -> np.ndarray:
+    """w(n) = sin^2(pi n / W), n = 0 .. W-1; at 75 % overlap the shifted copies sum to 2."""
+    n = np.arange(W, dtype=np.float64)
+    return np.sin(np.pi * n / W) ** 2
+
+
+def framewise_forward(e: np.ndarray, af: np.ndarray, hop: int):
+    """Frame-wise approximation of the time-varying filter (Sec. 3.2, the method of
+    the cited frame-wise work): each frame of the excitation is filtered by the
+    time-invariant filter of its own coefficient row (Eq. 2, zero initial state),
+    and the filtered frames are overlap-added through a Hann window, normalised by
+    the window sum (2).  e [B,T], af [B,F,M].  Returns (s [B,T], s_frames [B,F,W])."""
+    e = _f64(e)
+    af = _f64(af)
+    B, T = e.shape
+    W, F = framewise_geometry(T, hop)
+    assert af.shape[:2] == (B, F)
+    M = af.shape[2]
+    w = hann_periodic(W)
+    ef = np.zeros((B, F, W))
+    for f in range(F):
+        t0 = (f - 3) * hop
+        lo, hi = max(t0, 0), min(t0 + W, T)
+        if hi > lo:
+            ef[:, f, lo - t0:hi - t0] = e[:, lo:hi]
+    sf, _ = lp_forward_ti(ef.reshape(B * F, W), af.reshape(B * F, M))
+    sf = sf.reshape(B, F, W)
+    s = np.zeros((B, T))
+    for f in range(F):
+        t0 = (f - 3) * hop
+        lo, hi = max(t0, 0), min(t0 + W, T)
+        if hi > lo:
+            s[:, lo:hi] += 0.5 * w[lo - t0:hi - t0] * sf[:, f, lo - t0:hi - t0]
+    return s, sf
+
+
+def framewise_backward(g: np.ndarray, af: np.ndarray, sf: np.ndarray, hop: int):
+    """Adjoint of framewise_forward: dL/ds_f(n) = w(n) g(t0 + n) / 2 inside the
+    signal, the time-invariant adjoint per frame (Eqs. 3-4), then dL/de(t) = sum
+    over the four frames holding t of dL/de_f.  Returns (grad_e [B,T], grad_af [B,F,M])."""
+    g = _f64(g)
+    af = _f64(af)
+    B, T = g.shape
+    W, F = framewise_geometry(T, hop)
+    M = af.shape[2]
+    w = hann_periodic(W)
+    gf = np.zeros((B, F, W))
+    for f in range(F):
+        t0 = (f - 3) * hop
+        lo, hi = max(t0, 0), min(t0 + W, T)
+        if hi > lo:
+            gf[:, f, lo - t0:hi - t0] = 0.5 * w[lo - t0:hi - t0] * g[:, lo:hi]
+    gef, gaf, _ = lp_backward_ti(gf.reshape(B * F, W), af.reshape(B * F, M), sf.reshape(B * F, W))
+    gef = gef.reshape(B, F, W)
+    ge = np.zeros((B, T))
+    for f in range(F):
+        t0 = (f - 3) * hop
+        lo, hi = max(t0, 0), min(t0 + W, T)
+        if hi > lo:
+            ge[:, lo:hi] += gef[:, f, lo - t0:hi - t0]
+    return ge, gaf.reshape(B, F, M)
+
+
 def lp_forward_varlen(e: np.ndarray, a: np.ndarray, offsets: np.ndarray):
     """Packed variable-length batch: sequence b spans [offsets[b], offsets[b+1])."""
     s = np.empty(e.shape, np.float64)

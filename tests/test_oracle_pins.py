@@ -124,3 +124,46 @@ def test_oracle_time_invariant_entry_points():
         zm = zi.copy(); zm[0, j] -= h
         fd = (np.dot(g[0], oracle.lp_forward_ti(e, a, zp)[0][0]) - np.dot(g[0], oracle.lp_forward_ti(e, a, zm)[0][0])) / (2 * h)
         assert abs(fd - gz[0, j]) <= 1e-6 * (abs(fd) + 1.0)
+
+
+def test_oracle_framewise_approximation():
+    """Frame-wise approximation (time-invariant filter per frame, Hann overlap-add at
+    75 % overlap): an independent per-frame scipy.signal.lfilter computation, the
+    identity filter reconstructing its input, the adjoint identity in e, and
+    central finite differences for the frame coefficients."""
+    import scipy.signal
+    rng = np.random.default_rng(41)
+    B, T, M, hop = 2, 1300, 5, 60
+    W, F = oracle.framewise_geometry(T, hop)
+    af = np.stack([np.stack([pins.stable_ti_coeffs(rng, M) for _ in range(F)]) for _ in range(B)])
+    e = rng.standard_normal((B, T)); g = rng.standard_normal((B, T))
+    s, sf = oracle.framewise_forward(e, af, hop)
+    # independent: lfilter on each frame, window, overlap-add, halve
+    w = 0.5 - 0.5 * np.cos(2 * np.pi * np.arange(W) / W)
+    ref = np.zeros((B, T))
+    for b in range(B):
+        padded = np.concatenate([np.zeros(3 * hop), e[b], np.zeros(W)])
+        out = np.zeros(T + 3 * hop + W)
+        for f in range(F):
+            y = scipy.signal.lfilter([1.0], np.concatenate([[1.0], af[b, f]]), padded[f * hop:f * hop + W])
+            out[f * hop:f * hop + W] += w * y
+        ref[b] = 0.5 * out[3 * hop:3 * hop + T]
+    assert pins.rms_rel(s, ref) < 1e-12
+    # identity filter: the windows sum to 2, so the output is the input
+    s0, sf0 = oracle.framewise_forward(e, np.zeros_like(af), hop)
+    assert np.max(np.abs(s0 - e)) < 1e-12
+    ge0, _ = oracle.framewise_backward(g, np.zeros_like(af), sf0, hop)
+    assert np.max(np.abs(ge0 - g)) < 1e-12
+    # adjoint identity in e: <g, FW(x)> = <FW^T(g), x>
+    ge, gaf = oracle.framewise_backward(g, af, sf, hop)
+    x = rng.standard_normal((B, T))
+    lhs = float(np.sum(g * oracle.framewise_forward(x, af, hop)[0]))
+    rhs = float(np.sum(oracle.framewise_backward(g, af, oracle.framewise_forward(x, af, hop)[1], hop)[0] * x))
+    assert abs(lhs - rhs) <= 1e-10 * (abs(lhs) + 1.0)
+    # finite differences of L = <g, s> for a few frame coefficients
+    h = 1e-6
+    for (b, f, i) in [(0, 3, 0), (1, 10, 4), (0, F - 1, 2), (1, 0, 1)]:
+        ap = af.copy(); ap[b, f, i] += h
+        am = af.copy(); am[b, f, i] -= h
+        fd = (np.sum(g * oracle.framewise_forward(e, ap, hop)[0]) - np.sum(g * oracle.framewise_forward(e, am, hop)[0])) / (2 * h)
+        assert abs(fd - gaf[b, f, i]) <= 1e-6 * (abs(fd) + 1.0), (b, f, i, fd, gaf[b, f, i])
