@@ -165,6 +165,30 @@ int lp_backward_ti(lp_plan *p, int64_t B, int64_t T,
                    const double *zi, const float *s, const void *saved,
                    float *grad_e, float *grad_a, double *grad_zi, void *stream);
 
+/*
+ * Frame-wise approximation (the comparator of Sec. 3.2: time-invariant filtering
+ * of short overlapping frames, overlap-added; 75 % overlap as in Sec. 5).  Frames
+ * have length W = 4 hop; frame f of a sequence starts at sample (f - 3) hop and
+ * there are F = lp_frames_count(T, hop) = ceil(T / hop) + 3 of them, so every
+ * sample lies in exactly four frames.  With weighting on, a frame value at
+ * position n is multiplied by w(n) / 2, w the periodic Hann window
+ * sin^2(pi n / W) (the four shifted windows sum to 2).
+ *
+ * lp_frames_gather: xf [B,F,W] <- x [B,T] (zero outside the signal).
+ * lp_frames_overlap_add: x [B,T] <- sum over the four frames holding each
+ * sample of xf [B,F,W] (the adjoint of lp_frames_gather with the same weighting).
+ *
+ * The frame-wise filter is gather (unweighted) -> lp_forward_ti over the B*F
+ * frames with their coefficient rows af [B*F,M] -> overlap-add (weighted); its
+ * adjoint is gather (weighted) of dL/ds -> lp_backward_ti -> overlap-add
+ * (unweighted) of the frames' dL/de.  Device pointers, caller-owned; errors:
+ * LP_EINVAL for sizes < 1 or missing pointers.
+ */
+int64_t lp_frames_count(int64_t T, int64_t hop);
+int lp_frames_gather(int64_t B, int64_t T, int64_t hop, const float *x, float *xf, int weighted, void *stream);
+int lp_frames_overlap_add(int64_t B, int64_t T, int64_t hop, const float *xf, float *x, int weighted,
+                          void *stream);
+
 /* Variable-length batches: sequence b occupies samples [offsets[b], offsets[b+1])
  * of the packed arrays e [N], a [N,M], s [N] (N = offsets[B]).  `offsets` is a
  * device array; `N` must equal offsets[B].  Chunk boundaries are relative to

@@ -188,6 +188,51 @@ int ensure_ws(lp_plan *p, size_t need, hipStream_t stream) {
     return LP_OK;
 }
 
+// ---------------------------------------------------------------- frame-wise approximation
+// Frames of length W = 4 hop, frame f starting at sample (f - 3) hop, F =
+// ceil(T / hop) + 3 per sequence: every sample lies in exactly four frames.
+// The optional weight is w(n) / 2 with the periodic Hann window w(n) =
+// sin^2(pi n / W), whose shifted copies sum to 2 at this overlap.
+__device__ __forceinline__ float frame_weight(int64_t n, int64_t W) {
+    const float sn = sinpif((float)n / (float)W);
+    return 0.5f * sn * sn;
+}
+
+// xf[b][f][n] = x[b][(f - 3) hop + n] (0 outside the signal), times the weight if asked.
+__global__ __launch_bounds__(256) void k_frames_gather(int64_t B, int64_t T, int64_t hop, int64_t F,
+                                                       const float *__restrict__ x, float *__restrict__ xf,
+                                                       int weighted) {
+    const int64_t W = 4 * hop, n_all = B * F * W;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_all;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t n = q % W, bf = q / W, f = bf % F, b = bf / F;
+        const int64_t t = (f - 3) * hop + n;
+        float v = (t >= 0 && t < T) ? x[b * T + t] : 0.f;
+        if (weighted) v *= frame_weight(n, W);
+        xf[q] = v;
+    }
+}
+
+// x[b][t] = sum over the four frames holding t of xf[b][f][t - (f - 3) hop], each
+// times the weight if asked (the adjoint of k_frames_gather).
+__global__ __launch_bounds__(256) void k_frames_overlap_add(int64_t B, int64_t T, int64_t hop, int64_t F,
+                                                            const float *__restrict__ xf, float *__restrict__ x,
+                                                            int weighted) {
+    const int64_t W = 4 * hop, n_all = B * T;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_all;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = q % T, b = q / T, f0 = t / hop;
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t f = f0 + j, n = t - (f - 3) * hop;
+            const float v = xf[(b * F + f) * W + n];
+            acc += (double)(weighted ? frame_weight(n, W) * v : v);
+        }
+        x[q] = (float)acc;
+    }
+}
+
 // Prefix sums over a sequence table (single block): chunk counts (cbase) and
 // the group counts of the forward (gbf, cpwf chunks per group) and adjoint
 // (gbb, cpwb) scans.  The table is either packed offsets or starts + lens;
@@ -340,9 +385,11 @@ struct Ops {
         const int chain = w.S.ti ? 1 : w.chain;
         tm.begin("fwd_scan");
         if (w.S.ti) {
-            hipLaunchKernelGGL((k_ti_zs<M, RS::G>), dim3((unsigned)ceil_div(w.nch, RS::CPW)), dim3(64), 0, st, w.S, e,
-                               a, w.zbuf, w.zero, w.nch);
-            hipLaunchKernelGGL((k_ti_phi<M>), dim3((unsigned)w.S.n), dim3(256), 0, st, w.S, a, w.phiT);
+            if (w.S.T > w.S.L) {  // some chunk carries a transition (uniform batches)
+                hipLaunchKernelGGL((k_ti_zs<M, RS::G>), dim3((unsigned)ceil_div(w.nch, RS::CPW)), dim3(64), 0, st,
+                                   w.S, e, a, w.zbuf, w.zero, w.nch);
+                hipLaunchKernelGGL((k_ti_phi<M>), dim3((unsigned)w.S.n), dim3(256), 0, st, w.S, a, w.phiT);
+            }
         } else {
             hipLaunchKernelGGL((k_fwd_local<M, FS::LPC, FS::CPL, FS::R>), dim3((unsigned)w.gf.ngroups), dim3(64), 0,
                                st, w.S, w.gf, e, a, w.phiT, w.zbuf, w.aggf, w.chain);
@@ -749,6 +796,31 @@ int lp_backward_ti(lp_plan *p, int64_t B, int64_t T, const float *g, const float
                    const double *zi, const float *s, const void *saved, float *grad_e, float *grad_a,
                    double *grad_zi, void *stream) {
     return backward_impl(p, B, nullptr, T, g, a, e, zi, s, saved, grad_e, grad_a, grad_zi, stream, 0, true);
+}
+
+int64_t lp_frames_count(int64_t T, int64_t hop) { return (T < 1 || hop < 1) ? 0 : ceil_div(T, hop) + 3; }
+
+static int frames_launch(bool gather, int64_t B, int64_t T, int64_t hop, const float *src, float *dst, int weighted,
+                         void *stream) {
+    if (B < 1 || T < 1 || hop < 1) return fail(LP_EINVAL, "B, T and hop must be >= 1");
+    if (!src || !dst) return fail(LP_EINVAL, "input and output are required");
+    const int64_t F = ceil_div(T, hop) + 3, n = gather ? B * F * 4 * hop : B * T;
+    const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(n, 256), 65536);
+    if (gather)
+        hipLaunchKernelGGL(k_frames_gather, dim3(grid), dim3(256), 0, (hipStream_t)stream, B, T, hop, F, src, dst,
+                           weighted);
+    else
+        hipLaunchKernelGGL(k_frames_overlap_add, dim3(grid), dim3(256), 0, (hipStream_t)stream, B, T, hop, F, src,
+                           dst, weighted);
+    return check_hip(hipGetLastError(), gather ? "kernel launch (frames gather)" : "kernel launch (overlap-add)");
+}
+
+int lp_frames_gather(int64_t B, int64_t T, int64_t hop, const float *x, float *xf, int weighted, void *stream) {
+    return frames_launch(true, B, T, hop, x, xf, weighted, stream);
+}
+
+int lp_frames_overlap_add(int64_t B, int64_t T, int64_t hop, const float *xf, float *x, int weighted, void *stream) {
+    return frames_launch(false, B, T, hop, xf, x, weighted, stream);
 }
 
 int lp_plan_autotune(lp_plan *p, int64_t B, int64_t T, int reps, int *chosen, double *best_ms) {

@@ -365,3 +365,46 @@ def backward_plain(g: torch.Tensor, a: torch.Tensor, s: torch.Tensor, zi: Option
     _lib.check(_lib.load().lp_backward_plain(M, B, T, _ptr(g), _ptr(a), _ptr(zi), _ptr(s), _ptr(ge), _ptr(ga),
                                              _ptr(gz), _stream(g.device)))
     return ge, ga, gz
+
+
+def frames_count(T: int, hop: int) -> int:
+    """Frames of the frame-wise approximation for a length-T signal: ceil(T / hop) + 3."""
+    return int(_lib.load().lp_frames_count(int(T), int(hop)))
+
+
+def framewise_forward(plan: "Plan", e: torch.Tensor, af: torch.Tensor, hop: int):
+    """Frame-wise approximation of the filter (frames of 4 hop samples, 75 % overlap):
+    e [B,T], af [B,F,M] (F = frames_count(T, hop)) -> (s [B,T], ctx for the adjoint).
+
+    Gather the frames, filter each with its own time-invariant row (lp_forward_ti on
+    the plan, whose chunk length should cover a frame), overlap-add through the
+    halved Hann window.
+    """
+    _need(e, "e", torch.float32, 2)
+    _need(af, "af", torch.float32, 3)
+    B, T = e.shape
+    F, W, M = frames_count(T, hop), 4 * hop, plan.M
+    if af.shape != (B, F, M):
+        raise ValueError(f"af must have shape {(B, F, M)}, got {tuple(af.shape)}")
+    lib, st = _lib.load(), _stream(e.device)
+    ef = torch.empty((B * F, W), dtype=torch.float32, device=e.device)
+    _lib.check(lib.lp_frames_gather(B, T, hop, _ptr(e), _ptr(ef), 0, st))
+    sf, _, saved = plan.forward_ti(ef, af.reshape(B * F, M))
+    s = torch.empty_like(e)
+    _lib.check(lib.lp_frames_overlap_add(B, T, hop, _ptr(sf), _ptr(s), 1, st))
+    return s, (ef, sf, saved)
+
+
+def framewise_backward(plan: "Plan", g: torch.Tensor, af: torch.Tensor, ctx, hop: int):
+    """Adjoint of framewise_forward: returns (grad_e [B,T], grad_af [B,F,M])."""
+    _need(g, "g", torch.float32, 2)
+    ef, sf, saved = ctx
+    B, T = g.shape
+    F, W, M = frames_count(T, hop), 4 * hop, plan.M
+    lib, st = _lib.load(), _stream(g.device)
+    gf = torch.empty((B * F, W), dtype=torch.float32, device=g.device)
+    _lib.check(lib.lp_frames_gather(B, T, hop, _ptr(g), _ptr(gf), 1, st))
+    gef, gaf, _ = plan.backward_ti(gf, af.reshape(B * F, M), ef, saved, s=sf)
+    ge = torch.empty_like(g)
+    _lib.check(lib.lp_frames_overlap_add(B, T, hop, _ptr(gef), _ptr(ge), 0, st))
+    return ge, gaf.reshape(B, F, M)

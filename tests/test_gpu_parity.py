@@ -424,3 +424,85 @@ def test_time_invariant_training_shape_sampled(tv):
         assert rms_rel(host(s[b]), s_ref[0]) <= TOL, b
         assert rms_rel(host(ge[b]), ge_ref[0]) <= TOL, b
         assert rms_rel(host(ga[b]), ga_ref[0]) <= TOL, b
+
+
+def _framewise_inputs(B, T, M, hop, seed):
+    from tests.pins import stable_ti_coeffs
+    rng = np.random.default_rng(seed)
+    F = oracle.framewise_geometry(T, hop)[1]
+    af = np.stack([np.stack([stable_ti_coeffs(rng, M) for _ in range(F)]) for _ in range(B)]).astype(np.float32)
+    return make_excitation(rng, B, T), af, make_upstream_grad(rng, B, T)
+
+
+def test_frames_gather_and_overlap_add(tv):
+    """The framing kernels against their definition (NumPy), weighted and not."""
+    from paper_2406_05128_amd import _lib
+    B, T, hop = 2, 1000, 50
+    W, F = oracle.framewise_geometry(T, hop)
+    assert tv.frames_count(T, hop) == F
+    x = np.random.default_rng(3).standard_normal((B, T)).astype(np.float32)
+    xf_d = torch.empty((B, F, W), dtype=torch.float32, device=dev())
+    x_d = to_dev(x)
+    w = 0.5 * oracle.hann_periodic(W)
+    ref = np.zeros((B, F, W))
+    for f in range(F):
+        for n in range(W):
+            t = (f - 3) * hop + n
+            if 0 <= t < T:
+                ref[:, f, n] = x[:, t]
+    lib, st = _lib.load(), torch.cuda.current_stream(dev()).cuda_stream
+    import ctypes
+    for weighted in (0, 1):
+        assert lib.lp_frames_gather(B, T, hop, ctypes.c_void_p(x_d.data_ptr()), ctypes.c_void_p(xf_d.data_ptr()),
+                                    weighted, ctypes.c_void_p(st)) == 0
+        torch.cuda.synchronize()
+        exp = ref * (w if weighted else 1.0)
+        assert np.max(np.abs(host(xf_d) - exp)) <= 1e-6
+        back = torch.empty_like(x_d)
+        assert lib.lp_frames_overlap_add(B, T, hop, ctypes.c_void_p(xf_d.data_ptr()), ctypes.c_void_p(back.data_ptr()),
+                                         weighted, ctypes.c_void_p(st)) == 0
+        torch.cuda.synchronize()
+        ola = np.zeros((B, T))
+        got = host(xf_d)
+        for f in range(F):
+            for n in range(W):
+                t = (f - 3) * hop + n
+                if 0 <= t < T:
+                    ola[:, t] += got[:, f, n] * (w[n] if weighted else 1.0)
+        assert np.max(np.abs(host(back) - ola)) <= 1e-5
+
+
+@pytest.mark.parametrize("B,T,M,hop,L", [(2, 1300, 6, 60, 240), (3, 5000, 22, 240, 968), (2, 2000, 22, 240, 264)])
+def test_framewise_matches_oracle(tv, B, T, M, hop, L):
+    """Frame-wise approximation (frames filtered with their own rows, overlap-added):
+    s, dL/de and dL/daf against the oracle."""
+    e, af, g = _framewise_inputs(B, T, M, hop, seed=T + M)
+    s_ref, sf_ref = oracle.framewise_forward(e, af, hop)
+    ge_ref, gaf_ref = oracle.framewise_backward(g, af, sf_ref, hop)
+    plan = tv.Plan(M, dev(), L)
+    e_d, af_d, g_d = to_dev(e), to_dev(af), to_dev(g)
+    s, ctx = tv.framewise_forward(plan, e_d, af_d, hop)
+    ge, gaf = tv.framewise_backward(plan, g_d, af_d, ctx, hop)
+    plan.check_status()
+    torch.cuda.synchronize()
+    assert per_seq_err(host(s), s_ref) <= TOL
+    assert per_seq_err(host(ge), ge_ref) <= TOL
+    assert per_seq_err(host(gaf), gaf_ref) <= TOL
+
+
+def test_framewise_training_shape_sampled(tv):
+    """Frame-wise at B=64, T=48000, M=22, hop 240 (10 ms at 24 kHz): sampled sequences."""
+    B, T, M, hop = 64, 48000, 22, 240
+    e, af, g = _framewise_inputs(B, T, M, hop, seed=99)
+    plan = tv.Plan(M, dev(), 968)
+    e_d, af_d, g_d = to_dev(e), to_dev(af), to_dev(g)
+    s, ctx = tv.framewise_forward(plan, e_d, af_d, hop)
+    ge, gaf = tv.framewise_backward(plan, g_d, af_d, ctx, hop)
+    plan.check_status()
+    torch.cuda.synchronize()
+    for b in (0, 63):
+        s_ref, sf_ref = oracle.framewise_forward(e[b:b + 1], af[b:b + 1], hop)
+        ge_ref, gaf_ref = oracle.framewise_backward(g[b:b + 1], af[b:b + 1], sf_ref, hop)
+        assert rms_rel(host(s[b]), s_ref[0]) <= TOL, b
+        assert rms_rel(host(ge[b]), ge_ref[0]) <= TOL, b
+        assert rms_rel(host(gaf[b]), gaf_ref[0]) <= TOL, b
