@@ -130,6 +130,58 @@ def lp_backward_ti(g: np.ndarray, a: np.ndarray, s: np.ndarray, zi: Optional[np.
     return ge, ga.sum(axis=1), gz
 
 
+def coef_frames_count(T: int, hop: int) -> int:
+    """Frame-rate coefficient rows for a length-T signal: frame q sits at sample
+    q hop, and the last sample needs a right neighbour, so F = (T - 1) // hop + 2."""
+    return (T - 1) // hop + 2
+
+
+def upsample_frames(A: np.ndarray, T: int, hop: int) -> np.ndarray:
+    """Linear upsampling of frame-rate LP coefficients to the sample rate (Sec. 4.3):
+    for t = q hop + n (0 <= n < hop), a(t) = (1 - n/hop) A[q] + (n/hop) A[q+1].
+    A [B,F,M] with F = coef_frames_count(T, hop).  Returns a [B,T,M] in float64."""
+    A = _f64(A)
+    B, F, M = A.shape
+    assert F == coef_frames_count(T, hop)
+    t = np.arange(T)
+    q = t // hop
+    w = ((t - q * hop) / hop)[None, :, None]
+    return (1.0 - w) * A[:, q, :] + w * A[:, q + 1, :]
+
+
+def upsample_frames_adjoint(ga: np.ndarray, F: int, hop: int) -> np.ndarray:
+    """Adjoint of upsample_frames: every sample t = q hop + n hands (1 - n/hop) of
+    dL/da(t) to frame q and n/hop of it to frame q + 1.  ga [B,T,M] -> [B,F,M]."""
+    ga = np.asarray(ga, dtype=np.float64)
+    B, T, M = ga.shape
+    gA = np.zeros((B, F, M))
+    for q in range(F - 1):
+        lo, hi = q * hop, min((q + 1) * hop, T)
+        if lo >= hi:
+            continue
+        w = ((np.arange(lo, hi) - q * hop) / hop)[None, :, None]
+        gA[:, q] += ((1.0 - w) * ga[:, lo:hi]).sum(axis=1)
+        gA[:, q + 1] += (w * ga[:, lo:hi]).sum(axis=1)
+    return gA
+
+
+def lp_forward_frames(e: np.ndarray, A: np.ndarray, hop: int, zi: Optional[np.ndarray] = None):
+    """The filter with frame-rate coefficients A [B,F,M] linearly upsampled to every
+    sample (Sec. 4.3), then Eq. 6.  Returns (s, zf) as lp_forward."""
+    return lp_forward(e, upsample_frames(A, e.shape[1], hop), zi)
+
+
+def lp_backward_frames(g: np.ndarray, A: np.ndarray, s: np.ndarray, hop: int,
+                       zi: Optional[np.ndarray] = None, need_grad_zi: bool = False):
+    """Adjoint of lp_forward_frames: the per-sample adjoint (Eqs. 12-13) on the
+    upsampled rows, then dL/dA by the adjoint of the upsampling.
+    Returns (grad_e [B,T], grad_A [B,F,M], grad_zi [B,M] or None)."""
+    T = g.shape[1]
+    F = A.shape[1]
+    ge, ga, gz = lp_backward(g, upsample_frames(A, T, hop), s, zi, need_grad_zi=need_grad_zi)
+    return ge, upsample_frames_adjoint(ga, F, hop), gz
+
+
 def framewise_geometry(T: int, hop: int):
     """Frames of the frame-wise approximation: length W = 4 hop (75 % overlap),
     frame f starting at sample (f - 3) hop, F = ceil(T / hop) + 3 frames, so that

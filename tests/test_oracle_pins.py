@@ -167,3 +167,59 @@ def test_oracle_framewise_approximation():
         am = af.copy(); am[b, f, i] -= h
         fd = (np.sum(g * oracle.framewise_forward(e, ap, hop)[0]) - np.sum(g * oracle.framewise_forward(e, am, hop)[0])) / (2 * h)
         assert abs(fd - gaf[b, f, i]) <= 1e-6 * (abs(fd) + 1.0), (b, f, i, fd, gaf[b, f, i])
+
+
+def test_oracle_frame_rate_coefficients():
+    """Frame-rate LP coefficients linearly upsampled to the sample rate (Sec. 4.3):
+    the upsampling against numpy.interp and its values at the frame samples, a
+    constant track against the time-invariant filter, hop 1 against the
+    per-sample adjoint, the adjoint identity of the upsampling, and central
+    finite differences of L = <g, s> in the frame coefficients."""
+    from synth.inputs import reflection_to_lpc
+    rng = np.random.default_rng(43)
+    B, T, M, hop = 2, 700, 6, 50
+    F = oracle.coef_frames_count(T, hop)
+    assert F == 15
+    A = reflection_to_lpc(rng.uniform(-0.7, 0.7, size=(B, F, M)))
+    a = oracle.upsample_frames(A, T, hop)
+    # numpy.interp between frame samples q*hop, coefficient by coefficient
+    xp = np.arange(F) * hop
+    for b in range(B):
+        for i in range(M):
+            ref = np.interp(np.arange(T), xp, A[b, :, i])
+            assert np.max(np.abs(a[b, :, i] - ref)) <= 1e-14 * (1.0 + np.max(np.abs(ref)))
+    # the frame samples carry the frame rows exactly
+    qs = np.arange(0, T, hop)
+    assert np.array_equal(a[:, qs, :], A[:, qs // hop, :])
+    e = rng.standard_normal((B, T)); g = rng.standard_normal((B, T))
+    # a constant track is the time-invariant filter
+    Ac = np.repeat(A[:, :1, :], F, axis=1)
+    s_c, _ = oracle.lp_forward_frames(e, Ac, hop)
+    s_ti, _ = oracle.lp_forward_ti(e, A[:, 0, :])
+    assert pins.rms_rel(s_c, s_ti) < 1e-12
+    # hop 1: every sample has its own row; the frame gradient is the per-sample one
+    A1 = reflection_to_lpc(rng.uniform(-0.5, 0.5, size=(B, T + 1, M)))
+    s1, _ = oracle.lp_forward_frames(e, A1, 1)
+    ge1, gA1, _ = oracle.lp_backward_frames(g, A1, s1, 1)
+    ge_ref, ga_ref, _ = oracle.lp_backward(g, A1[:, :T], s1)
+    assert np.array_equal(ge1, ge_ref)
+    assert np.allclose(gA1[:, :T], ga_ref, rtol=0, atol=1e-12 * np.max(np.abs(ga_ref)))
+    assert np.all(gA1[:, T] == 0.0)
+    # adjoint identity of the upsampling: <up(X), Y> = <X, up^T(Y)>
+    X = rng.standard_normal((B, F, M)); Y = rng.standard_normal((B, T, M))
+    lhs = float(np.sum(oracle.upsample_frames(X, T, hop) * Y))
+    rhs = float(np.sum(X * oracle.upsample_frames_adjoint(Y, F, hop)))
+    assert abs(lhs - rhs) <= 1e-11 * (abs(lhs) + 1.0)
+    # finite differences of L = <g, s> in the frame coefficients
+    s, _ = oracle.lp_forward_frames(e, A, hop)
+    ge, gA, _ = oracle.lp_backward_frames(g, A, s, hop)
+    h = 1e-6
+    for (b, q, i) in [(0, 0, 0), (1, 4, 3), (0, F - 1, 5), (1, F - 2, 1), (0, 7, 2)]:
+        ap = A.copy(); ap[b, q, i] += h
+        am = A.copy(); am[b, q, i] -= h
+        fd = (np.sum(g * oracle.lp_forward_frames(e, ap, hop)[0])
+              - np.sum(g * oracle.lp_forward_frames(e, am, hop)[0])) / (2 * h)
+        assert abs(fd - gA[b, q, i]) <= 1e-6 * (abs(fd) + 1.0), (b, q, i, fd, gA[b, q, i])
+    # the excitation gradient is the per-sample one on the upsampled rows
+    ge_ps, _, _ = oracle.lp_backward(g, a, s)
+    assert np.array_equal(ge, ge_ps)
