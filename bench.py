@@ -231,6 +231,111 @@ def time_invariant_bench(tv, B: int, T: int, M: int, L: int, steps: int, warmup:
                     "chunked rerun and adjoint kernels"}
 
 
+def frame_rate_bench(tv, B: int, T: int, M: int, L: int, steps: int, warmup: int, ms_samplewise: float):
+    """Training shape with frame-rate LP coefficients (Sec. 4.3: one row per
+    240-sample frame, linearly upsampled to the sample rate) interpolated inside
+    the kernels: forward + recompute adjoint through lp_forward_frames /
+    lp_backward_frames, giving dL/de and dL/dA [B,F,M].
+
+    Algorithmic bytes per sample: e, s (forward), g, e, grad_e (adjoint) = 20 B;
+    the frame rows and their gradient are B*F*M floats each.  Agreement with the
+    per-sample path is checked on 4 sequences whose rows are upsampled on the host
+    (numpy.interp) and fed to lp_forward / lp_backward.
+    """
+    import numpy as np
+    import torch
+    from synth import make_excitation, make_upstream_grad, reflection_to_lpc
+
+    hop = 240
+    dev = torch.device("cuda", 0)
+    rng = np.random.default_rng(78)
+    F = tv.coef_frames_count(T, hop)
+    # bounded random walk of the reflection coefficients per frame (neighbouring
+    # frames close enough that interpolated LPCs stay stable), bandwidth 0.98
+    k = np.empty((B, F, M))
+    k[:, 0] = rng.uniform(-0.95, 0.95, size=(B, M))
+    dk = rng.normal(0.0, 0.01, size=(B, F, M))
+    for f in range(1, F):
+        k[:, f] = np.clip(k[:, f - 1] + dk[:, f], -0.95, 0.95)
+    A_h = (reflection_to_lpc(k) * 0.98 ** np.arange(1, M + 1)).astype(np.float32)
+    e_h = make_excitation(rng, B, T)
+    g_h = make_upstream_grad(rng, B, T)
+    A, e, g = (torch.from_numpy(x).to(dev) for x in (A_h, e_h, g_h))
+
+    def step_with(p_):
+        s, _, saved = p_.forward_frames(e, A, hop)
+        return p_.backward_frames(g, A, hop, e, saved)
+
+    # chunk length: a short sweep around the per-sample choice (the frame-rate kernels
+    # hold more LDS per wave, which moves the occupancy steps)
+    sweep = {}
+    for Lc in sorted({L} | {k * M for k in range(max(1, (L - 5 * M) // M), (L + 6 * M) // M + 1)}):
+        try:
+            pc = tv.Plan(M, dev, Lc)
+            for _ in range(2):
+                step_with(pc)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                step_with(pc)
+            torch.cuda.synchronize()
+            sweep[Lc] = round((time.perf_counter() - t0) * 1e3 / 5, 4)
+        except Exception as ex:  # chunk lengths whose staged frame rows do not fit
+            log(f"frame-rate: chunk {Lc} skipped ({ex})")
+    L = min(sweep, key=sweep.get)
+    plan = tv.Plan(M, dev, L)
+
+    def step():
+        return step_with(plan)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    plan.set_timing(True)
+    plan.reset_timings()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    kern = {k: round(1e3 * v[0] / max(v[1], 1), 2) for k, v in plan.timings().items()}
+    plan.set_timing(False)
+    # agreement with the per-sample path on rows upsampled on the host
+    nb = 4
+    x = np.arange(T)
+    a_h = np.empty((nb, T, M), np.float32)
+    for b in range(nb):
+        for i in range(M):
+            a_h[b, :, i] = np.interp(x, np.arange(F) * hop, A_h[b, :, i])
+    a4 = torch.from_numpy(a_h).to(dev)
+    s_f, _, sv_f = plan.forward_frames(e[:nb].contiguous(), A[:nb].contiguous(), hop)
+    ge_f, _, _ = plan.backward_frames(g[:nb].contiguous(), A[:nb].contiguous(), hop, e[:nb].contiguous(), sv_f)
+    s_p, _, sv_p = plan.forward(e[:nb].contiguous(), a4)
+    ge_p, _, _ = plan.backward(g[:nb].contiguous(), a4, e[:nb].contiguous(), sv_p, need_a=False)
+    torch.cuda.synchronize()
+    plan.check_status()
+
+    def rel(x_, r_):
+        d = x_.double() - r_.double()
+        return float(torch.sqrt((d * d).mean(dim=1) / (r_.double() ** 2).mean(dim=1)).max())
+
+    alg = B * T * 20 + 2 * B * F * M * 4
+    return {"workload": f"frame_rate_b{B}_t{T}_m{M}_hop{hop}", "frames": F, "chunk": L, "chunk_sweep_ms": sweep,
+            "ms_per_step": round(ms, 4), "samples_per_s": round(B * T / (ms * 1e-3), 1),
+            "vs_samplewise_time": round(ms / ms_samplewise, 3),
+            "step_hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "kernels_us": kern,
+            "max_rms_rel_diff_vs_per_sample_rows_4seq": {"s": round(rel(s_f, s_p), 9),
+                                                         "grad_e": round(rel(ge_f, ge_p), 9)},
+            "inputs": "reflection coefficients per frame as a bounded random walk (|k| <= 0.95, step sd 0.01), "
+                      "step-up at the frame rate, a_i scaled by 0.98^i",
+            "note": "rows interpolated in LDS by the ring producers (no [B,T,M] array read or written); "
+                    "dL/dA from per-chunk float64 shares summed per frame"}
+
+
 def framewise_bench(tv, sets, B: int, T: int, M: int, steps: int, warmup: int, ms_samplewise: float):
     """The frame-wise approximation (hop 240 = 10 ms at 24 kHz, frames of 960 samples,
     75 % overlap) on the training shape: frames filtered with the coefficient row
@@ -365,6 +470,7 @@ def main():
     ap.add_argument("--no-stress", action="store_true")
     ap.add_argument("--no-ti", action="store_true", help="skip the time-invariant coefficient section")
     ap.add_argument("--no-framewise", action="store_true", help="skip the frame-wise approximation section")
+    ap.add_argument("--no-frame-rate", action="store_true", help="skip the frame-rate coefficient section")
     ap.add_argument("--serve-requests", type=int, default=100)
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-batch", type=int, default=8)
@@ -532,6 +638,13 @@ def main():
         log(f"time-invariant: {ti['ms_per_step']:.3f} ms/step")
         torch.cuda.empty_cache()
 
+    frame_rate = None
+    if not args.no_frame_rate:
+        log("frame-rate coefficients (hop 240, interpolated in the kernels)")
+        frame_rate = frame_rate_bench(tv, B, T, M, L, args.steps, args.warmup, ms_step)
+        log(f"frame-rate: {frame_rate['ms_per_step']:.3f} ms/step")
+        torch.cuda.empty_cache()
+
     framewise = None
     if not args.no_framewise:
         log("frame-wise approximation (hop 240, 75 % overlap)")
@@ -566,6 +679,7 @@ def main():
         "serve": serve,
         "stress": stress,
         "time_invariant": ti,
+        "frame_rate": frame_rate,
         "framewise": framewise,
     }
     print(json.dumps(out), flush=True)

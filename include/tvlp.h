@@ -166,6 +166,32 @@ int lp_backward_ti(lp_plan *p, int64_t B, int64_t T,
                    float *grad_e, float *grad_a, double *grad_zi, void *stream);
 
 /*
+ * Frame-rate coefficients (the pipeline of Sec. 4.3: LP coefficients produced
+ * once per analysis frame and linearly upsampled to the sample rate).  A
+ * [B,F,M] holds one row per frame, frame q at sample q*hop of its sequence, F =
+ * lp_coef_frames_count(T, hop) = (T - 1) / hop + 2 (the last sample has a right
+ * neighbour).  Sample t = q*hop + n (0 <= n < hop) uses
+ *   a(t) = A[q] + n (A[q+1] - A[q]) / hop,
+ * interpolated inside the kernels (float32), so no [B,T,M] array is read or
+ * written.  lp_forward_frames is lp_forward with those rows (same saved buffer,
+ * zi, zf); lp_backward_frames is lp_backward with grad_A [B,F,M] = dL/dA in place
+ * of grad_a: each sample hands (1 - n/hop) of dL/da(t) = -ghat(t) s(t-i) (Eq. 13)
+ * to frame q and n/hop to frame q + 1, accumulated per chunk in float64 and
+ * summed per frame.  Uniform batches only; hop in [1, 2^20].  Errors: LP_EINVAL
+ * for bad sizes or pointers, or when hop is so short against the plan's chunk
+ * length that the frame rows one chunk touches ((L - 1) / hop + 3 of them) do not
+ * fit in LDS; otherwise as for lp_forward / lp_backward.
+ */
+int64_t lp_coef_frames_count(int64_t T, int64_t hop);
+int lp_forward_frames(lp_plan *p, int64_t B, int64_t T, int64_t hop,
+                      const float *e, const float *A, const double *zi,
+                      float *s, double *zf, void *saved, void *stream);
+int lp_backward_frames(lp_plan *p, int64_t B, int64_t T, int64_t hop,
+                       const float *g, const float *A, const float *e,
+                       const double *zi, const float *s, const void *saved,
+                       float *grad_e, float *grad_A, double *grad_zi, void *stream);
+
+/*
  * Frame-wise approximation (the comparator of Sec. 3.2: time-invariant filtering
  * of short overlapping frames, overlap-added; 75 % overlap as in Sec. 5).  Frames
  * have length W = 4 hop; frame f of a sequence starts at sample (f - 3) hop and

@@ -9,10 +9,10 @@ from . import _lib
 _lib.load()
 
 from .ops import Plan, PairStepGraph, forward_plain, backward_plain  # noqa: E402
-from .ops import frames_count, framewise_forward, framewise_backward  # noqa: E402
+from .ops import coef_frames_count, frames_count, framewise_forward, framewise_backward  # noqa: E402
 from .autograd import LPFunction, lp, get_plan  # noqa: E402
 from .serve import Server  # noqa: E402
 
 __all__ = ["Plan", "PairStepGraph", "forward_plain", "backward_plain", "LPFunction", "lp", "get_plan", "Server",
-           "frames_count", "framewise_forward", "framewise_backward"]
+           "coef_frames_count", "frames_count", "framewise_forward", "framewise_backward"]
 __version__ = "0.1.0"

@@ -53,6 +53,9 @@ SIGNATURES = {
     "lp_forward_ti": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P]),
     "lp_backward_ti": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "lp_frames_count": (_I64, [_I64, _I64]),
+    "lp_coef_frames_count": (_I64, [_I64, _I64]),
+    "lp_forward_frames": (_INT, [_P, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P, _P]),
+    "lp_backward_frames": (_INT, [_P, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "lp_frames_gather": (_INT, [_I64, _I64, _I64, _P, _P, ctypes.c_int, _P]),
     "lp_frames_overlap_add": (_INT, [_I64, _I64, _I64, _P, _P, ctypes.c_int, _P]),
     "lp_forward_varlen": (_INT, [_P, _I64, _P, _I64, _P, _P, _P, _P, _P, _P, _P]),

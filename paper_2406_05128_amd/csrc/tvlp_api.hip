@@ -138,12 +138,14 @@ constexpr size_t kStatusOffset = 256;  // byte offset of the scan status word in
 
 // Workspace layout for one call with nch chunks and n samples over B sequences.
 struct WsLayout {
-    size_t zero, xs, phi, yend, q, cbase, gbf, gbb, aggf, inclf, aggb, inclb, sbuf, status, total;
+    size_t zero, xs, phi, yend, q, cbase, gbf, gbb, aggf, inclf, aggb, inclb, sbuf, fpart, status, total;
 };
 
 // ngf / ngb: group slots of the forward / adjoint scans; nsamp: sample slots
-// of the sequence layout (B*T, or N), for s recomputed by the adjoint.
-WsLayout ws_layout(int M, int64_t nch, int64_t B, int64_t ngf, int64_t ngb, int64_t nsamp) {
+// of the sequence layout (B*T, or N), for s recomputed by the adjoint;
+// fpart_bytes: the chunks' shares of a frame-rate coefficient gradient.
+WsLayout ws_layout(int M, int64_t nch, int64_t B, int64_t ngf, int64_t ngb, int64_t nsamp,
+                   size_t fpart_bytes = 0) {
     WsLayout w{};
     size_t off = 0;
     const size_t agg = (size_t)(M * M + M) * sizeof(double);
@@ -161,6 +163,7 @@ WsLayout ws_layout(int M, int64_t nch, int64_t B, int64_t ngf, int64_t ngb, int6
     w.aggb = off;  off += align_up((size_t)ngb * agg);
     w.inclb = off; off += align_up((size_t)ngb * M * sizeof(double));
     w.sbuf = off;  off += align_up((size_t)nsamp * sizeof(float));
+    w.fpart = off; off += align_up(fpart_bytes);
     w.total = off;
     return w;
 }
@@ -374,25 +377,49 @@ struct Ops {
         int *status;
         const float *zero;  // 64 floats of 0 in device memory
         float *sbuf;        // s recomputed by the adjoint (one float per sample slot)
+        double *fpart;      // frame-rate coefficients: chunk shares of dL/dA [nch][nf][M]
         int chain;  // chained carry: no matrix products between chunk transitions
     };
 
+    // Frame-rate coefficients with chunk length L and nf staged frame rows per
+    // chunk: whether every kernel's LDS (ring, staging, emit buffers) fits a CU.
+    static bool frames_lds_ok(int L, int nf) {
+        constexpr size_t lds = 160 * 1024;
+        using FSH = FwdScanShape<M, FS::LPC, FS::CPL, FS::R, true>;
+        const size_t ff = frame_lds_bytes(FS::CPW, M, nf), fr = frame_lds_bytes(RS::CPW, M, nf);
+        const size_t front = std::max<size_t>(BwdScanShape<M, RS::G, RS::R, true>::LDS_BYTES,
+                                              RerunLds<M, RS::G, true>::BYTES);
+        const size_t emit = FrameRing<M, RS::CPW, true, 12>::FLOATS * sizeof(float) +
+                            emit_frame_lds_offset(RS::CPW, M, L) + fr;
+        return FSH::LDS_BYTES + ff <= lds && front + fr <= lds && emit <= lds;
+    }
+
     static void forward(const Bufs &w, const float *e, const float *a, const double *zi, float *s, double *zf,
                         hipStream_t st, Timer &tm) {
+        forward_t<false>(w, e, a, zi, s, zf, st, tm);
+    }
+
+    // FR: a holds frame-rate rows [B][F][M] (w.S.hop, nf, F set), interpolated in the kernels.
+    template <bool FR>
+    static void forward_t(const Bufs &w, const float *e, const float *a, const double *zi, float *s, double *zf,
+                          hipStream_t st, Timer &tm) {
         if (w.nch <= 0) return;
         // time-invariant coefficients: one transition per sequence (a matrix power)
         // and the chunks' zero-state offsets; the carry then runs chained
-        const int chain = w.S.ti ? 1 : w.chain;
+        const bool ti = !FR && w.S.ti;
+        const int chain = ti ? 1 : w.chain;
+        const size_t dynf = FR ? frame_lds_bytes(FS::CPW, M, w.S.nf) : 0;
+        const size_t dynr = FR ? frame_lds_bytes(RS::CPW, M, w.S.nf) : 0;
         tm.begin("fwd_scan");
-        if (w.S.ti) {
+        if (ti) {
             if (w.S.T > w.S.L) {  // some chunk carries a transition (uniform batches)
                 hipLaunchKernelGGL((k_ti_zs<M, RS::G>), dim3((unsigned)ceil_div(w.nch, RS::CPW)), dim3(64), 0, st,
                                    w.S, e, a, w.zbuf, w.zero, w.nch);
                 hipLaunchKernelGGL((k_ti_phi<M>), dim3((unsigned)w.S.n), dim3(256), 0, st, w.S, a, w.phiT);
             }
         } else {
-            hipLaunchKernelGGL((k_fwd_local<M, FS::LPC, FS::CPL, FS::R>), dim3((unsigned)w.gf.ngroups), dim3(64), 0,
-                               st, w.S, w.gf, e, a, w.phiT, w.zbuf, w.aggf, w.chain);
+            hipLaunchKernelGGL((k_fwd_local<M, FS::LPC, FS::CPL, FS::R, FR>), dim3((unsigned)w.gf.ngroups), dim3(64),
+                               dynf, st, w.S, w.gf, e, a, w.phiT, w.zbuf, w.aggf, w.chain);
         }
         tm.end();
         tm.begin("fwd_carry");
@@ -404,26 +431,35 @@ struct Ops {
                                w.zbuf, w.inclf, w.xs);
         tm.end();
         tm.begin("fwd_emit");
-        hipLaunchKernelGGL((k_fwd_rerun2<M, RS::G>), dim3((unsigned)ceil_div(w.nch, RS::CPW)), dim3(64), 0, st,
-                           w.S, e, a, w.xs, s, zf, w.zero, w.nch);
+        hipLaunchKernelGGL((k_fwd_rerun2<M, RS::G, FR>), dim3((unsigned)ceil_div(w.nch, RS::CPW)), dim3(64), dynr,
+                           st, w.S, e, a, w.xs, s, zf, w.zero, w.nch);
         tm.end();
     }
 
     static void backward(const Bufs &w, const float *g, const float *a, const float *e, const float *s_in,
                          float *ge, float *ga, double *gzi, hipStream_t st, Timer &tm) {
+        backward_t<false>(w, g, a, e, s_in, ge, ga, gzi, st, tm);
+    }
+
+    // FR: a holds frame-rate rows and ga receives dL/dA [B][F][M] (chunk shares in
+    // w.fpart, then summed per frame).
+    template <bool FR>
+    static void backward_t(const Bufs &w, const float *g, const float *a, const float *e, const float *s_in,
+                           float *ge, float *ga, double *gzi, hipStream_t st, Timer &tm) {
         if (w.nch <= 0) return;
         // without a stored s the emit kernel reads s recomputed alongside the local scan
         const bool emit = ge || ga;
         const float *s_use = s_in ? s_in : w.sbuf;
+        const size_t dynr = FR ? frame_lds_bytes(RS::CPW, M, w.S.nf) : 0;
         tm.begin("bwd_scan");
         if (emit && !s_in) {
             const int64_t nrun = ceil_div(w.nch, RS::CPW);
-            hipLaunchKernelGGL((k_bwd_front<M, RS::G, RS::R>), dim3((unsigned)(w.gb.ngroups + nrun)), dim3(64), 0,
-                               st, w.S, w.gb, g, a, w.phiT, w.qbuf, w.aggb, w.zero, w.chain, e, w.xs, w.sbuf,
+            hipLaunchKernelGGL((k_bwd_front<M, RS::G, RS::R, FR>), dim3((unsigned)(w.gb.ngroups + nrun)), dim3(64),
+                               dynr, st, w.S, w.gb, g, a, w.phiT, w.qbuf, w.aggb, w.zero, w.chain, e, w.xs, w.sbuf,
                                w.nch);
         } else {
-            hipLaunchKernelGGL((k_bwd_local<M, RS::G, RS::R>), dim3((unsigned)w.gb.ngroups), dim3(64), 0, st, w.S,
-                               w.gb, g, a, w.phiT, w.qbuf, w.aggb, w.zero, w.chain);
+            hipLaunchKernelGGL((k_bwd_local<M, RS::G, RS::R, FR>), dim3((unsigned)w.gb.ngroups), dim3(64), dynr, st,
+                               w.S, w.gb, g, a, w.phiT, w.qbuf, w.aggb, w.zero, w.chain);
         }
         tm.end();
         tm.begin("bwd_carry");
@@ -434,7 +470,19 @@ struct Ops {
             hipLaunchKernelGGL((k_bwd_expand<M, RS::CPW>), dim3((unsigned)w.gb.ngroups), ct, 0, st, w.S, w.gb, w.phiT,
                                w.qbuf, w.inclb, w.yend, gzi);
         tm.end();
-        if (emit) {
+        if (emit && FR) {
+            const unsigned grid = (unsigned)ceil_div(w.nch, RS::CPW);
+            const size_t dyn = emit_frame_lds_offset(RS::CPW, M, w.S.L) + dynr;
+            tm.begin("bwd_emit");
+            hipLaunchKernelGGL((k_adj_emit2<M, RS::G, true>), dim3(grid), dim3(64), dyn, st, w.S, g, a, s_use, w.xs,
+                               w.yend, ge, nullptr, ga ? w.fpart : nullptr, w.zero, w.nch);
+            if (ga) {
+                const int64_t nout = w.S.n * w.S.F * M;
+                hipLaunchKernelGGL((k_frames_reduce<M>), dim3((unsigned)ceil_div(nout, 256)), dim3(256), 0, st, w.S,
+                                   w.fpart, ga);
+            }
+            tm.end();
+        } else if (emit) {
             const unsigned grid = (unsigned)ceil_div(w.nch, RS::CPW);
             const size_t dyn = emit_lds_bytes(w.S.L);
             tm.begin("bwd_emit");
@@ -524,7 +572,7 @@ int64_t uniform_nchunks(int64_t B, int64_t T, int L) { return B * ceil_div(T, L)
 template <class O>
 int prepare(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, const void *saved, hipStream_t st,
             typename O::Bufs &w, const int64_t *starts = nullptr, const int64_t *lens = nullptr,
-            int64_t bound = 0) {
+            int64_t bound = 0, size_t fpart_bytes = 0) {
     const int M = p->M, L = p->L;
     const int cpwf = O::FS::CPW, cpwb = O::RS::CPW;
     int64_t nch, ngf, ngb;
@@ -541,7 +589,7 @@ int prepare(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, const
         ngf = B * ceil_div(C, cpwf);
         ngb = B * ceil_div(C, cpwb);
     }
-    WsLayout lay = ws_layout(M, nch, B, ngf, ngb, tabled ? T_or_N : B * T_or_N);
+    WsLayout lay = ws_layout(M, nch, B, ngf, ngb, tabled ? T_or_N : B * T_or_N, fpart_bytes);
     if (int r = ensure_ws(p, lay.total, st)) return r;
     char *ws = (char *)p->ws;
     w.nch = nch;
@@ -578,6 +626,7 @@ int prepare(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, const
     w.status = (int *)(ws + lay.status);
     w.zero = (const float *)(ws + lay.zero);
     w.sbuf = (float *)(ws + lay.sbuf);
+    w.fpart = (double *)(ws + lay.fpart);
     w.chain = (p->flags & LP_FLAG_CHAINED_CARRY) ? 1 : 0;
     return LP_OK;
 }
@@ -796,6 +845,87 @@ int lp_backward_ti(lp_plan *p, int64_t B, int64_t T, const float *g, const float
                    const double *zi, const float *s, const void *saved, float *grad_e, float *grad_a,
                    double *grad_zi, void *stream) {
     return backward_impl(p, B, nullptr, T, g, a, e, zi, s, saved, grad_e, grad_a, grad_zi, stream, 0, true);
+}
+
+// ---- frame-rate coefficients: rows once per hop samples, interpolated in the kernels
+
+int64_t lp_coef_frames_count(int64_t T, int64_t hop) { return (T < 1 || hop < 1) ? 0 : (T - 1) / hop + 2; }
+
+}  // extern "C"
+
+namespace {
+
+// Validates a frame-rate call and fills the frame fields of the sequence view.
+template <class O>
+int frames_setup(const lp_plan *p, int64_t T, int64_t hop, typename O::Bufs &w) {
+    const int nf = (int)((p->L - 1) / hop + 3);
+    if (!O::frames_lds_ok(p->L, nf))
+        return fail(LP_EINVAL, "hop %lld is too short for chunk length %d: the staged frame rows do not fit in LDS",
+                    (long long)hop, p->L);
+    w.S.hop = (int)hop;
+    w.S.nf = nf;
+    w.S.F = lp_coef_frames_count(T, hop);
+    return LP_OK;
+}
+
+int frames_args(int64_t B, int64_t T, int64_t hop) {
+    if (B < 1) return fail(LP_EINVAL, "B must be >= 1 (got %lld)", (long long)B);
+    if (T < 1) return fail(LP_EINVAL, "T must be >= 1 (got %lld)", (long long)T);
+    if (hop < 1 || hop > (1 << 20)) return fail(LP_EINVAL, "hop must be in [1, 2^20] (got %lld)", (long long)hop);
+    return LP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lp_forward_frames(lp_plan *p, int64_t B, int64_t T, int64_t hop, const float *e, const float *A,
+                      const double *zi, float *s, double *zf, void *saved, void *stream) {
+    if (int r = check_plan(p)) return r;
+    if (int r = frames_args(B, T, hop)) return r;
+    if (!e || !A || !s) return fail(LP_EINVAL, "e, A and s are required");
+    DeviceGuard dg(p->device);
+    if (!dg.ok) return fail(LP_EDEVICE, "cannot select device %d", p->device);
+    hipStream_t st = (hipStream_t)stream;
+    int rc = LP_OK;
+    Timer tm{p, st};
+    dispatch(p->M, [&](auto ops) {
+        using O = decltype(ops);
+        typename O::Bufs w;
+        rc = prepare<O>(p, B, nullptr, T, saved, st, w);
+        if (rc == LP_OK) rc = frames_setup<O>(p, T, hop, w);
+        if (rc == LP_OK) O::template forward_t<true>(w, e, A, zi, s, zf, st, tm);
+    });
+    if (rc != LP_OK) return rc;
+    return check_hip(hipGetLastError(), "kernel launch (frame-rate forward)");
+}
+
+int lp_backward_frames(lp_plan *p, int64_t B, int64_t T, int64_t hop, const float *g, const float *A,
+                       const float *e, const double *zi, const float *s, const void *saved, float *grad_e,
+                       float *grad_A, double *grad_zi, void *stream) {
+    if (int r = check_plan(p)) return r;
+    if (int r = frames_args(B, T, hop)) return r;
+    if (!g || !A || !saved) return fail(LP_EINVAL, "g, A and saved are required");
+    if ((grad_e || grad_A) && !s && !e) return fail(LP_EINVAL, "the adjoint needs s or e (to recompute s)");
+    if (!grad_e && !grad_A && !grad_zi) return LP_OK;
+    (void)zi;
+    DeviceGuard dg(p->device);
+    if (!dg.ok) return fail(LP_EDEVICE, "cannot select device %d", p->device);
+    hipStream_t st = (hipStream_t)stream;
+    int rc = LP_OK;
+    Timer tm{p, st};
+    dispatch(p->M, [&](auto ops) {
+        using O = decltype(ops);
+        typename O::Bufs w;
+        const int64_t nch = B * ceil_div(T, p->L);
+        const int nf = (int)((p->L - 1) / hop + 3);
+        rc = prepare<O>(p, B, nullptr, T, saved, st, w, nullptr, nullptr, 0,
+                        grad_A ? (size_t)nch * nf * p->M * sizeof(double) : 0);
+        if (rc == LP_OK) rc = frames_setup<O>(p, T, hop, w);
+        if (rc == LP_OK) O::template backward_t<true>(w, g, A, e, s, grad_e, grad_A, grad_zi, st, tm);
+    });
+    if (rc != LP_OK) return rc;
+    return check_hip(hipGetLastError(), "kernel launch (frame-rate backward)");
 }
 
 int64_t lp_frames_count(int64_t T, int64_t hop) { return (T < 1 || hop < 1) ? 0 : ceil_div(T, hop) + 3; }

@@ -55,6 +55,12 @@ struct Seqs {
     // time-invariant coefficients: one row a[b][0..M-1] per sequence, used at
     // every sample of sequence b (uniform batches only)
     int ti;
+    // frame-rate coefficients (uniform batches only; hop > 0): rows A[b][q][0..M-1]
+    // for q < F, frame q at sample q*hop, linearly interpolated per sample; nf:
+    // frame rows one chunk can touch, (L - 1) / hop + 3
+    int hop = 0;
+    int nf = 0;
+    int64_t F = 0;
 };
 
 // Coefficient row (in rows of M floats) of the first sample of a chunk of

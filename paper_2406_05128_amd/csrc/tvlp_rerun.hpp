@@ -159,6 +159,244 @@ struct RowRing {
     }
 };
 
+// ---------------------------------------------------------------- frame-rate coefficients
+//
+// Coefficients given once per hop samples (frame q at sample q*hop of its
+// sequence) and linearly interpolated per sample,
+//   a(q*hop + n) = A[q] + n * (A[q+1] - A[q]) / hop,   0 <= n < hop.
+// A wave first stages the frame rows its chunks touch in LDS (per chunk k, nf
+// rows starting at the chunk's first frame), then produces one interpolated row
+// per ring step with one FMA and one LDS store per 64 words, in place of a DMA
+// of the per-sample row.  Every lane word keeps its frame row, slope and phase in
+// registers; frame changes happen at a handful of steps per chunk, at which the
+// affected words reload from the staged rows.
+
+struct FrameInfo {
+    int64_t arow;  // element offset of the chunk's sequence in A (b * F * M)
+    int64_t tin;   // in-sequence sample index of the chunk's row 0
+    int64_t q0;    // frame of row 0 (staged row 0 of the chunk)
+    int64_t len;   // rows of the chunk (0: inactive)
+};
+
+// LDS bytes of a wave's staging area: CPW records, then [CPW][nf][M] rows.
+__host__ __device__ constexpr size_t frame_lds_bytes(int cpw, int m, int nf) {
+    return (size_t)cpw * sizeof(FrameInfo) + (size_t)cpw * nf * m * sizeof(float);
+}
+
+__device__ __forceinline__ int wave_min_i32(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Produces ring words j = 64 i + lane (coefficient f = j % M of chunk j / M)
+// for rows issued in order: row u of a chunk is its sample u (ascending) or
+// len - 1 - u (descending).  Rows past a chunk's end extrapolate the last
+// frame's line (finite values, only ever read by masked steps).
+template <int M, int CPW, bool DESC>
+struct FrameCoefs {
+    static constexpr int NC = (CPW * M + 63) / 64;  // LDS stores per produced row
+    static constexpr int NONE = 0x7fffffff;
+    typedef __attribute__((address_space(3))) float lfloat;
+    float a0[NC], sl[NC], nf[NC];
+    int ti[NC];  // staged index of the word's current frame row
+    int nx[NC];  // issue count at which the word's frame changes (NONE: never)
+    int p;       // rows issued so far (wave-uniform)
+    int ev;      // smallest nx over the wave
+    int hop;
+    float inv_hop;
+    const float *rows;
+    const FrameInfo *info;
+
+    // All 64 lanes call this.  lds: the staging area (frame_lds_bytes); slot /
+    // lead: the lane's chunk slot and whether it is the first lane of it;
+    // my_b, my_tin, my_len: sequence, first in-sequence sample and rows of the
+    // lane's chunk (my_len 0: inactive).
+    __device__ __forceinline__ void init(const float *__restrict__ A, const Seqs &S, unsigned char *lds, int lane,
+                                         int slot, bool lead, int64_t my_b, int64_t my_tin, int64_t my_len) {
+        hop = S.hop;
+        inv_hop = 1.0f / (float)hop;
+        const int nfr = S.nf;
+        FrameInfo *inf = reinterpret_cast<FrameInfo *>(lds);
+        float *st = reinterpret_cast<float *>(lds + CPW * sizeof(FrameInfo));
+        if (lead && slot < CPW) {
+            FrameInfo fi;
+            fi.arow = my_b * S.F * M;
+            fi.tin = my_tin;
+            fi.q0 = my_tin / hop;
+            fi.len = my_len;
+            inf[slot] = fi;
+        }
+        __syncthreads();
+        const int n_all = CPW * nfr * M;
+        for (int idx = lane; idx < n_all; idx += 64) {
+            const int k = idx / (nfr * M);
+            const int rem = idx - k * nfr * M;
+            const int qq = rem / M, f = rem - qq * M;
+            const FrameInfo fi = inf[k];
+            float v = 0.f;
+            if (fi.len > 0) {
+                const int64_t q = min(fi.q0 + qq, S.F - 1);
+                v = A[fi.arow + q * M + f];
+            }
+            st[idx] = v;
+        }
+        __syncthreads();
+        rows = st;
+        info = inf;
+        p = 0;
+        int mn = NONE;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            const int j = 64 * i + lane;
+            a0[i] = 0.f;
+            sl[i] = 0.f;
+            nf[i] = 0.f;
+            ti[i] = 0;
+            nx[i] = NONE;
+            if (j < CPW * M) {
+                const int k = j / M, f = j - k * M;
+                const FrameInfo fi = inf[k];
+                if (fi.len > 0) {
+                    const int64_t t0 = fi.tin + (DESC ? fi.len - 1 : 0);
+                    const int64_t q = t0 / hop;
+                    const int n = (int)(t0 - q * hop);
+                    ti[i] = (k * nfr + (int)(q - fi.q0)) * M + f;
+                    a0[i] = st[ti[i]];
+                    sl[i] = (st[ti[i] + M] - a0[i]) * inv_hop;
+                    nf[i] = (float)n;
+                    // rows until the frame changes: down to phase 0, or up to phase hop - 1
+                    const int first = DESC ? n + 1 : hop - n;
+                    nx[i] = first < fi.len ? first : NONE;
+                }
+            }
+            mn = min(mn, nx[i]);
+        }
+        ev = wave_min_i32(mn);
+    }
+
+    // The words whose frame changes at row p move to the neighbouring frame.
+    __device__ __forceinline__ void advance() {
+        const int lane = threadIdx.x & 63;
+        int mn = NONE;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            if (nx[i] == p) {
+                ti[i] += DESC ? -M : M;
+                a0[i] = rows[ti[i]];
+                sl[i] = (rows[ti[i] + M] - a0[i]) * inv_hop;
+                nf[i] = DESC ? (float)(hop - 1) : 0.f;
+                const int64_t len = info[(64 * i + lane) / M].len;
+                nx[i] = (int64_t)p + hop < len ? p + hop : NONE;
+            }
+            mn = min(mn, nx[i]);
+        }
+        ev = wave_min_i32(mn);
+    }
+
+    // Writes the next row's CPW*M words to dst[0 .. CPW*M) (nothing beyond).
+    __device__ __forceinline__ void produce(lfloat *dst) {
+        if (p == ev) advance();
+        const int lane = threadIdx.x & 63;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            if (64 * (i + 1) <= CPW * M || 64 * i + lane < CPW * M)
+                dst[64 * i + lane] = __builtin_fmaf(nf[i], sl[i], a0[i]);
+            nf[i] += DESC ? -1.f : 1.f;
+        }
+        ++p;
+    }
+};
+
+// RowRing's interface over frame-rate coefficients: a slot holds the CPW*M
+// produced coefficient words ([chunk][M]), the CPW scalars of the step and a
+// zero word (ZERO).  The scalars are the only DMA: one instruction per step,
+// issued by lanes 0 .. CPW only (lane CPW reads the zero word), so that it
+// writes nothing beyond the slot.  DL: steps in flight.
+template <int M, int CPW, bool DESC, int DL = 15>
+struct FrameRing {
+    using FC = FrameCoefs<M, CPW, DESC>;
+    static constexpr int NC = FC::NC;
+    static constexpr int XOFF = CPW * M;
+    static constexpr int D = DL;
+    static constexpr int NS = D + 1;
+    static constexpr int SLOT = (CPW * M + CPW + 1 + 3) / 4 * 4;
+    static constexpr int FLOATS = NS * SLOT;
+    static constexpr int ZERO = XOFF + CPW;
+    static_assert(CPW < 64, "the scalar DMA needs a spare lane");
+
+    typedef __attribute__((address_space(1))) const char gchar;
+    typedef __attribute__((address_space(3))) float lfloat;
+
+    gchar *base;
+    gchar *ptr;
+    int off, step, lim;
+    FC fc;
+
+    // As RowRing::init for the scalar stream x; A: frame rows [B][F][M];
+    // my_b / my_tin: the lane's chunk's sequence and first in-sequence sample;
+    // lds: the frame staging area.
+    __device__ __forceinline__ void init(const float *A, const float *x, const float *zero, int lane, int64_t my_base,
+                                         int64_t my_len, int G, int64_t my_xoff, int64_t my_b, int64_t my_tin,
+                                         const Seqs &S, unsigned char *lds) {
+        const int k = lane < CPW ? lane : 0;
+        const int64_t kb = __shfl(my_base, k * G, 64);
+        const int64_t kl = __shfl(my_len, k * G, 64);
+        const int64_t kx = __shfl(my_xoff, k * G, 64);
+        const bool live = lane < CPW && kl > 0;
+        base = (gchar *)(live ? x + kb + kx : zero);
+        step = live ? 4 : 0;
+        lim = live ? 4 * (int)(kl - 1) : 0;
+        off = DESC ? lim : 0;
+        fc.init(A, S, lds, lane, lane / G, lane % G == 0, my_b, my_tin, my_len);
+    }
+
+    __device__ __forceinline__ void issue(float *ring, int u) {
+        lfloat *dst = (lfloat *)ring + (u % NS) * SLOT;
+        if ((threadIdx.x & 63) <= CPW)
+            __builtin_amdgcn_global_load_lds((const void *)(base + off), (lds_void_t *)(dst + XOFF), 4, 0, 0);
+        off = DESC ? max(off - step, 0) : min(off + step, lim);
+        fc.produce(dst);
+    }
+    __device__ __forceinline__ void begin_fast() { ptr = base + off; }
+    template <int KS>
+    __device__ __forceinline__ void issue_fast(float *ring) {
+        lfloat *dst = (lfloat *)ring + KS * SLOT;
+        if ((threadIdx.x & 63) <= CPW)
+            __builtin_amdgcn_global_load_lds((const void *)ptr, (lds_void_t *)(dst + XOFF), 4, 0, 0);
+        ptr += DESC ? -(int64_t)step : (int64_t)step;
+        fc.produce(dst);
+    }
+    __device__ __forceinline__ void end_fast(int n) { off = DESC ? max(lim - n * step, 0) : min(n * step, lim); }
+
+    __device__ __forceinline__ static void wait() { __builtin_amdgcn_s_waitcnt(waitcnt_vm_only(D)); }
+    __device__ __forceinline__ static void wait_next() { __builtin_amdgcn_s_waitcnt(waitcnt_vm_only(D - 1)); }
+    __device__ __forceinline__ static void drain() { __builtin_amdgcn_s_waitcnt(waitcnt_vm_only(0)); }
+
+    template <int TPL>
+    struct Lanes {
+        int tap[TPL];
+        int x;
+        __device__ __forceinline__ Lanes(int slot, int r) {
+#pragma unroll
+            for (int m = 0; m < TPL; ++m) {
+                const int t = r * TPL + m;
+                tap[m] = t < M ? slot * M + t : ZERO;
+            }
+            x = XOFF + slot;
+        }
+    };
+    template <int TPL, class KS, class LN>
+    __device__ __forceinline__ static void load(const float *ring, KS ks, const LN &ln, double (&av)[TPL],
+                                                double &x) {
+        static_assert(sizeof(ln.tap) == TPL * sizeof(int), "lane table of another tap count");
+        const float *sp = ring + (int)ks * SLOT;
+#pragma unroll
+        for (int m = 0; m < TPL; ++m) av[m] = (double)sp[ln.tap[m]];
+        x = (double)sp[ln.x];
+    }
+};
+
 // Number of leading steps (a multiple of NS) whose issued rows all lie inside
 // their chunks: every chunk slot of the wave must be active with at least
 // U + D rows.  my_len: the lane's chunk rows (0 if inactive).
@@ -208,20 +446,26 @@ __device__ __forceinline__ void ring_loop(RR &rr, float *ring, int L, int U, Bod
 // of RerunLds<M, G>::BYTES bytes.  xs == nullptr: from the zero state; s ==
 // nullptr: no output samples; zall: every chunk's final state, zall[c][k] =
 // s(end - 1 - k) (the chunk's zero-state offset z_c when run from zero).
-template <int M, int G>
+// Row ring of CPW chunks: per-sample rows, or frame-rate rows (FR) interpolated in LDS.
+template <int M, int CPW, bool DESC, bool FR>
+using RingOf = std::conditional_t<FR, FrameRing<M, CPW, DESC>, RowRing<M, CPW, DESC>>;
+
+template <int M, int G, bool FR = false>
 struct RerunLds {
-    static constexpr int BYTES = RowRing<M, 64 / G, false>::FLOATS * 4;
+    static constexpr int BYTES = RingOf<M, 64 / G, false, FR>::FLOATS * 4;
 };
 
-template <int M, int G>
+// FR: a holds frame-rate rows [B][F][M] and frl is the frame staging area
+// (frame_lds_bytes(64 / G, M, S.nf) bytes of LDS).
+template <int M, int G, bool FR = false>
 __device__ __forceinline__ void rerun_chunks(Seqs S, const float *__restrict__ e, const float *__restrict__ a,
                                              const double *__restrict__ xs, float *__restrict__ s,
                                              double *__restrict__ zf, const float *__restrict__ zero,
                                              int64_t nch, int64_t blk, float *ring,
-                                             double *__restrict__ zall = nullptr) {
+                                             double *__restrict__ zall = nullptr, unsigned char *frl = nullptr) {
     constexpr int CPW = 64 / G;
     constexpr int TPL = (M + G - 1) / G;
-    using RR = RowRing<M, CPW, false>;
+    using RR = RingOf<M, CPW, false, FR>;
 
     const int lane = threadIdx.x;
     const int slot = lane / G, r = lane % G;
@@ -245,7 +489,10 @@ __device__ __forceinline__ void rerun_chunks(Seqs S, const float *__restrict__ e
         hist[m] = (active && k < M && xs) ? xs[gc * M + k] : 0.0;
     }
     RR rr;
-    rr.init(a, e, zero, lane, base, len, G, 0, coef_row(S, b, base), S.ti);
+    if constexpr (FR)
+        rr.init(a, e, zero, lane, base, len, G, 0, b, c * S.L, S, frl);
+    else
+        rr.init(a, e, zero, lane, base, len, G, 0, coef_row(S, b, base), S.ti);
     const typename RR::template Lanes<TPL> ln(slot, r);
     const int L = S.L;
     for (int u = 0; u < RR::D; ++u) rr.issue(ring, u);
@@ -302,14 +549,15 @@ __device__ __forceinline__ void rerun_chunks(Seqs S, const float *__restrict__ e
     }
 }
 
-template <int M, int G>
+template <int M, int G, bool FR = false>
 __global__ __launch_bounds__(64) void k_fwd_rerun2(Seqs S, const float *__restrict__ e,
                                                    const float *__restrict__ a,
                                                    const double *__restrict__ xs,
                                                    float *__restrict__ s, double *__restrict__ zf,
                                                    const float *__restrict__ zero, int64_t nch) {
-    __shared__ __attribute__((aligned(16))) float ring[RerunLds<M, G>::BYTES / 4];
-    rerun_chunks<M, G>(S, e, a, xs, s, zf, zero, nch, blockIdx.x, ring);
+    __shared__ __attribute__((aligned(16))) float ring[RerunLds<M, G, FR>::BYTES / 4];
+    extern __shared__ __attribute__((aligned(16))) unsigned char rerun_dyn[];  // FR: frame staging
+    rerun_chunks<M, G, FR>(S, e, a, xs, s, zf, zero, nch, blockIdx.x, ring, nullptr, rerun_dyn);
 }
 
 // Adjoint rerun of each chunk (push form of Eq. 12, descending), from the
@@ -321,8 +569,17 @@ __global__ __launch_bounds__(64) void k_fwd_rerun2(Seqs S, const float *__restri
 // wave with coalesced stores.
 //
 // Dynamic LDS: [CPW][M + L] floats of s (ssh[M + t] = s(t), ssh[M-1-k] =
-// s(-1-k)) followed by [CPW][L] floats of ghat.
-template <int M, int G>
+// s(-1-k)) followed by [CPW][L] floats of ghat (and, with FR, the frame staging
+// area at the next 16-byte boundary: emit_frame_lds_offset).
+//
+// tipart: time-invariant coefficients, each chunk's share of dL/da [nch][M];
+// with FR (frame-rate rows in a), each chunk's share of dL/dA for the S.nf
+// frames from its first one, [nch][S.nf][M] (ga is then unused).
+__host__ __device__ constexpr size_t emit_frame_lds_offset(int cpw, int m, int L) {
+    return ((size_t)cpw * (m + 2 * (size_t)L) * sizeof(float) + 15) & ~(size_t)15;
+}
+
+template <int M, int G, bool FR = false>
 __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restrict__ g,
                                                   const float *__restrict__ a, const float *__restrict__ s_in,
                                                   const double *__restrict__ xs,
@@ -332,20 +589,21 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
                                                   const float *__restrict__ zero, int64_t nch) {
     constexpr int CPW = 64 / G;
     constexpr int TPL = (M + G - 1) / G;
-    using RD = RowRing<M, CPW, true>;
+    // frame-rate rows: 12 steps in flight keep four blocks of the training shape per CU
+    using RD = std::conditional_t<FR, FrameRing<M, CPW, true, 12>, RowRing<M, CPW, true>>;
     __shared__ __attribute__((aligned(16))) float ring[RD::FLOATS];
-    extern __shared__ float ssh_dyn[];
+    extern __shared__ __attribute__((aligned(16))) float ssh_dyn[];
 
     const int lane = threadIdx.x;
     const int slot = lane / G, r = lane % G;
     const int L = S.L;
     const int64_t gc = (int64_t)blockIdx.x * CPW + slot;
     bool active = gc < nch;
-    int64_t len = 0, base = 0, goff = 0, b = 0;
+    int64_t len = 0, base = 0, goff = 0, b = 0, c = 0;
     if (active) {
         b = seq_of_chunk(S, gc);
         const SeqView v = seq_view(S, b);
-        const int64_t c = gc - v.cbase;
+        c = gc - v.cbase;
         active = c < v.C;
         if (active) {
             base = v.start + c * L;
@@ -375,7 +633,11 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
         }
     }
     RD rd;
-    rd.init(a, g, zero, lane, base, len, G, goff, coef_row(S, b, base), S.ti);
+    if constexpr (FR)
+        rd.init(a, g, zero, lane, base, len, G, goff, b, c * L, S,
+                reinterpret_cast<unsigned char *>(ssh_dyn) + emit_frame_lds_offset(CPW, M, L));
+    else
+        rd.init(a, g, zero, lane, base, len, G, goff, coef_row(S, b, base), S.ti);
     for (int u = 0; u < RD::D; ++u) rd.issue(ring, u);
     RD::wait_next();  // row 0 (sample len - 1)
     double av[TPL], gx;
@@ -411,8 +673,72 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
     });
     __syncthreads();
 
+    // ---- frame-rate coefficients: with w = n / hop the chunk's samples t = q*hop + n
+    // give dL/dA[q] += sum (1 - w) dL/da(t) and dL/dA[q+1] += sum w dL/da(t), from
+    // P = sum -ghat(t) s(t-i) and Q = sum n (-ghat(t) s(t-i)) over each frame's samples
+    if constexpr (FR) {
+        if (tipart) {
+            // The wave walks t over the stretches between consecutive boundaries of
+            // any of its chunks (a frame's end or a chunk's end), accumulating
+            // without branches; at a boundary only the lanes whose boundary it is
+            // flush their shares.  Lanes past their chunk's end add zeros.
+            constexpr int NONE = 0x7fffffff;
+            const int hop = S.hop, nfr = S.nf;
+            const int ln = (int)len;  // 0 for an inactive chunk
+            double P[TPL], Q[TPL], cr[TPL];
+#pragma unroll
+            for (int m = 0; m < TPL; ++m) P[m] = Q[m] = cr[m] = 0.0;
+            double *out = tipart + gc * nfr * M;
+            int n = active ? (int)((c * L) % hop) : 0;  // phase of sample t in its frame
+            int qq = 0, t = 0;
+            int tb_l = ln > 0 ? min(hop - n, ln) : NONE;  // this lane's next boundary
+            int tb = wave_min_i32(tb_l);
+            while (tb != NONE) {
+                double nd = (double)n;
+                const int t_start = t;
+                for (; t < tb; ++t) {
+                    const double gt = t < ln ? (double)gsh[t] : 0.0;
+                    const double gn = gt * nd;
+#pragma unroll
+                    for (int m = 0; m < TPL; ++m) {
+                        const int i = r * TPL + m;  // tap i + 1
+                        const double sv = (double)ssh[M + t - 1 - (i < M ? i : 0)];
+                        P[m] = fma(-gt, sv, P[m]);
+                        Q[m] = fma(-gn, sv, Q[m]);
+                    }
+                    nd += 1.0;
+                }
+                n += tb - t_start;
+                if (tb_l == tb) {  // the chunk's part of frame q ends here
+#pragma unroll
+                    for (int m = 0; m < TPL; ++m) {
+                        const int i = r * TPL + m;
+                        const double qh = Q[m] / hop;
+                        if (i < M) out[qq * M + i] = cr[m] + P[m] - qh;
+                        cr[m] = qh;
+                        P[m] = Q[m] = 0.0;
+                    }
+                    ++qq;
+                    if (n == hop) n = 0;
+                    tb_l = t < ln ? min(t + hop - n, ln) : NONE;
+                }
+                tb = wave_min_i32(tb_l);
+            }
+            if (active) {
+#pragma unroll
+                for (int m = 0; m < TPL; ++m) {
+                    const int i = r * TPL + m;
+                    if (i < M) {
+                        out[qq * M + i] = cr[m];
+                        for (int z = qq + 1; z < nfr; ++z) out[z * M + i] = 0.0;
+                    }
+                }
+            }
+        }
+    }
+
     // ---- time-invariant coefficients: the chunk's share of dL/da_i = -sum_t ghat(t) s(t-i)
-    if (tipart) {
+    if (!FR && tipart) {
         double acc[TPL];
 #pragma unroll
         for (int m = 0; m < TPL; ++m) acc[m] = 0.0;
@@ -484,6 +810,30 @@ __global__ __launch_bounds__(64) void k_ti_reduce(Seqs S, const double *__restri
     double sum = 0.0;
     for (int64_t c = 0; c < v.C; ++c) sum += tipart[(v.cbase + c) * M + i];
     ga[b * M + i] = (float)sum;
+}
+
+// dL/dA[b][q][i] for frame-rate coefficients (uniform batches): the shares of
+// the chunks whose staged frames include q, summed in float64.  Chunk c stages
+// frames floor(c L / hop) .. + nf - 1.  One thread per output.
+template <int M>
+__global__ __launch_bounds__(256) void k_frames_reduce(Seqs S, const double *__restrict__ part,
+                                                       float *__restrict__ gA) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = S.F * M;
+    if (idx >= S.n * per) return;
+    const int64_t b = idx / per, rem = idx - b * per;
+    const int64_t q = rem / M;
+    const int i = (int)(rem - q * M);
+    const int64_t L = S.L, hop = S.hop, nfr = S.nf;
+    const int64_t C = (S.T + L - 1) / L;
+    const int64_t chi = min(C - 1, ((q + 1) * hop - 1) / L);  // last chunk starting at or before frame q
+    double sum = 0.0;
+    for (int64_t c = chi; c >= 0; --c) {
+        const int64_t k = q - (c * L) / hop;
+        if (k >= nfr) break;  // earlier chunks stage only earlier frames
+        sum += part[((b * C + c) * nfr + k) * M + i];
+    }
+    gA[idx] = (float)sum;
 }
 
 // Time-invariant coefficients: every full chunk of sequence b has the same

@@ -122,20 +122,28 @@ __device__ __forceinline__ void matmul_rm(const double *A, const double *B, doub
 
 // ---------------------------------------------------------------- forward scan
 
-template <int M, int LPC, int CPL, int R>
+template <int M, int LPC, int CPL, int R, bool FR = false>
 struct FwdScanShape {
     static constexpr int CPW = 64 / LPC;
     // DMA ring: each step moves one coefficient row (M floats) and one
     // excitation value for each of the CPW chunks into a ring slot of
-    // DMA_N x 64 floats; D steps are kept in flight.
+    // DMA_N x 64 floats; D steps are kept in flight.  FR (frame-rate rows):
+    // the ring moves only the excitation (one 64-float slot per step), and an
+    // M-step block starting at row t0 first produces the interpolated rows
+    // t0+1 .. t0+M (the rows its steps read) into an LDS row buffer of M x CW
+    // floats (row t0 was read by the previous block's last step).
     static constexpr int ROWF = CPW * M + CPW;           // floats per step slot actually used
-    static constexpr int DMA_N = (ROWF + 63) / 64;       // dword DMA instructions per step
+    static constexpr int NC = (CPW * M + 63) / 64;
+    static constexpr int CW = (CPW * M + 3) / 4 * 4;     // floats per produced row
+    static constexpr int DMA_N = FR ? 1 : (ROWF + 63) / 64;  // dword DMA instructions per step
     static constexpr int D = (63 / DMA_N) < 15 ? (63 / DMA_N) : 15;  // steps in flight (vmcnt <= 63)
+    static constexpr int SLOTF = DMA_N * 64;                         // floats per ring slot
+    static constexpr int XOFF = FR ? 0 : CPW * M;                    // slot float of chunk 0's excitation
     // ring slots: M when that suffices, so that the slot of row t0 + K in the
     // M-step unrolled loop (t0 a multiple of M) is the constant K
     static constexpr int NS = M >= D + 1 ? M : D + 1;
     static constexpr bool CONST_SLOTS = NS == M;
-    static constexpr int RING_BYTES = NS * DMA_N * 64 * 4;
+    static constexpr int RING_BYTES = NS * SLOTF * 4 + (FR ? M * CW * 4 : 0);
     static constexpr int RM = R * M;
     static constexpr bool VEC2 = (M % 2 == 0);
     static constexpr int WORDS = VEC2 ? RM / 2 : RM;
@@ -151,15 +159,18 @@ struct FwdScanShape {
 // s_waitcnt immediate that waits for vmcnt <= n only (gfx9 encoding).
 constexpr int waitcnt_vm(int n) { return (n & 0xF) | (0x7 << 4) | (0xF << 8) | (((n >> 4) & 0x3) << 14); }
 
-template <int M, int LPC, int CPL, int R>
+// FR: a holds frame-rate rows [B][F][M], interpolated per sample in LDS
+// (dynamic LDS: the frame staging area, frame_lds_bytes(CPW, M, S.nf) bytes).
+template <int M, int LPC, int CPL, int R, bool FR = false>
 __global__ __launch_bounds__(64) void k_fwd_local(
     Seqs S, Groups GR, const float *__restrict__ e, const float *__restrict__ a, double *__restrict__ phiT,
     double *__restrict__ zbuf, double *__restrict__ aggbuf, int chain) {
-    using SH = FwdScanShape<M, LPC, CPL, R>;
+    using SH = FwdScanShape<M, LPC, CPL, R, FR>;
     constexpr int CPW = SH::CPW;
     constexpr int MM = M * M;
     static_assert(M % R == 0, "slab rows must divide M");
     __shared__ __attribute__((aligned(16))) unsigned char lds_raw[SH::LDS_BYTES];
+    extern __shared__ __attribute__((aligned(16))) unsigned char fwd_dyn[];
     double *PT = reinterpret_cast<double *>(lds_raw);  // aggregate, column-major
     double *FT = PT + MM;                              // current chunk's Phi, column-major
     double *QT = FT + MM;                              // product scratch
@@ -200,9 +211,14 @@ __global__ __launch_bounds__(64) void k_fwd_local(
 #pragma unroll
         for (int i = 0; i < SH::DMA_N; ++i) {
             const int j = 64 * i + lane;
-            const float *p = a;  // valid dummy for unused slots
+            const float *p = e;  // valid dummy for unused slots
             int st = 0;
-            if (j < CPW * M) {
+            if constexpr (FR) {
+                if (lane < CPW && lane < nbasis) {  // excitation of chunk `lane`
+                    p = e + v.start + (c0 + lane) * L;
+                    st = 1;
+                }
+            } else if (j < CPW * M) {
                 const int k = j / M, f = j % M;
                 if (k < nbasis) {
                     p = a + coef_row(S, b, v.start + (c0 + k) * L) * M + f;
@@ -223,7 +239,20 @@ __global__ __launch_bounds__(64) void k_fwd_local(
         float *ring = reinterpret_cast<float *>(lds_raw);
         typedef __attribute__((address_space(3))) float lfloat;
         lfloat *ring_l = (lfloat *)lds_raw;
-        constexpr int SLOTF = SH::DMA_N * 64;  // floats per ring slot
+        constexpr int SLOTF = SH::SLOTF;  // floats per ring slot
+        // FR: produced rows t0+1 .. t0+M of the block starting at row t0 (row
+        // t0+1+k at k; row 0 alone at 0 before the first block)
+        lfloat *rows_l = ring_l + SH::NS * SLOTF;
+        const float *rows = ring + SH::NS * SLOTF;
+        FrameCoefs<M, CPW, false> fc;
+        auto produce_block = [&]() {
+#pragma unroll 1
+            for (int k = 0; k < M; ++k) fc.produce(rows_l + k * SH::CW);
+        };
+        if constexpr (FR) {
+            fc.init(a, S, fwd_dyn, lane, slot, sub == 0, b, (c0 + slot) * L, act ? L : 0);
+            fc.produce(rows_l);
+        }
         // Rows are issued in order t = 0, 1, ...; every chunk of the basis pass
         // has exactly L rows, and look-ahead issues past row L-1 repeat that row.
         auto issue = [&](int t, int slotn) {  // row min(t, L-1) of every chunk into ring slot slotn
@@ -245,23 +274,26 @@ __global__ __launch_bounds__(64) void k_fwd_local(
                 src[i] += step[i];
             }
         };
-        // row t's coefficients and excitation (ring slot slotn), read during step t-1
-        auto load_row = [&](int slotn, float (&rv)[M], float &ex) {
+        // row t's coefficients and excitation (ring slot slotn; FR: produced row
+        // rk), read during step t-1
+        auto load_row = [&](int slotn, int rk, float (&rv)[M], float &ex) {
             const float *slotp = ring + slotn * SLOTF;
-            const float *row = slotp + (slot < CPW ? slot : 0) * M;
+            const float *row = FR ? rows + rk * SH::CW + (slot < CPW ? slot : 0) * M
+                                  : slotp + (slot < CPW ? slot : 0) * M;
 #pragma unroll
             for (int i = 0; i < M; ++i) rv[i] = row[i];
-            ex = slotp[CPW * M + (slot < CPW ? slot : 0)];
+            ex = slotp[SH::XOFF + (slot < CPW ? slot : 0)];
         };
         for (int t = 0; t < SH::D; ++t) issue(t, t % SH::NS);
         __builtin_amdgcn_s_waitcnt(waitcnt_vm(SH::DMA_N * (SH::D - 1)));  // row 0 has landed
         float rv[M], ex;
-        load_row(0, rv, ex);
+        load_row(0, 0, rv, ex);
         // blocks of M steps whose issued rows (up to t0 + M - 1 + D) all lie inside the chunk
         const int Lfast = SH::CONST_SLOTS && L > SH::D ? (L - SH::D) / M * M : 0;
         int t0 = 0;
         auto block = [&](auto fastc) {
             constexpr bool F = decltype(fastc)::value;
+            if constexpr (FR) produce_block();
             Unroll<M, 0>::run([&](auto kc) {
                 constexpr int K = decltype(kc)::value;
                 const int t = t0 + K;
@@ -273,7 +305,7 @@ __global__ __launch_bounds__(64) void k_fwd_local(
                     issue(t + SH::D, SH::CONST_SLOTS ? (K + SH::D) % SH::NS : (t + SH::D) % SH::NS);
                 __builtin_amdgcn_s_waitcnt(waitcnt_vm(SH::DMA_N * (SH::D - 1)));  // row t+1 has landed
                 float nrv[M], nex;
-                load_row(SH::CONST_SLOTS ? (K + 1) % SH::NS : (t + 1) % SH::NS, nrv, nex);
+                load_row(SH::CONST_SLOTS ? (K + 1) % SH::NS : (t + 1) % SH::NS, K, nrv, nex);
                 double acc[CPL][2];
 #pragma unroll
                 for (int m = 0; m < CPL; ++m) {
@@ -374,23 +406,24 @@ __global__ __launch_bounds__(64) void k_fwd_local(
 
 // ---------------------------------------------------------------- adjoint scan
 
-template <int M, int G, int R>
+template <int M, int G, int R, bool FR = false>
 struct BwdScanShape {
     static constexpr int CPW = 64 / G;
-    using RD = RowRing<M, CPW, true>;
+    using RD = RingOf<M, CPW, true, FR>;
     static constexpr int RING_BYTES = RD::FLOATS * 4;
     static constexpr int MAT_BYTES = (3 * M * M + 4 * M + CPW * M) * 8;
     static constexpr int LDS_BYTES = RING_BYTES > MAT_BYTES ? RING_BYTES : MAT_BYTES;
 };
 
-// One wave handles adjoint group tid_; lds_raw: SH::LDS_BYTES bytes of LDS.
-template <int M, int G, int R>
+// One wave handles adjoint group tid_; lds_raw: SH::LDS_BYTES bytes of LDS;
+// FR: a holds frame-rate rows and frl is the frame staging area.
+template <int M, int G, int R, bool FR = false>
 __device__ __forceinline__ void bwd_local_group(Seqs S, Groups GR, const float *__restrict__ g_in,
                                                 const float *__restrict__ a, const double *__restrict__ phiT,
                                                 double *__restrict__ qbuf, double *__restrict__ aggbuf,
                                                 const float *__restrict__ zero, int chain, int64_t tid_,
-                                                unsigned char *lds_raw) {
-    using SH = BwdScanShape<M, G, R>;
+                                                unsigned char *lds_raw, unsigned char *frl = nullptr) {
+    using SH = BwdScanShape<M, G, R, FR>;
     using RD = typename SH::RD;
     constexpr int CPW = SH::CPW;
     constexpr int TPL = (M + G - 1) / G;
@@ -430,7 +463,10 @@ __device__ __forceinline__ void bwd_local_group(Seqs S, Groups GR, const float *
     for (int m = 0; m < TPL; ++m) P[m] = 0.0;
     {
         RD rd;
-        rd.init(a, g_in, zero, lane, base, len, G, gshare_offset(S, b), coef_row(S, b, base), S.ti);
+        if constexpr (FR)
+            rd.init(a, g_in, zero, lane, base, len, G, gshare_offset(S, b), b, c * L, S, frl);
+        else
+            rd.init(a, g_in, zero, lane, base, len, G, gshare_offset(S, b), coef_row(S, b, base), S.ti);
         const typename RD::template Lanes<TPL> ln(slot, r);
         for (int u = 0; u < RD::D; ++u) rd.issue(ring, u);
         RD::wait_next();  // row 0 (the chunk's last sample)
@@ -533,28 +569,30 @@ __device__ __forceinline__ void bwd_local_group(Seqs S, Groups GR, const float *
     }
 }
 
-template <int M, int G, int R>
+template <int M, int G, int R, bool FR = false>
 __global__ __launch_bounds__(64) void k_bwd_local(Seqs S, Groups GR, const float *__restrict__ g_in,
                                                   const float *__restrict__ a, const double *__restrict__ phiT,
                                                   double *__restrict__ qbuf, double *__restrict__ aggbuf,
                                                   const float *__restrict__ zero, int chain) {
-    __shared__ __attribute__((aligned(16))) unsigned char lds_raw[BwdScanShape<M, G, R>::LDS_BYTES];
-    bwd_local_group<M, G, R>(S, GR, g_in, a, phiT, qbuf, aggbuf, zero, chain, blockIdx.x, lds_raw);
+    __shared__ __attribute__((aligned(16))) unsigned char lds_raw[BwdScanShape<M, G, R, FR>::LDS_BYTES];
+    extern __shared__ __attribute__((aligned(16))) unsigned char bwd_dyn[];  // FR: frame staging
+    bwd_local_group<M, G, R, FR>(S, GR, g_in, a, phiT, qbuf, aggbuf, zero, chain, blockIdx.x, lds_raw, bwd_dyn);
 }
 
 // The adjoint's local scan together with the recompute of s from the saved
 // chunk entry states (into s_out), in one launch: neither needs the other, and
 // interleaving their blocks gives every SIMD two independent waves whose
 // latencies overlap.  Blocks alternate (scan, rerun) while both kinds remain.
-template <int M, int G, int R>
+template <int M, int G, int R, bool FR = false>
 __global__ __launch_bounds__(64) void k_bwd_front(Seqs S, Groups GR, const float *__restrict__ g_in,
                                                   const float *__restrict__ a, const double *__restrict__ phiT,
                                                   double *__restrict__ qbuf, double *__restrict__ aggbuf,
                                                   const float *__restrict__ zero, int chain,
                                                   const float *__restrict__ e, const double *__restrict__ xs,
                                                   float *__restrict__ s_out, int64_t nch) {
-    constexpr int B1 = BwdScanShape<M, G, R>::LDS_BYTES, B2 = RerunLds<M, G>::BYTES;
+    constexpr int B1 = BwdScanShape<M, G, R, FR>::LDS_BYTES, B2 = RerunLds<M, G, FR>::BYTES;
     __shared__ __attribute__((aligned(16))) unsigned char lds_raw[B1 > B2 ? B1 : B2];
+    extern __shared__ __attribute__((aligned(16))) unsigned char front_dyn[];  // FR: frame staging
     const int64_t nscan = GR.ngroups, nrun = (nch + 64 / G - 1) / (64 / G);
     const int64_t both = nscan < nrun ? nscan : nrun;
     const int64_t i = blockIdx.x;
@@ -568,9 +606,10 @@ __global__ __launch_bounds__(64) void k_bwd_front(Seqs S, Groups GR, const float
         j = i - both;
     }
     if (scan)
-        bwd_local_group<M, G, R>(S, GR, g_in, a, phiT, qbuf, aggbuf, zero, chain, j, lds_raw);
+        bwd_local_group<M, G, R, FR>(S, GR, g_in, a, phiT, qbuf, aggbuf, zero, chain, j, lds_raw, front_dyn);
     else
-        rerun_chunks<M, G>(S, e, a, xs, s_out, nullptr, zero, nch, j, reinterpret_cast<float *>(lds_raw));
+        rerun_chunks<M, G, FR>(S, e, a, xs, s_out, nullptr, zero, nch, j, reinterpret_cast<float *>(lds_raw),
+                               nullptr, front_dyn);
 }
 
 }  // namespace tvlp

@@ -197,6 +197,44 @@ class Plan:
                                               _ptr(saved), _ptr(ge), _ptr(ga), _ptr(gz), _stream(g.device)))
         return ge, ga, gz
 
+    def forward_frames(self, e: torch.Tensor, A: torch.Tensor, hop: int, zi: Optional[torch.Tensor] = None,
+                       want_zf: bool = False, save: bool = True):
+        """Frame-rate coefficients: e [B,T], A [B,F,M] (frame q at sample q*hop, F =
+        coef_frames_count(T, hop)), interpolated per sample inside the kernels
+        -> (s, zf or None, saved or None)."""
+        _need(e, "e", torch.float32, 2)
+        _need(A, "A", torch.float32, 3)
+        B, T = e.shape
+        F = coef_frames_count(T, hop)
+        if A.shape != (B, F, self.M):
+            raise ValueError(f"A must have shape {(B, F, self.M)}, got {tuple(A.shape)}")
+        if zi is not None:
+            _need(zi, "zi", torch.float64, 2)
+        s = torch.empty_like(e)
+        zf = torch.empty((B, self.M), dtype=torch.float64, device=e.device) if want_zf else None
+        saved = torch.empty(self.saved_bytes(B, T), dtype=torch.uint8, device=e.device) if save else None
+        _lib.check(_lib.load().lp_forward_frames(self._h, B, T, int(hop), _ptr(e), _ptr(A), _ptr(zi), _ptr(s),
+                                                 _ptr(zf), _ptr(saved), _stream(e.device)))
+        return s, zf, saved
+
+    def backward_frames(self, g: torch.Tensor, A: torch.Tensor, hop: int, e: Optional[torch.Tensor],
+                        saved: torch.Tensor, s: Optional[torch.Tensor] = None, zi: Optional[torch.Tensor] = None,
+                        need_e: bool = True, need_a: bool = True, need_zi: bool = False):
+        """Frame-rate coefficients: returns (grad_e [B,T], grad_A [B,F,M], grad_zi [B,M])."""
+        _need(g, "g", torch.float32, 2)
+        _need(A, "A", torch.float32, 3)
+        B, T = g.shape
+        F = coef_frames_count(T, hop)
+        if A.shape != (B, F, self.M):
+            raise ValueError(f"A must have shape {(B, F, self.M)}, got {tuple(A.shape)}")
+        ge = torch.empty_like(g) if need_e else None
+        gA = torch.empty_like(A) if need_a else None
+        gz = torch.empty((B, self.M), dtype=torch.float64, device=g.device) if need_zi else None
+        _lib.check(_lib.load().lp_backward_frames(self._h, B, T, int(hop), _ptr(g), _ptr(A), _ptr(e), _ptr(zi),
+                                                  _ptr(s), _ptr(saved), _ptr(ge), _ptr(gA), _ptr(gz),
+                                                  _stream(g.device)))
+        return ge, gA, gz
+
     def backward(self, g: torch.Tensor, a: torch.Tensor, e: Optional[torch.Tensor], saved: torch.Tensor,
                  s: Optional[torch.Tensor] = None, zi: Optional[torch.Tensor] = None,
                  need_e: bool = True, need_a: bool = True, need_zi: bool = False):
@@ -365,6 +403,11 @@ def backward_plain(g: torch.Tensor, a: torch.Tensor, s: torch.Tensor, zi: Option
     _lib.check(_lib.load().lp_backward_plain(M, B, T, _ptr(g), _ptr(a), _ptr(zi), _ptr(s), _ptr(ge), _ptr(ga),
                                              _ptr(gz), _stream(g.device)))
     return ge, ga, gz
+
+
+def coef_frames_count(T: int, hop: int) -> int:
+    """Frame-rate coefficient rows for a length-T signal: (T - 1) // hop + 2."""
+    return int(_lib.load().lp_coef_frames_count(int(T), int(hop)))
 
 
 def frames_count(T: int, hop: int) -> int:

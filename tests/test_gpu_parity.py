@@ -506,3 +506,110 @@ def test_framewise_training_shape_sampled(tv):
         assert rms_rel(host(s[b]), s_ref[0]) <= TOL, b
         assert rms_rel(host(ge[b]), ge_ref[0]) <= TOL, b
         assert rms_rel(host(gaf[b]), gaf_ref[0]) <= TOL, b
+
+
+# ---------------------------------------------------------------- frame-rate coefficients
+
+def _frame_inputs(B, T, M, hop, seed, kappa=0.9, gamma=0.98, sigma=0.01):
+    """Frame-rate LPCs from a bounded random walk of reflection coefficients (step
+    N(0, sigma^2) per frame, |k| <= kappa), step-up at the frame rate and
+    bandwidth expansion, plus excitation and upstream gradient.  Interpolating
+    LPCs (unlike reflection coefficients) can leave the stable region between
+    unrelated frames; neighbouring frames this close keep every interpolated row
+    inside radius ~gamma."""
+    from synth.inputs import reflection_to_lpc
+    rng = np.random.default_rng(seed)
+    F = oracle.coef_frames_count(T, hop)
+    k = np.empty((B, F, M))
+    k[:, 0] = rng.uniform(-kappa, kappa, size=(B, M))
+    steps = rng.normal(0.0, sigma, size=(B, F, M))
+    for f in range(1, F):
+        k[:, f] = np.clip(k[:, f - 1] + steps[:, f], -kappa, kappa)
+    A = (reflection_to_lpc(k) * gamma ** np.arange(1, M + 1)).astype(np.float32)
+    e = make_excitation(rng, B, T)
+    g = make_upstream_grad(rng, B, T)
+    return e, A, g
+
+
+@pytest.mark.parametrize("B,T,M,L,hop,with_zi,store_s,chained", [
+    (3, 5000, 22, 418, 240, False, False, False),
+    (2, 3001, 16, 256, 100, True, True, False),
+    (2, 2000, 22, 264, 37, False, False, True),
+    (4, 1500, 8, 96, 240, False, False, False),
+    (1, 777, 32, 128, 50, True, False, False),
+    (2, 4000, 6, 60, 16, False, True, False),
+    (3, 999, 1, 64, 10, False, False, False),
+    (2, 200, 22, 418, 240, False, False, False),
+    (2, 1, 12, 48, 240, False, False, False),
+])
+def test_frame_rate_coefficients_match_oracle(tv, B, T, M, L, hop, with_zi, store_s, chained):
+    """Frame-rate rows A [B,F,M] interpolated inside the kernels: s, grad_e,
+    grad_A [B,F,M] and grad_zi against the oracle (upsampling, per-sample filter,
+    adjoint of the upsampling), over several chunks per frame and frames per chunk,
+    ragged and short sequences."""
+    e, A, g = _frame_inputs(B, T, M, hop, seed=T + M + hop)
+    zi = np.random.default_rng(9).standard_normal((B, M)) if with_zi else None
+    s_ref, zf_ref = oracle.lp_forward_frames(e, A, hop, zi)
+    ge_ref, gA_ref, gz_ref = oracle.lp_backward_frames(g, A, s_ref, hop, zi, need_grad_zi=with_zi)
+    plan = tv.Plan(M, dev(), L, chained=chained)
+    e_d, A_d, g_d, zi_d = to_dev(e), to_dev(A), to_dev(g), to_dev(zi)
+    s, zf, saved = plan.forward_frames(e_d, A_d, hop, zi_d, want_zf=True)
+    ge, gA, gz = plan.backward_frames(g_d, A_d, hop, e_d, saved, s=s if store_s else None, zi=zi_d,
+                                      need_zi=with_zi)
+    plan.check_status()
+    torch.cuda.synchronize()
+    assert per_seq_err(host(s), s_ref) <= TOL
+    assert rms_rel(host(zf), zf_ref) <= TOL
+    assert per_seq_err(host(ge), ge_ref) <= TOL
+    for b in range(B):
+        assert rms_rel(host(gA)[b], gA_ref[b]) <= TOL, b
+    if with_zi:
+        assert rms_rel(host(gz), gz_ref) <= TOL
+
+
+def test_frame_rate_matches_per_sample_rows(tv):
+    """The in-kernel interpolation against the per-sample path fed with the same
+    rows upsampled on the host: equal up to the interpolation's float32 rounding."""
+    B, T, M, hop = 4, 6000, 22, 240
+    e, A, g = _frame_inputs(B, T, M, hop, seed=77)
+    a = oracle.upsample_frames(A, T, hop).astype(np.float32)
+    plan = tv.Plan(M, dev(), 418)
+    e_d, A_d, a_d, g_d = to_dev(e), to_dev(A), to_dev(a), to_dev(g)
+    s_f, _, saved_f = plan.forward_frames(e_d, A_d, hop)
+    ge_f, _, _ = plan.backward_frames(g_d, A_d, hop, e_d, saved_f)
+    s_p, _, saved_p = plan.forward(e_d, a_d)
+    ge_p, _, _ = plan.backward(g_d, a_d, e_d, saved_p, need_a=False)
+    plan.check_status()
+    torch.cuda.synchronize()
+    assert per_seq_err(host(s_f), host(s_p).astype(np.float64)) <= 1e-5
+    assert per_seq_err(host(ge_f), host(ge_p).astype(np.float64)) <= 1e-5
+
+
+def test_frame_rate_training_shape_sampled(tv):
+    """B=64, T=48000, M=22, hop 240 (one frame per 10 ms at 24 kHz), recompute
+    adjoint at the default chunk length; sampled sequences against the oracle."""
+    B, T, M, hop = 64, 48000, 22, 240
+    e, A, g = _frame_inputs(B, T, M, hop, seed=2406, kappa=0.95)
+    plan = tv.Plan(M, dev())
+    e_d, A_d, g_d = to_dev(e), to_dev(A), to_dev(g)
+    s, _, saved = plan.forward_frames(e_d, A_d, hop)
+    ge, gA, _ = plan.backward_frames(g_d, A_d, hop, e_d, saved)
+    plan.check_status()
+    torch.cuda.synchronize()
+    for b in (0, 17, 63):
+        s_ref, _ = oracle.lp_forward_frames(e[b:b + 1], A[b:b + 1], hop)
+        ge_ref, gA_ref, _ = oracle.lp_backward_frames(g[b:b + 1], A[b:b + 1], s_ref, hop)
+        assert rms_rel(host(s[b]), s_ref[0]) <= TOL, b
+        assert rms_rel(host(ge[b]), ge_ref[0]) <= TOL, b
+        assert rms_rel(host(gA[b]), gA_ref[0]) <= TOL, b
+
+
+def test_frame_rate_rejects_hop_too_short_for_lds(tv):
+    """hop 1 at chunk length 418 would stage 420 frame rows per chunk: rejected by
+    the host before any launch."""
+    B, T, M = 1, 1000, 22
+    plan = tv.Plan(M, dev(), 418)
+    e = torch.zeros((B, T), dtype=torch.float32, device=dev())
+    A = torch.zeros((B, tv.coef_frames_count(T, 1), M), dtype=torch.float32, device=dev())
+    with pytest.raises(Exception, match="hop"):
+        plan.forward_frames(e, A, 1)
