@@ -167,9 +167,11 @@ struct RowRing {
 // A wave first stages the frame rows its chunks touch in LDS (per chunk k, nf
 // rows starting at the chunk's first frame), then produces one interpolated row
 // per ring step with one FMA and one LDS store per 64 words, in place of a DMA
-// of the per-sample row.  Every lane word keeps its frame row, slope and phase in
-// registers; frame changes happen at a handful of steps per chunk, at which the
-// affected words reload from the staged rows.
+// of the per-sample row.  Every lane word keeps its frame row, slope and phase
+// offset in registers: at wave-uniform issue count p the phase is p + c
+// (descending c - p), an exact integer in float32, and the word is
+// fma(phase, slope, row), one rounding.  Frame changes happen at a handful of
+// steps per chunk, at which the affected words reload from the staged rows.
 
 struct FrameInfo {
     int64_t arow;  // element offset of the chunk's sequence in A (b * F * M)
@@ -198,7 +200,7 @@ struct FrameCoefs {
     static constexpr int NC = (CPW * M + 63) / 64;  // LDS stores per produced row
     static constexpr int NONE = 0x7fffffff;
     typedef __attribute__((address_space(3))) float lfloat;
-    float a0[NC], sl[NC], nf[NC];
+    float a0[NC], sl[NC], cf[NC];  // frame row, slope, phase offset
     int ti[NC];  // staged index of the word's current frame row
     int nx[NC];  // issue count at which the word's frame changes (NONE: never)
     int p;       // rows issued so far (wave-uniform)
@@ -251,7 +253,7 @@ struct FrameCoefs {
             const int j = 64 * i + lane;
             a0[i] = 0.f;
             sl[i] = 0.f;
-            nf[i] = 0.f;
+            cf[i] = 0.f;
             ti[i] = 0;
             nx[i] = NONE;
             if (j < CPW * M) {
@@ -264,7 +266,7 @@ struct FrameCoefs {
                     ti[i] = (k * nfr + (int)(q - fi.q0)) * M + f;
                     a0[i] = st[ti[i]];
                     sl[i] = (st[ti[i] + M] - a0[i]) * inv_hop;
-                    nf[i] = (float)n;
+                    cf[i] = (float)n;  // phase n at issue 0
                     // rows until the frame changes: down to phase 0, or up to phase hop - 1
                     const int first = DESC ? n + 1 : hop - n;
                     nx[i] = first < fi.len ? first : NONE;
@@ -285,7 +287,8 @@ struct FrameCoefs {
                 ti[i] += DESC ? -M : M;
                 a0[i] = rows[ti[i]];
                 sl[i] = (rows[ti[i] + M] - a0[i]) * inv_hop;
-                nf[i] = DESC ? (float)(hop - 1) : 0.f;
+                // phase at issue p: ascending 0, descending hop - 1
+                cf[i] = DESC ? (float)(hop - 1 + p) : -(float)p;
                 const int64_t len = info[(64 * i + lane) / M].len;
                 nx[i] = (int64_t)p + hop < len ? p + hop : NONE;
             }
@@ -298,11 +301,11 @@ struct FrameCoefs {
     __device__ __forceinline__ void produce(lfloat *dst) {
         if (p == ev) advance();
         const int lane = threadIdx.x & 63;
+        const float pf = DESC ? -(float)p : (float)p;
 #pragma unroll
         for (int i = 0; i < NC; ++i) {
             if (64 * (i + 1) <= CPW * M || 64 * i + lane < CPW * M)
-                dst[64 * i + lane] = __builtin_fmaf(nf[i], sl[i], a0[i]);
-            nf[i] += DESC ? -1.f : 1.f;
+                dst[64 * i + lane] = __builtin_fmaf(pf + cf[i], sl[i], a0[i]);
         }
         ++p;
     }
@@ -682,41 +685,47 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
             // any of its chunks (a frame's end or a chunk's end), accumulating
             // without branches; at a boundary only the lanes whose boundary it is
             // flush their shares.  Lanes past their chunk's end add zeros.
+            // Within one frame part (at most hop samples) the products and their
+            // sums are float32; the parts are combined in float64.
             constexpr int NONE = 0x7fffffff;
             const int hop = S.hop, nfr = S.nf;
             const int ln = (int)len;  // 0 for an inactive chunk
-            double P[TPL], Q[TPL], cr[TPL];
+            float P[TPL], Q[TPL];
+            double cr[TPL];
 #pragma unroll
-            for (int m = 0; m < TPL; ++m) P[m] = Q[m] = cr[m] = 0.0;
+            for (int m = 0; m < TPL; ++m) {
+                P[m] = Q[m] = 0.f;
+                cr[m] = 0.0;
+            }
             double *out = tipart + gc * nfr * M;
             int n = active ? (int)((c * L) % hop) : 0;  // phase of sample t in its frame
             int qq = 0, t = 0;
             int tb_l = ln > 0 ? min(hop - n, ln) : NONE;  // this lane's next boundary
             int tb = wave_min_i32(tb_l);
             while (tb != NONE) {
-                double nd = (double)n;
+                float nd = (float)n;
                 const int t_start = t;
                 for (; t < tb; ++t) {
-                    const double gt = t < ln ? (double)gsh[t] : 0.0;
-                    const double gn = gt * nd;
+                    const float gt = t < ln ? gsh[t] : 0.f;
+                    const float gn = gt * nd;
 #pragma unroll
                     for (int m = 0; m < TPL; ++m) {
                         const int i = r * TPL + m;  // tap i + 1
-                        const double sv = (double)ssh[M + t - 1 - (i < M ? i : 0)];
-                        P[m] = fma(-gt, sv, P[m]);
-                        Q[m] = fma(-gn, sv, Q[m]);
+                        const float sv = ssh[M + t - 1 - (i < M ? i : 0)];
+                        P[m] = __builtin_fmaf(-gt, sv, P[m]);
+                        Q[m] = __builtin_fmaf(-gn, sv, Q[m]);
                     }
-                    nd += 1.0;
+                    nd += 1.f;
                 }
                 n += tb - t_start;
                 if (tb_l == tb) {  // the chunk's part of frame q ends here
 #pragma unroll
                     for (int m = 0; m < TPL; ++m) {
                         const int i = r * TPL + m;
-                        const double qh = Q[m] / hop;
-                        if (i < M) out[qq * M + i] = cr[m] + P[m] - qh;
+                        const double qh = (double)Q[m] / hop;
+                        if (i < M) out[qq * M + i] = cr[m] + (double)P[m] - qh;
                         cr[m] = qh;
-                        P[m] = Q[m] = 0.0;
+                        P[m] = Q[m] = 0.f;
                     }
                     ++qq;
                     if (n == hop) n = 0;

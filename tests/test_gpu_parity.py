@@ -558,13 +558,13 @@ def test_frame_rate_coefficients_match_oracle(tv, B, T, M, L, hop, with_zi, stor
                                       need_zi=with_zi)
     plan.check_status()
     torch.cuda.synchronize()
-    assert per_seq_err(host(s), s_ref) <= TOL
-    assert rms_rel(host(zf), zf_ref) <= TOL
-    assert per_seq_err(host(ge), ge_ref) <= TOL
-    for b in range(B):
-        assert rms_rel(host(gA)[b], gA_ref[b]) <= TOL, b
+    errs = {"s": per_seq_err(host(s), s_ref), "zf": rms_rel(host(zf), zf_ref), "grad_e": per_seq_err(host(ge), ge_ref),
+            "grad_A": max(rms_rel(host(gA)[b], gA_ref[b]) for b in range(B))}
     if with_zi:
-        assert rms_rel(host(gz), gz_ref) <= TOL
+        errs["grad_zi"] = rms_rel(host(gz), gz_ref)
+    print("frame-rate", (B, T, M, L, hop), {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= TOL, (k, v)
 
 
 def test_frame_rate_matches_per_sample_rows(tv):
