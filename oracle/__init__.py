@@ -182,6 +182,87 @@ def lp_backward_frames(g: np.ndarray, A: np.ndarray, s: np.ndarray, hop: int,
     return ge, upsample_frames_adjoint(ga, F, hop), gz
 
 
+def framewise_fir(n: np.ndarray, C: np.ndarray, hop: int) -> np.ndarray:
+    """Frame-wise FIR filtering (the noise filter C(z) of Eq. 5): each hop-sample
+    frame q of the input is convolved with its own taps C[q] and the results
+    overlap-add, u(t) = sum_k C[q(t-k)][k] n(t-k) with q(tau) = tau // hop.
+    n [B,T], C [B,F,K] (F >= ceil(T / hop)).  Returns u [B,T] in float64."""
+    n = _f64(n)
+    C = _f64(C)
+    B, T = n.shape
+    K = C.shape[2]
+    u = np.zeros((B, T))
+    for q in range(-(-T // hop)):
+        lo, hi = q * hop, min((q + 1) * hop, T)
+        for b in range(B):
+            y = np.convolve(n[b, lo:hi], C[b, q])[: T - lo]
+            u[b, lo:lo + len(y)] += y
+    return u
+
+
+def framewise_fir_adjoint(gu: np.ndarray, n: np.ndarray, F: int, K: int, hop: int) -> np.ndarray:
+    """dL/dC[q][k] = sum over the samples tau of frame q of dL/du(tau + k) n(tau)."""
+    gu = np.asarray(gu, dtype=np.float64)
+    n = _f64(n)
+    B, T = n.shape
+    gC = np.zeros((B, F, K))
+    for q in range(-(-T // hop)):
+        lo, hi = q * hop, min((q + 1) * hop, T)
+        for k in range(K):
+            if lo + k >= T:
+                break
+            m = min(hi, T - k)
+            gC[:, q, k] = np.sum(gu[:, lo + k:m + k] * n[:, lo:m], axis=1)
+    return gC
+
+
+def fir(s: np.ndarray, h: np.ndarray) -> np.ndarray:
+    """Causal FIR y(t) = sum_k h[k] s(t-k) (the trainable output filter)."""
+    s = _f64(s)
+    h = _f64(h)
+    return np.stack([np.convolve(s[b], h)[: s.shape[1]] for b in range(s.shape[0])])
+
+
+def fir_adjoint(gy: np.ndarray, s: np.ndarray, h: np.ndarray):
+    """Adjoint of fir: dL/ds(t) = sum_k h[k] dL/dy(t+k), dL/dh[k] = sum_b,t dL/dy(t) s(t-k)."""
+    gy = np.asarray(gy, dtype=np.float64)
+    s = _f64(s)
+    h = _f64(h)
+    B, T = s.shape
+    K = h.shape[0]
+    gs = np.stack([np.convolve(gy[b][::-1], h)[:T][::-1] for b in range(B)])
+    gh = np.array([np.sum(gy[:, k:] * s[:, :T - k]) if k < T else 0.0 for k in range(K)])
+    return gs, gh
+
+
+def sf_forward(p, n, C, gain, A, h, hop: int):
+    """Source-filter synthesiser of Eq. 5 around the LP filter: the source is the
+    pulse train plus frame-wise FIR filtered noise, u = p + C * n; the LP filter
+    H takes it through an input gain linearly upsampled from frame values,
+    x = gamma u, s = LP_A(x) with frame-rate rows A (Sec. 4.3); the output filter
+    is the trainable FIR y = h * s.  gain [B,F], A [B,F,M], C [B,F,K], F =
+    coef_frames_count(T, hop).  Returns y and the intermediates (u, gamma, x, s)."""
+    T = p.shape[1]
+    u = _f64(p) + framewise_fir(n, C, hop)
+    gam = upsample_frames(_f64(gain)[..., None], T, hop)[..., 0]
+    x = gam * u
+    s, _ = lp_forward_frames(x, A, hop)
+    return fir(s, h), (u, gam, x, s)
+
+
+def sf_backward(gy, n, C, gain, A, h, inter, hop: int):
+    """Adjoint of sf_forward.  Returns (grad_p [B,T], grad_C [B,F,K], grad_gain [B,F],
+    grad_A [B,F,M], grad_h [K2])."""
+    u, gam, x, s = inter
+    F = A.shape[1]
+    gs, gh = fir_adjoint(gy, s, h)
+    gx, gA, _ = lp_backward_frames(gs, A, s, hop)
+    ggain = upsample_frames_adjoint((gx * u)[..., None], F, hop)[..., 0]
+    gu = gam * gx
+    gC = framewise_fir_adjoint(gu, n, F, C.shape[2], hop)
+    return gu, gC, ggain, gA, gh
+
+
 def framewise_geometry(T: int, hop: int):
     """Frames of the frame-wise approximation: length W = 4 hop (75 % overlap),
     frame f starting at sample (f - 3) hop, F = ceil(T / hop) + 3 frames, so that

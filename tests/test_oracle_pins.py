@@ -223,3 +223,67 @@ def test_oracle_frame_rate_coefficients():
     # the excitation gradient is the per-sample one on the upsampled rows
     ge_ps, _, _ = oracle.lp_backward(g, a, s)
     assert np.array_equal(ge, ge_ps)
+
+
+def test_oracle_source_filter_synthesiser():
+    """The source-filter synthesiser of Eq. 5 around the LP filter: the frame-wise
+    noise FIR against numpy.convolve (identical taps) and a per-sample double loop
+    (varying taps), the output FIR against scipy.signal.lfilter, adjoint
+    identities, the reduction to the LP filter alone, and central finite
+    differences for every parameter gradient."""
+    import scipy.signal
+    from synth.inputs import reflection_to_lpc
+    rng = np.random.default_rng(47)
+    B, T, M, hop, K, K2 = 2, 400, 6, 50, 9, 5
+    F = oracle.coef_frames_count(T, hop)
+    n = rng.standard_normal((B, T)); p = rng.standard_normal((B, T))
+    C = 0.3 * rng.standard_normal((B, F, K))
+    # identical taps in every frame: one convolution of the whole signal
+    Cs = np.repeat(C[:, :1], F, axis=1)
+    u1 = oracle.framewise_fir(n, Cs, hop)
+    for b in range(B):
+        assert np.max(np.abs(u1[b] - np.convolve(n[b], Cs[b, 0])[:T])) < 1e-12
+    # varying taps: each input sample filtered by its own frame's taps
+    u2 = oracle.framewise_fir(n, C, hop)
+    ref = np.zeros((B, T))
+    for b in range(B):
+        for t in range(T):
+            for k in range(K):
+                if t - k >= 0:
+                    ref[b, t] += C[b, (t - k) // hop, k] * n[b, t - k]
+    assert np.max(np.abs(u2 - ref)) < 1e-12
+    # the output FIR is lfilter with numerator h
+    h = rng.standard_normal(K2)
+    s = rng.standard_normal((B, T))
+    assert np.max(np.abs(oracle.fir(s, h) - scipy.signal.lfilter(h, [1.0], s, axis=1))) < 1e-12
+    # adjoint identities: frame-wise FIR in its taps, output FIR in s and in h
+    gy = rng.standard_normal((B, T))
+    gC = oracle.framewise_fir_adjoint(gy, n, F, K, hop)
+    assert abs(np.sum(gy * u2) - np.sum(gC * C)) < 1e-9 * (1 + abs(np.sum(gy * u2)))
+    gs, gh = oracle.fir_adjoint(gy, s, h)
+    y = oracle.fir(s, h)
+    assert abs(np.sum(gy * y) - np.sum(gs * s)) < 1e-9 * (1 + abs(np.sum(gy * y)))
+    assert abs(np.sum(gy * y) - np.sum(gh * h)) < 1e-9 * (1 + abs(np.sum(gy * y)))
+    # the whole synthesiser
+    A = (reflection_to_lpc(rng.uniform(-0.6, 0.6, size=(B, F, M))) * 0.98 ** np.arange(1, M + 1))
+    gain = rng.uniform(0.5, 1.5, size=(B, F))
+    # no noise, unit gain, identity output filter: the LP filter of the pulse train
+    delta = np.zeros(K2); delta[0] = 1.0
+    y0, _ = oracle.sf_forward(p, n, np.zeros_like(C), np.ones_like(gain), A, delta, hop)
+    assert np.max(np.abs(y0 - oracle.lp_forward_frames(p, A, hop)[0])) < 1e-12
+    y, inter = oracle.sf_forward(p, n, C, gain, A, h, hop)
+    gp, gCs, ggain, gA, ghs = oracle.sf_backward(gy, n, C, gain, A, h, inter, hop)
+
+    def loss(**kw):
+        args = dict(p=p, C=C, gain=gain, A=A, h=h)
+        args.update(kw)
+        return float(np.sum(gy * oracle.sf_forward(args["p"], n, args["C"], args["gain"], args["A"], args["h"], hop)[0]))
+
+    eps = 1e-6
+    for name, arr, grad, idx in [("p", p, gp, (1, 123)), ("C", C, gCs, (0, 3, 4)), ("C", C, gCs, (1, 7, 0)),
+                                 ("gain", gain, ggain, (0, 2)), ("gain", gain, ggain, (1, F - 1)),
+                                 ("A", A, gA, (1, 5, 2)), ("h", h, ghs, (3,))]:
+        ap = arr.copy(); ap[idx] += eps
+        am = arr.copy(); am[idx] -= eps
+        fd = (loss(**{name: ap}) - loss(**{name: am})) / (2 * eps)
+        assert abs(fd - grad[idx]) <= 1e-6 * (abs(fd) + 1.0), (name, idx, fd, grad[idx])
