@@ -165,20 +165,30 @@ def upsample_frames_adjoint(ga: np.ndarray, F: int, hop: int) -> np.ndarray:
     return gA
 
 
-def lp_forward_frames(e: np.ndarray, A: np.ndarray, hop: int, zi: Optional[np.ndarray] = None):
+def _frame_rows(A: np.ndarray, T: int, hop: int, round_rows: bool) -> np.ndarray:
+    """Upsampled rows as the filter reads them: by default rounded once to float32,
+    the precision of the per-sample rows (and of a float32 upsampling)."""
+    a = upsample_frames(A, T, hop)
+    return a.astype(np.float32) if round_rows else a
+
+
+def lp_forward_frames(e: np.ndarray, A: np.ndarray, hop: int, zi: Optional[np.ndarray] = None,
+                      round_rows: bool = True):
     """The filter with frame-rate coefficients A [B,F,M] linearly upsampled to every
-    sample (Sec. 4.3), then Eq. 6.  Returns (s, zf) as lp_forward."""
-    return lp_forward(e, upsample_frames(A, e.shape[1], hop), zi)
+    sample (Sec. 4.3), then Eq. 6.  round_rows=False keeps the float64 rows (for
+    finite differences).  Returns (s, zf) as lp_forward."""
+    return lp_forward(e, _frame_rows(A, e.shape[1], hop, round_rows), zi)
 
 
 def lp_backward_frames(g: np.ndarray, A: np.ndarray, s: np.ndarray, hop: int,
-                       zi: Optional[np.ndarray] = None, need_grad_zi: bool = False):
+                       zi: Optional[np.ndarray] = None, need_grad_zi: bool = False, round_rows: bool = True):
     """Adjoint of lp_forward_frames: the per-sample adjoint (Eqs. 12-13) on the
-    upsampled rows, then dL/dA by the adjoint of the upsampling.
+    upsampled rows, then dL/dA by the adjoint of the upsampling (the rounding of
+    the rows is taken as the identity).
     Returns (grad_e [B,T], grad_A [B,F,M], grad_zi [B,M] or None)."""
     T = g.shape[1]
     F = A.shape[1]
-    ge, ga, gz = lp_backward(g, upsample_frames(A, T, hop), s, zi, need_grad_zi=need_grad_zi)
+    ge, ga, gz = lp_backward(g, _frame_rows(A, T, hop, round_rows), s, zi, need_grad_zi=need_grad_zi)
     return ge, upsample_frames_adjoint(ga, F, hop), gz
 
 
@@ -235,7 +245,7 @@ def fir_adjoint(gy: np.ndarray, s: np.ndarray, h: np.ndarray):
     return gs, gh
 
 
-def sf_forward(p, n, C, gain, A, h, hop: int):
+def sf_forward(p, n, C, gain, A, h, hop: int, round_rows: bool = True):
     """Source-filter synthesiser of Eq. 5 around the LP filter: the source is the
     pulse train plus frame-wise FIR filtered noise, u = p + C * n; the LP filter
     H takes it through an input gain linearly upsampled from frame values,
@@ -246,17 +256,17 @@ def sf_forward(p, n, C, gain, A, h, hop: int):
     u = _f64(p) + framewise_fir(n, C, hop)
     gam = upsample_frames(_f64(gain)[..., None], T, hop)[..., 0]
     x = gam * u
-    s, _ = lp_forward_frames(x, A, hop)
+    s, _ = lp_forward_frames(x, A, hop, round_rows=round_rows)
     return fir(s, h), (u, gam, x, s)
 
 
-def sf_backward(gy, n, C, gain, A, h, inter, hop: int):
+def sf_backward(gy, n, C, gain, A, h, inter, hop: int, round_rows: bool = True):
     """Adjoint of sf_forward.  Returns (grad_p [B,T], grad_C [B,F,K], grad_gain [B,F],
     grad_A [B,F,M], grad_h [K2])."""
     u, gam, x, s = inter
     F = A.shape[1]
     gs, gh = fir_adjoint(gy, s, h)
-    gx, gA, _ = lp_backward_frames(gs, A, s, hop)
+    gx, gA, _ = lp_backward_frames(gs, A, s, hop, round_rows=round_rows)
     ggain = upsample_frames_adjoint((gx * u)[..., None], F, hop)[..., 0]
     gu = gam * gx
     gC = framewise_fir_adjoint(gu, n, F, C.shape[2], hop)

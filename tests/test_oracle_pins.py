@@ -193,12 +193,12 @@ def test_oracle_frame_rate_coefficients():
     assert np.array_equal(a[:, qs, :], A[:, qs // hop, :])
     e = rng.standard_normal((B, T)); g = rng.standard_normal((B, T))
     # a constant track is the time-invariant filter
-    Ac = np.repeat(A[:, :1, :], F, axis=1)
+    Ac = np.repeat(A[:, :1, :], F, axis=1).astype(np.float32)
     s_c, _ = oracle.lp_forward_frames(e, Ac, hop)
-    s_ti, _ = oracle.lp_forward_ti(e, A[:, 0, :])
+    s_ti, _ = oracle.lp_forward_ti(e, Ac[:, 0, :])
     assert pins.rms_rel(s_c, s_ti) < 1e-12
     # hop 1: every sample has its own row; the frame gradient is the per-sample one
-    A1 = reflection_to_lpc(rng.uniform(-0.5, 0.5, size=(B, T + 1, M)))
+    A1 = reflection_to_lpc(rng.uniform(-0.5, 0.5, size=(B, T + 1, M))).astype(np.float32)
     s1, _ = oracle.lp_forward_frames(e, A1, 1)
     ge1, gA1, _ = oracle.lp_backward_frames(g, A1, s1, 1)
     ge_ref, ga_ref, _ = oracle.lp_backward(g, A1[:, :T], s1)
@@ -210,19 +210,22 @@ def test_oracle_frame_rate_coefficients():
     lhs = float(np.sum(oracle.upsample_frames(X, T, hop) * Y))
     rhs = float(np.sum(X * oracle.upsample_frames_adjoint(Y, F, hop)))
     assert abs(lhs - rhs) <= 1e-11 * (abs(lhs) + 1.0)
-    # finite differences of L = <g, s> in the frame coefficients
-    s, _ = oracle.lp_forward_frames(e, A, hop)
-    ge, gA, _ = oracle.lp_backward_frames(g, A, s, hop)
+    # finite differences of L = <g, s> in the frame coefficients (float64 rows)
+    s, _ = oracle.lp_forward_frames(e, A, hop, round_rows=False)
+    ge, gA, _ = oracle.lp_backward_frames(g, A, s, hop, round_rows=False)
     h = 1e-6
     for (b, q, i) in [(0, 0, 0), (1, 4, 3), (0, F - 1, 5), (1, F - 2, 1), (0, 7, 2)]:
         ap = A.copy(); ap[b, q, i] += h
         am = A.copy(); am[b, q, i] -= h
-        fd = (np.sum(g * oracle.lp_forward_frames(e, ap, hop)[0])
-              - np.sum(g * oracle.lp_forward_frames(e, am, hop)[0])) / (2 * h)
+        fd = (np.sum(g * oracle.lp_forward_frames(e, ap, hop, round_rows=False)[0])
+              - np.sum(g * oracle.lp_forward_frames(e, am, hop, round_rows=False)[0])) / (2 * h)
         assert abs(fd - gA[b, q, i]) <= 1e-6 * (abs(fd) + 1.0), (b, q, i, fd, gA[b, q, i])
     # the excitation gradient is the per-sample one on the upsampled rows
     ge_ps, _, _ = oracle.lp_backward(g, a, s)
     assert np.array_equal(ge, ge_ps)
+    # by default the filter reads the rows rounded once to float32
+    s_r, _ = oracle.lp_forward_frames(e, A, hop)
+    assert np.array_equal(s_r, oracle.lp_forward(e, a.astype(np.float32))[0])
 
 
 def test_oracle_source_filter_synthesiser():
@@ -271,13 +274,14 @@ def test_oracle_source_filter_synthesiser():
     delta = np.zeros(K2); delta[0] = 1.0
     y0, _ = oracle.sf_forward(p, n, np.zeros_like(C), np.ones_like(gain), A, delta, hop)
     assert np.max(np.abs(y0 - oracle.lp_forward_frames(p, A, hop)[0])) < 1e-12
-    y, inter = oracle.sf_forward(p, n, C, gain, A, h, hop)
-    gp, gCs, ggain, gA, ghs = oracle.sf_backward(gy, n, C, gain, A, h, inter, hop)
+    y, inter = oracle.sf_forward(p, n, C, gain, A, h, hop, round_rows=False)
+    gp, gCs, ggain, gA, ghs = oracle.sf_backward(gy, n, C, gain, A, h, inter, hop, round_rows=False)
 
     def loss(**kw):
         args = dict(p=p, C=C, gain=gain, A=A, h=h)
         args.update(kw)
-        return float(np.sum(gy * oracle.sf_forward(args["p"], n, args["C"], args["gain"], args["A"], args["h"], hop)[0]))
+        return float(np.sum(gy * oracle.sf_forward(args["p"], n, args["C"], args["gain"], args["A"], args["h"], hop,
+                                                   round_rows=False)[0]))
 
     eps = 1e-6
     for name, arr, grad, idx in [("p", p, gp, (1, 123)), ("C", C, gCs, (0, 3, 4)), ("C", C, gCs, (1, 7, 0)),
