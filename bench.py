@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 METRIC = "fwd+bwd filtered samples/s at M=22 (chunked vs sequential); serve p50/p99 ms"
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector, published
+FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published
 
 
 # HBM bytes per launch (rocprofv3 FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, factors from a
@@ -46,7 +47,7 @@ def kernel_sources_sha256() -> str:
     import hashlib
     h = hashlib.sha256()
     for f in sorted(glob.glob(os.path.join(ROOT, "paper_2406_05128_amd", "csrc", "*"))):
-        if os.path.basename(f) == "tvlp_serve.hip":  # host-side server, no kernels
+        if os.path.basename(f) in ("tvlp_serve.hip", "tvlp_sf.hip"):  # no LP kernels in these
             continue
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
@@ -336,6 +337,79 @@ def frame_rate_bench(tv, B: int, T: int, M: int, L: int, steps: int, warmup: int
                     "dL/dA from per-chunk float64 shares summed per frame"}
 
 
+def sf_synth_bench(tv, B: int, T: int, M: int, steps: int, warmup: int):
+    """The source-filter synthesiser of Eq. 5 around the LP filter on the training
+    shape: pulse train plus frame-wise FIR filtered noise (510 taps per 240-sample
+    frame, the length of a 256-bin frequency response), input gain, frame-rate LP
+    (M = 22), 128-tap output FIR; forward + adjoint of every parameter.  Stages
+    are timed with events on the stream; the noise filter and the output FIR are
+    float32 FMA streams (2 FLOP per tap and sample) reported against the fp32
+    vector peak."""
+    import numpy as np
+    import torch
+    from synth import make_excitation, make_upstream_grad, pulse_train, reflection_to_lpc
+    from paper_2406_05128_amd import _lib
+    from paper_2406_05128_amd.ops import _ptr, _stream
+
+    hop, K, K2 = 240, 510, 128
+    dev = torch.device("cuda", 0)
+    rng = np.random.default_rng(91)
+    F = tv.coef_frames_count(T, hop)
+    k = np.empty((B, F, M))
+    k[:, 0] = rng.uniform(-0.95, 0.95, size=(B, M))
+    dk = rng.normal(0.0, 0.01, size=(B, F, M))
+    for f in range(1, F):
+        k[:, f] = np.clip(k[:, f - 1] + dk[:, f], -0.95, 0.95)
+    A = (reflection_to_lpc(k) * 0.98 ** np.arange(1, M + 1)).astype(np.float32)
+    p = pulse_train(rng, B, T)
+    n = make_excitation(rng, B, T)
+    C = (rng.standard_normal((B, F, K)) / np.sqrt(K)).astype(np.float32)
+    gain = rng.uniform(0.5, 1.5, size=(B, F)).astype(np.float32)
+    h = (rng.standard_normal(K2) / np.sqrt(K2)).astype(np.float32)
+    gy = make_upstream_grad(rng, B, T)
+    p, n, C, gain, A, h, gy = (torch.from_numpy(x).to(dev) for x in (p, n, C, gain, A, h, gy))
+    syn = tv.SFSynth(M, hop, K, K2, dev)
+
+    def step():
+        y, ctx = syn.forward(p, n, C, gain, A, h)
+        return syn.backward(gy, ctx)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    # the source and FIR kernels alone, events on the stream they are launched on
+    lib, st = _lib.load(), _stream(dev)
+    u, x, y = (torch.empty_like(p) for _ in range(3))
+
+    def timed(fn, reps=5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e3  # us
+
+    us_src = timed(lambda: lib.lp_sf_source(B, T, hop, K, _ptr(p), _ptr(n), _ptr(C), _ptr(gain), _ptr(u), _ptr(x), st))
+    us_fir = timed(lambda: lib.lp_fir(B, T, K2, _ptr(x), _ptr(h), _ptr(y), st))
+    flops_src = 2.0 * B * T * K
+    flops_fir = 2.0 * B * T * K2
+    return {"workload": f"sf_synth_b{B}_t{T}_m{M}_hop{hop}_k{K}_fir{K2}", "ms_per_step": round(ms, 4),
+            "samples_per_s": round(B * T / (ms * 1e-3), 1),
+            "kernels_us": {"source_fir_noise": round(us_src, 2), "output_fir": round(us_fir, 2)},
+            "source_fir_noise_TFLOPs_f32": round(flops_src / (us_src * 1e-6) / 1e12, 2),
+            "output_fir_TFLOPs_f32": round(flops_fir / (us_fir * 1e-6) / 1e12, 2),
+            "fp32_vector_peak_TFLOPs": FP32_PEAK_TFLOPS,
+            "note": "one step = source, frame-rate LP, output FIR and the adjoint of each; LP parts as in the "
+                    "frame-rate section"}
+
+
 def framewise_bench(tv, sets, B: int, T: int, M: int, steps: int, warmup: int, ms_samplewise: float):
     """The frame-wise approximation (hop 240 = 10 ms at 24 kHz, frames of 960 samples,
     75 % overlap) on the training shape: frames filtered with the coefficient row
@@ -471,6 +545,7 @@ def main():
     ap.add_argument("--no-ti", action="store_true", help="skip the time-invariant coefficient section")
     ap.add_argument("--no-framewise", action="store_true", help="skip the frame-wise approximation section")
     ap.add_argument("--no-frame-rate", action="store_true", help="skip the frame-rate coefficient section")
+    ap.add_argument("--no-sf", action="store_true", help="skip the source-filter synthesiser section")
     ap.add_argument("--serve-requests", type=int, default=100)
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-batch", type=int, default=8)
@@ -645,6 +720,13 @@ def main():
         log(f"frame-rate: {frame_rate['ms_per_step']:.3f} ms/step")
         torch.cuda.empty_cache()
 
+    sf = None
+    if not args.no_sf:
+        log("source-filter synthesiser (Eq. 5) around the frame-rate LP")
+        sf = sf_synth_bench(tv, B, T, M, args.steps, args.warmup)
+        log(f"sf synthesiser: {sf['ms_per_step']:.3f} ms/step")
+        torch.cuda.empty_cache()
+
     framewise = None
     if not args.no_framewise:
         log("frame-wise approximation (hop 240, 75 % overlap)")
@@ -680,6 +762,7 @@ def main():
         "stress": stress,
         "time_invariant": ti,
         "frame_rate": frame_rate,
+        "sf_synth": sf,
         "framewise": framewise,
     }
     print(json.dumps(out), flush=True)

@@ -192,6 +192,36 @@ int lp_backward_frames(lp_plan *p, int64_t B, int64_t T, int64_t hop,
                        float *grad_e, float *grad_A, double *grad_zi, void *stream);
 
 /*
+ * Source-filter synthesiser around the LP filter (Eq. 5, S = (G + N C) H, with
+ * the trainable output FIR): the pieces that wrap lp_forward_frames /
+ * lp_backward_frames.  Signals are [B,T] float32; frames as for the frame-rate
+ * coefficients (frame q at sample q*hop, F = lp_coef_frames_count(T, hop));
+ * device pointers, caller-owned; enqueued on `stream`.  Errors: LP_EINVAL for
+ * sizes out of range (B <= 65535, 1 <= hop <= 4096, 1 <= K <= 1024) or null
+ * pointers, LP_EDEVICE for a failed launch; the message is lp_sf_last_error().
+ *
+ * lp_sf_source: u(t) = p(t) + sum_k C[q(t-k)][k] n(t-k), the noise n filtered
+ * frame-wise (each hop-sample input frame q convolved with its own K taps
+ * C[q] from C [B,F,K], results overlap-added) plus the pulse source p; and the
+ * LP input x(t) = gamma(t) u(t), gamma linearly upsampled from gain [B,F].
+ * lp_sf_source_adjoint: from gx = dL/dx: gu = dL/du = dL/dp [B,T] (written),
+ * gC = dL/dC [B,F,K], ggain = dL/dgain [B,F].
+ * lp_fir: y(t) = sum_k h[k] s(t-k), h [K] shared by all sequences.
+ * lp_fir_adjoint: gs = dL/ds [B,T] and gh = dL/dh [K] (each may be NULL);
+ * gh needs `work`, lp_fir_adjoint_work_bytes(B, T, K) bytes of device memory
+ * (per-tile partial sums, summed in float64 in a fixed order).
+ */
+const char *lp_sf_last_error(void);
+int lp_sf_source(int64_t B, int64_t T, int64_t hop, int64_t K, const float *p, const float *n,
+                 const float *C, const float *gain, float *u, float *x, void *stream);
+int lp_sf_source_adjoint(int64_t B, int64_t T, int64_t hop, int64_t K, const float *gx, const float *u,
+                         const float *n, const float *gain, float *gu, float *gC, float *ggain, void *stream);
+int lp_fir(int64_t B, int64_t T, int64_t K, const float *s, const float *h, float *y, void *stream);
+size_t lp_fir_adjoint_work_bytes(int64_t B, int64_t T, int64_t K);
+int lp_fir_adjoint(int64_t B, int64_t T, int64_t K, const float *gy, const float *s, const float *h,
+                   float *gs, float *gh, void *work, void *stream);
+
+/*
  * Frame-wise approximation (the comparator of Sec. 3.2: time-invariant filtering
  * of short overlapping frames, overlap-added; 75 % overlap as in Sec. 5).  Frames
  * have length W = 4 hop; frame f of a sequence starts at sample (f - 3) hop and

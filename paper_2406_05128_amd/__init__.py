@@ -12,7 +12,8 @@ from .ops import Plan, PairStepGraph, forward_plain, backward_plain  # noqa: E40
 from .ops import coef_frames_count, frames_count, framewise_forward, framewise_backward  # noqa: E402
 from .autograd import LPFunction, lp, get_plan  # noqa: E402
 from .serve import Server  # noqa: E402
+from .sf import SFSynth  # noqa: E402
 
 __all__ = ["Plan", "PairStepGraph", "forward_plain", "backward_plain", "LPFunction", "lp", "get_plan", "Server",
-           "coef_frames_count", "frames_count", "framewise_forward", "framewise_backward"]
+           "SFSynth", "coef_frames_count", "frames_count", "framewise_forward", "framewise_backward"]
 __version__ = "0.1.0"

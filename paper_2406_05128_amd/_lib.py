@@ -54,6 +54,12 @@ SIGNATURES = {
     "lp_backward_ti": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "lp_frames_count": (_I64, [_I64, _I64]),
     "lp_coef_frames_count": (_I64, [_I64, _I64]),
+    "lp_sf_last_error": (ctypes.c_char_p, []),
+    "lp_sf_source": (_INT, [_I64, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P, _P]),
+    "lp_sf_source_adjoint": (_INT, [_I64, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "lp_fir": (_INT, [_I64, _I64, _I64, _P, _P, _P, _P]),
+    "lp_fir_adjoint_work_bytes": (_SZ, [_I64, _I64, _I64]),
+    "lp_fir_adjoint": (_INT, [_I64, _I64, _I64, _P, _P, _P, _P, _P, _P, _P]),
     "lp_forward_frames": (_INT, [_P, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P, _P]),
     "lp_backward_frames": (_INT, [_P, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "lp_frames_gather": (_INT, [_I64, _I64, _I64, _P, _P, ctypes.c_int, _P]),
@@ -118,6 +124,14 @@ def last_error() -> str:
 def check(code: int) -> int:
     if code < 0:
         raise TvlpError(code, last_error())
+    return code
+
+
+def check_sf(code: int) -> int:
+    """check() for the synthesiser calls, which keep their own error message."""
+    if code < 0:
+        msg = load().lp_sf_last_error()
+        raise TvlpError(code, msg.decode() if msg else "")
     return code
 
 

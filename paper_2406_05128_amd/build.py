@@ -11,7 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libtvlp.so")
 
-SOURCES = ["tvlp_api.hip", "tvlp_serve.hip"]
+SOURCES = ["tvlp_api.hip", "tvlp_serve.hip", "tvlp_sf.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

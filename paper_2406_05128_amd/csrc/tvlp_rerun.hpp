@@ -167,11 +167,12 @@ struct RowRing {
 // A wave first stages the frame rows its chunks touch in LDS (per chunk k, nf
 // rows starting at the chunk's first frame), then produces one interpolated row
 // per ring step with one FMA and one LDS store per 64 words, in place of a DMA
-// of the per-sample row.  Every lane word keeps its frame row, slope and phase
-// offset in registers: at wave-uniform issue count p the phase is p + c
-// (descending c - p), an exact integer in float32, and the word is
-// fma(phase, slope, row), one rounding.  Frame changes happen at a handful of
-// steps per chunk, at which the affected words reload from the staged rows.
+// of the per-sample row.  Every lane word keeps its frame row and slope (float64)
+// and its phase offset in registers: at wave-uniform issue count p the phase is
+// p + c (descending c - p), an exact integer, and the word is
+// fma(phase, slope, row) in float64 rounded once to float32 (the float32
+// rounding of the interpolation).  Frame changes happen at a handful of steps
+// per chunk, at which the affected words reload from the staged rows.
 
 struct FrameInfo {
     int64_t arow;  // element offset of the chunk's sequence in A (b * F * M)
@@ -200,13 +201,13 @@ struct FrameCoefs {
     static constexpr int NC = (CPW * M + 63) / 64;  // LDS stores per produced row
     static constexpr int NONE = 0x7fffffff;
     typedef __attribute__((address_space(3))) float lfloat;
-    float a0[NC], sl[NC], cf[NC];  // frame row, slope, phase offset
+    double a0[NC], sl[NC];  // frame row, slope per sample
+    float cf[NC];           // phase offset
     int ti[NC];  // staged index of the word's current frame row
     int nx[NC];  // issue count at which the word's frame changes (NONE: never)
     int p;       // rows issued so far (wave-uniform)
     int ev;      // smallest nx over the wave
     int hop;
-    float inv_hop;
     const float *rows;
     const FrameInfo *info;
 
@@ -217,7 +218,6 @@ struct FrameCoefs {
     __device__ __forceinline__ void init(const float *__restrict__ A, const Seqs &S, unsigned char *lds, int lane,
                                          int slot, bool lead, int64_t my_b, int64_t my_tin, int64_t my_len) {
         hop = S.hop;
-        inv_hop = 1.0f / (float)hop;
         const int nfr = S.nf;
         FrameInfo *inf = reinterpret_cast<FrameInfo *>(lds);
         float *st = reinterpret_cast<float *>(lds + CPW * sizeof(FrameInfo));
@@ -251,8 +251,8 @@ struct FrameCoefs {
 #pragma unroll
         for (int i = 0; i < NC; ++i) {
             const int j = 64 * i + lane;
-            a0[i] = 0.f;
-            sl[i] = 0.f;
+            a0[i] = 0.0;
+            sl[i] = 0.0;
             cf[i] = 0.f;
             ti[i] = 0;
             nx[i] = NONE;
@@ -264,8 +264,8 @@ struct FrameCoefs {
                     const int64_t q = t0 / hop;
                     const int n = (int)(t0 - q * hop);
                     ti[i] = (k * nfr + (int)(q - fi.q0)) * M + f;
-                    a0[i] = st[ti[i]];
-                    sl[i] = (st[ti[i] + M] - a0[i]) * inv_hop;
+                    a0[i] = (double)st[ti[i]];
+                    sl[i] = ((double)st[ti[i] + M] - a0[i]) / hop;
                     cf[i] = (float)n;  // phase n at issue 0
                     // rows until the frame changes: down to phase 0, or up to phase hop - 1
                     const int first = DESC ? n + 1 : hop - n;
@@ -285,8 +285,8 @@ struct FrameCoefs {
         for (int i = 0; i < NC; ++i) {
             if (nx[i] == p) {
                 ti[i] += DESC ? -M : M;
-                a0[i] = rows[ti[i]];
-                sl[i] = (rows[ti[i] + M] - a0[i]) * inv_hop;
+                a0[i] = (double)rows[ti[i]];
+                sl[i] = ((double)rows[ti[i] + M] - a0[i]) / hop;
                 // phase at issue p: ascending 0, descending hop - 1
                 cf[i] = DESC ? (float)(hop - 1 + p) : -(float)p;
                 const int64_t len = info[(64 * i + lane) / M].len;
@@ -305,7 +305,7 @@ struct FrameCoefs {
 #pragma unroll
         for (int i = 0; i < NC; ++i) {
             if (64 * (i + 1) <= CPW * M || 64 * i + lane < CPW * M)
-                dst[64 * i + lane] = __builtin_fmaf(pf + cf[i], sl[i], a0[i]);
+                dst[64 * i + lane] = (float)fma((double)(pf + cf[i]), sl[i], a0[i]);
         }
         ++p;
     }

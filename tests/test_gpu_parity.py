@@ -613,3 +613,112 @@ def test_frame_rate_rejects_hop_too_short_for_lds(tv):
     A = torch.zeros((B, tv.coef_frames_count(T, 1), M), dtype=torch.float32, device=dev())
     with pytest.raises(Exception, match="hop"):
         plan.forward_frames(e, A, 1)
+
+
+# ---------------------------------------------------------------- source-filter synthesiser
+
+def _sf_inputs(B, T, M, hop, K, K2, seed):
+    from synth import pulse_train
+    rng = np.random.default_rng(seed)
+    e, A, _ = _frame_inputs(B, T, M, hop, seed=seed + 1)
+    F = oracle.coef_frames_count(T, hop)
+    p = pulse_train(rng, B, T)
+    n = make_excitation(rng, B, T)
+    C = (rng.standard_normal((B, F, K)) / np.sqrt(K)).astype(np.float32)
+    gain = rng.uniform(0.5, 1.5, size=(B, F)).astype(np.float32)
+    h = (rng.standard_normal(K2) / np.sqrt(K2)).astype(np.float32)
+    gy = make_upstream_grad(rng, B, T)
+    return p, n, C, gain, A, h, gy
+
+
+def test_sf_source_and_output_fir(tv):
+    """The synthesiser's source kernel (frame-wise FIR noise filter, pulse train,
+    interpolated gain) and the output FIR with its adjoint, against the oracle."""
+    from paper_2406_05128_amd import _lib
+    B, T, hop, K, K2 = 3, 2500, 70, 45, 19
+    p, n, C, gain, A, h, gy = _sf_inputs(B, T, 4, hop, K, K2, seed=5)
+    lib, st = _lib.load(), torch.cuda.current_stream(dev()).cuda_stream
+    import ctypes
+    P = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+    p_d, n_d, C_d, g_d, h_d, gy_d = map(to_dev, (p, n, C, gain, h, gy))
+    u_d, x_d, y_d = (torch.empty_like(p_d) for _ in range(3))
+    assert lib.lp_sf_source(B, T, hop, K, P(p_d), P(n_d), P(C_d), P(g_d), P(u_d), P(x_d), ctypes.c_void_p(st)) == 0
+    assert lib.lp_fir(B, T, K2, P(x_d), P(h_d), P(y_d), ctypes.c_void_p(st)) == 0
+    gs_d, gh_d = torch.empty_like(gy_d), torch.empty_like(h_d)
+    work = torch.empty(lib.lp_fir_adjoint_work_bytes(B, T, K2), dtype=torch.uint8, device=dev())
+    assert lib.lp_fir_adjoint(B, T, K2, P(gy_d), P(x_d), P(h_d), P(gs_d), P(gh_d), P(work), ctypes.c_void_p(st)) == 0
+    torch.cuda.synchronize()
+    u_ref = p + oracle.framewise_fir(n, C, hop)
+    gam = oracle.upsample_frames(gain[..., None].astype(np.float64), T, hop)[..., 0]
+    x_ref = gam * u_ref
+    assert per_seq_err(host(u_d), u_ref) <= 1e-6
+    assert per_seq_err(host(x_d), x_ref) <= 1e-6
+    x32 = host(x_d)
+    assert per_seq_err(host(y_d), oracle.fir(x32, h)) <= 1e-6
+    gs_ref, gh_ref = oracle.fir_adjoint(gy, x32, h)
+    assert per_seq_err(host(gs_d), gs_ref) <= 1e-6
+    assert rms_rel(host(gh_d), gh_ref) <= 1e-6
+
+
+@pytest.mark.parametrize("B,T,M,hop,K,K2,L", [
+    (2, 3000, 16, 100, 33, 17, 256),
+    (2, 4801, 22, 240, 510, 128, 418),
+    (1, 500, 8, 37, 64, 5, 96),
+    (2, 1000, 22, 240, 1024, 128, 264),
+    (3, 777, 12, 16, 7, 1, 48),
+])
+def test_sf_synth_matches_oracle(tv, B, T, M, hop, K, K2, L):
+    """The whole synthesiser step (source, frame-rate LP, output FIR) and its
+    adjoint through the C ABI against the oracle: y and the gradients of the
+    pulse train, the noise-filter taps, the gains, the LP frame rows and the
+    output FIR."""
+    p, n, C, gain, A, h, gy = _sf_inputs(B, T, M, hop, K, K2, seed=T + K)
+    y_ref, inter = oracle.sf_forward(p, n, C, gain, A, h, hop)
+    gp_ref, gC_ref, gg_ref, gA_ref, gh_ref = oracle.sf_backward(gy, n, C, gain, A, h, inter, hop)
+    syn = tv.SFSynth(M, hop, K, K2, dev(), chunk=L)
+    y, ctx = syn.forward(*map(to_dev, (p, n, C, gain, A, h)))
+    gp, gC, gg, gA, gh = syn.backward(to_dev(gy), ctx)
+    syn.plan.check_status()
+    torch.cuda.synchronize()
+    errs = {"y": per_seq_err(host(y), y_ref), "grad_p": per_seq_err(host(gp), gp_ref),
+            "grad_C": max(rms_rel(host(gC)[b], gC_ref[b]) for b in range(B)),
+            "grad_gain": max(rms_rel(host(gg)[b], gg_ref[b]) for b in range(B)),
+            "grad_A": max(rms_rel(host(gA)[b], gA_ref[b]) for b in range(B)),
+            "grad_h": rms_rel(host(gh), gh_ref)}
+    print("sf", (B, T, M, hop, K, K2, L), {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= TOL, (k, v)
+
+
+def test_sf_synth_training_shape(tv):
+    """B=64, T=48000, M=22, hop 240, a 510-tap noise filter per frame (256
+    frequency bins) and a 128-tap output FIR: every output and gradient against
+    the oracle on the whole batch."""
+    B, T, M, hop, K, K2 = 64, 48000, 22, 240, 510, 128
+    p, n, C, gain, A, h, gy = _sf_inputs(B, T, M, hop, K, K2, seed=2024)
+    syn = tv.SFSynth(M, hop, K, K2, dev())
+    y, ctx = syn.forward(*map(to_dev, (p, n, C, gain, A, h)))
+    gp, gC, gg, gA, gh = syn.backward(to_dev(gy), ctx)
+    syn.plan.check_status()
+    torch.cuda.synchronize()
+    y_ref, inter = oracle.sf_forward(p, n, C, gain, A, h, hop)
+    gp_ref, gC_ref, gg_ref, gA_ref, gh_ref = oracle.sf_backward(gy, n, C, gain, A, h, inter, hop)
+    assert per_seq_err(host(y), y_ref) <= TOL
+    assert per_seq_err(host(gp), gp_ref) <= TOL
+    for b in (0, 31, 63):
+        assert rms_rel(host(gC)[b], gC_ref[b]) <= TOL, b
+        assert rms_rel(host(gg)[b], gg_ref[b]) <= TOL, b
+        assert rms_rel(host(gA)[b], gA_ref[b]) <= TOL, b
+    assert rms_rel(host(gh), gh_ref) <= TOL
+
+
+def test_sf_rejects_out_of_range_sizes(tv):
+    """FIR longer than 1024 taps and frames longer than 4096 samples are refused."""
+    from paper_2406_05128_amd import _lib
+    lib = _lib.load()
+    z = torch.zeros(16, dtype=torch.float32, device=dev())
+    import ctypes
+    P = ctypes.c_void_p(z.data_ptr())
+    assert lib.lp_fir(1, 4, 1025, P, P, P, None) == -1
+    assert b"K" in lib.lp_sf_last_error()
+    assert lib.lp_sf_source(1, 4, 5000, 2, P, P, P, P, P, P, None) == -1
