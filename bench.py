@@ -398,13 +398,22 @@ def sf_synth_bench(tv, B: int, T: int, M: int, steps: int, warmup: int):
 
     us_src = timed(lambda: lib.lp_sf_source(B, T, hop, K, _ptr(p), _ptr(n), _ptr(C), _ptr(gain), _ptr(u), _ptr(x), st))
     us_fir = timed(lambda: lib.lp_fir(B, T, K2, _ptr(x), _ptr(h), _ptr(y), st))
+    gC, gg, gs, gh = torch.empty_like(C), torch.empty_like(gain), torch.empty_like(p), torch.empty_like(h)
+    work = torch.empty(lib.lp_fir_adjoint_work_bytes(B, T, K2), dtype=torch.uint8, device=dev)
+    us_src_adj = timed(lambda: lib.lp_sf_source_adjoint(B, T, hop, K, _ptr(gy), _ptr(u), _ptr(n), _ptr(gain),
+                                                        _ptr(gs), _ptr(gC), _ptr(gg), st))
+    us_fir_adj = timed(lambda: lib.lp_fir_adjoint(B, T, K2, _ptr(gy), _ptr(x), _ptr(h), _ptr(gs), _ptr(gh),
+                                                  _ptr(work), st))
     flops_src = 2.0 * B * T * K
     flops_fir = 2.0 * B * T * K2
     return {"workload": f"sf_synth_b{B}_t{T}_m{M}_hop{hop}_k{K}_fir{K2}", "ms_per_step": round(ms, 4),
             "samples_per_s": round(B * T / (ms * 1e-3), 1),
-            "kernels_us": {"source_fir_noise": round(us_src, 2), "output_fir": round(us_fir, 2)},
+            "kernels_us": {"source_fir_noise": round(us_src, 2), "output_fir": round(us_fir, 2),
+                           "source_adjoint": round(us_src_adj, 2), "output_fir_adjoint": round(us_fir_adj, 2)},
             "source_fir_noise_TFLOPs_f32": round(flops_src / (us_src * 1e-6) / 1e12, 2),
             "output_fir_TFLOPs_f32": round(flops_fir / (us_fir * 1e-6) / 1e12, 2),
+            "source_adjoint_TFLOPs_f32": round(flops_src / (us_src_adj * 1e-6) / 1e12, 2),
+            "output_fir_adjoint_TFLOPs_f32": round(2 * flops_fir / (us_fir_adj * 1e-6) / 1e12, 2),
             "fp32_vector_peak_TFLOPs": FP32_PEAK_TFLOPS,
             "note": "one step = source, frame-rate LP, output FIR and the adjoint of each; LP parts as in the "
                     "frame-rate section"}

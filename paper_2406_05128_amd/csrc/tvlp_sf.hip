@@ -65,6 +65,129 @@ __global__ __launch_bounds__(TT) void k_sf_source(int64_t T, int hop, int K, int
     x[b * T + t] = lerp_gain(gain + b * F, t, hop) * uu;
 }
 
+// The same source, register-blocked: a block of SW_WAVES waves covers
+// SW_WAVES * TT consecutive outputs, each wave TT of them, RB per lane (lane j:
+// t_j = t0 + RB j .. + RB - 1); the frame rows of taps the block reads are
+// staged in LDS once, with PAD zeros on either side, so that each wave walks the
+// input samples tau of its tile in lockstep (taps outside a row read zeros).  Each lane keeps the window of RB taps C[q][t_j + r - tau]; when
+// tau advances, the tap entering lane j's window is the one leaving lane j-1's,
+// so it moves one lane up by a wave-wide DPP shift, lane 0 taking it from a
+// broadcast read of the row.  Per tau: two broadcast LDS reads (n and lane 0's
+// tap), one DPP move and RB FMAs.
+constexpr int RB = 4;
+constexpr int PAD = TT + 2 * RB;
+constexpr int SW_WAVES = 4;
+constexpr int DPP_WAVE_SHR1 = 0x138;  // lane i <- lane i-1 across the wave (lane 0 keeps `old`)
+constexpr int DPP_WAVE_SHL1 = 0x130;  // lane i <- lane i+1 across the wave (lane 63 keeps `old`)
+
+template <int CTRL>
+__device__ __forceinline__ float wave_shift(float v, float old) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+__global__ __launch_bounds__(64 * SW_WAVES) void k_sf_source_rb(int64_t T, int hop, int K, int64_t F,
+                                                                const float *__restrict__ p,
+                                                                const float *__restrict__ n,
+                                                                const float *__restrict__ C,
+                                                                const float *__restrict__ gain,
+                                                                float *__restrict__ u, float *__restrict__ x) {
+    extern __shared__ float sh[];
+    constexpr int BT = SW_WAVES * TT;  // outputs per block
+    const int SW = K + 2 * PAD;        // staged row width
+    const int64_t b = blockIdx.y;
+    const int64_t t0b = (int64_t)blockIdx.x * BT;
+    const int64_t tlo = t0b - (K - 1);                              // first input sample of the block
+    const int64_t qlo = (tlo > 0 ? tlo : 0) / hop;
+    const int64_t tlast = t0b + BT - 1 < T - 1 ? t0b + BT - 1 : T - 1;
+    const int nrow = (int)(tlast / hop - qlo + 1);
+    float *ns = sh;                  // n(tau) at tau - tlo, BT + K - 1 floats
+    float *rows = sh + BT + K - 1;   // staged rows, nrow x SW
+    const float *nb = n + b * T;
+    for (int i = threadIdx.x; i < BT + K - 1; i += 64 * SW_WAVES) {
+        const int64_t tau = tlo + i;
+        ns[i] = (tau >= 0 && tau < T) ? nb[tau] : 0.f;
+    }
+    for (int r = 0; r < nrow; ++r) {
+        const float *Cq = C + (b * F + qlo + r) * K;
+        float *row = rows + r * SW;
+        for (int i = threadIdx.x; i < SW; i += 64 * SW_WAVES) {
+            const int k = i - PAD;
+            row[i] = (k >= 0 && k < K) ? Cq[k] : 0.f;
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t t0 = t0b + (int64_t)TT * (threadIdx.x >> 6);     // this wave's tile
+    if (t0 >= T) return;
+    const int64_t ta = t0 - (K - 1) > 0 ? t0 - (K - 1) : 0;         // the tile's first input sample
+    const int64_t tb = t0 + TT - 1 < T - 1 ? t0 + TT - 1 : T - 1;   // and last
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+    int64_t tau = ta;
+    while (tau <= tb) {
+        const int64_t q = tau / hop;
+        const int64_t end = (q + 1) * hop - 1 < tb ? (q + 1) * hop - 1 : tb;  // last tau of this frame's stretch
+        const float *row = rows + (q - qlo) * SW;
+        int b0 = (int)(PAD + t0 - tau);  // row index of lane 0's tap t0 - tau
+        const int bi = b0 + RB * lane;   // this lane's
+        float w0 = row[bi], w1 = row[bi + 1], w2 = row[bi + 2], w3 = row[bi + 3];
+        const float *nt = ns + (tau - tlo);
+        int cnt = (int)(end - tau + 1);
+        while (cnt >= 4) {
+            const float x1 = wave_shift<DPP_WAVE_SHR1>(w3, row[b0 - 1]);
+            const float x2 = wave_shift<DPP_WAVE_SHR1>(w2, row[b0 - 2]);
+            const float x3 = wave_shift<DPP_WAVE_SHR1>(w1, row[b0 - 3]);
+            const float x4 = wave_shift<DPP_WAVE_SHR1>(w0, row[b0 - 4]);
+            float v = nt[0];
+            a0 = __builtin_fmaf(w0, v, a0); a1 = __builtin_fmaf(w1, v, a1);
+            a2 = __builtin_fmaf(w2, v, a2); a3 = __builtin_fmaf(w3, v, a3);
+            v = nt[1];
+            a0 = __builtin_fmaf(x1, v, a0); a1 = __builtin_fmaf(w0, v, a1);
+            a2 = __builtin_fmaf(w1, v, a2); a3 = __builtin_fmaf(w2, v, a3);
+            v = nt[2];
+            a0 = __builtin_fmaf(x2, v, a0); a1 = __builtin_fmaf(x1, v, a1);
+            a2 = __builtin_fmaf(w0, v, a2); a3 = __builtin_fmaf(w1, v, a3);
+            v = nt[3];
+            a0 = __builtin_fmaf(x3, v, a0); a1 = __builtin_fmaf(x2, v, a1);
+            a2 = __builtin_fmaf(x1, v, a2); a3 = __builtin_fmaf(w0, v, a3);
+            w0 = x4; w1 = x3; w2 = x2; w3 = x1;
+            b0 -= 4;
+            nt += 4;
+            cnt -= 4;
+        }
+        while (cnt > 0) {
+            const float x1 = wave_shift<DPP_WAVE_SHR1>(w3, row[b0 - 1]);
+            const float v = nt[0];
+            a0 = __builtin_fmaf(w0, v, a0); a1 = __builtin_fmaf(w1, v, a1);
+            a2 = __builtin_fmaf(w2, v, a2); a3 = __builtin_fmaf(w3, v, a3);
+            w3 = w2; w2 = w1; w1 = w0; w0 = x1;
+            b0 -= 1;
+            nt += 1;
+            cnt -= 1;
+        }
+        tau = end + 1;
+    }
+    const float acc[RB] = {a0, a1, a2, a3};
+    const float *gb = gain + b * F;
+    const int64_t tj = t0 + RB * lane;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        const int64_t t = tj + r;
+        if (t < T) {
+            const float uu = p[b * T + t] + acc[r];
+            u[b * T + t] = uu;
+            x[b * T + t] = lerp_gain(gb, t, hop) * uu;
+        }
+    }
+}
+
+// Staged-row bytes of k_sf_source_rb for the worst block (0: the rows do not fit).
+size_t source_rb_lds(int hop, int K) {
+    const int64_t span = SW_WAVES * TT + K - 1;
+    const int64_t nrow = (span - 1) / hop + 2;
+    const size_t bytes = (size_t)(span + nrow * (K + 2 * PAD)) * sizeof(float);
+    return bytes <= 128 * 1024 ? bytes : 0;
+}
+
 // y(t) = sum_k h[k] s(t-k) (corr = 0), or the adjoint in s,
 // g_s(t) = sum_k h[k] g_y(t+k) (corr = 1).  LDS: the K taps, then the input over
 // [t0 - K + 1, t0 + TT) (convolution) or [t0, t0 + TT + K - 1) (correlation).
@@ -168,8 +291,12 @@ __global__ __launch_bounds__(256) void k_sf_gu(int64_t B, int64_t T, int hop, in
 //   dL/dC[q][k] = sum over the samples tau of frame q of g_u(tau + k) n(tau);
 //   dL/dgain[q] = sum over frame q of (1 - w) g_x u + sum over frame q-1 of w g_x u,
 //   w = (t - frame start) / hop.
-// LDS: n over frame q, g_u over [q hop, q hop + hop + K - 1), g_x u over
-// [(q-1) hop, (q+1) hop), a reduction buffer.
+// Taps: wave w, lane j owns k = 256 w + RB j + r (r < RB) and keeps the window
+// g_u(tau + k); when tau advances the element entering lane j's window is the
+// one leaving lane j+1's (a wave-wide DPP shift down; lane 63 reads it from
+// LDS).  LDS: n over frame q, g_u over [q hop, q hop + hop + GUW) (zeros
+// beyond the signal), g_x u over [(q-1) hop, (q+1) hop), a reduction buffer.
+constexpr int GUW = KMAX + 16;
 __global__ __launch_bounds__(256) void k_sf_frame_grads(int64_t T, int hop, int K, int64_t F,
                                                         const float *__restrict__ n, const float *__restrict__ gu,
                                                         const float *__restrict__ gx, const float *__restrict__ u,
@@ -178,16 +305,16 @@ __global__ __launch_bounds__(256) void k_sf_frame_grads(int64_t T, int hop, int 
     __shared__ double red[256];
     const int64_t q = blockIdx.x, b = blockIdx.y;
     const int64_t lo = q * hop;
-    float *ns = sh;                 // hop
-    float *gus = ns + hop;          // hop + K - 1
-    float *gxu = gus + hop + K - 1; // 2 hop, from (q-1) hop
+    float *ns = sh;                  // hop
+    float *gus = ns + hop;           // hop + GUW
+    float *gxu = gus + hop + GUW;    // 2 hop, from (q-1) hop
     for (int i = threadIdx.x; i < hop; i += blockDim.x) {
         const int64_t t = lo + i;
         ns[i] = t < T ? n[b * T + t] : 0.f;
     }
-    for (int i = threadIdx.x; i < hop + K - 1; i += blockDim.x) {
+    for (int i = threadIdx.x; i < hop + GUW; i += blockDim.x) {
         const int64_t t = lo + i;
-        gus[i] = t < T ? gu[b * T + t] : 0.f;
+        gus[i] = (i < hop + K - 1 && t < T) ? gu[b * T + t] : 0.f;
     }
     for (int i = threadIdx.x; i < 2 * hop; i += blockDim.x) {
         const int64_t t = lo - hop + i;
@@ -195,16 +322,45 @@ __global__ __launch_bounds__(256) void k_sf_frame_grads(int64_t T, int hop, int 
     }
     __syncthreads();
     // the frame's taps (frames at or beyond the signal's end get zeros)
-    float *gCq = gC + (b * F + q) * K;
-    for (int k = threadIdx.x; k < K; k += blockDim.x) {
-        float acc0 = 0.f, acc1 = 0.f;
+    {
+        const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const int kw = 256 * wv;                   // the wave's first tap
+        const int k0 = kw + RB * lane;             // this lane's first tap
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+        float w0 = gus[k0], w1 = gus[k0 + 1], w2 = gus[k0 + 2], w3 = gus[k0 + 3];
+        const float *g63 = gus + kw + 256;  // lane 63's entering elements: g63[i + s - 1] at step i + s
         int i = 0;
-        for (; i + 1 < hop; i += 2) {
-            acc0 = __builtin_fmaf(gus[i + k], ns[i], acc0);
-            acc1 = __builtin_fmaf(gus[i + k + 1], ns[i + 1], acc1);
+        for (; i + 4 <= hop; i += 4) {
+            const float y1 = wave_shift<DPP_WAVE_SHL1>(w0, g63[i]);
+            const float y2 = wave_shift<DPP_WAVE_SHL1>(w1, g63[i + 1]);
+            const float y3 = wave_shift<DPP_WAVE_SHL1>(w2, g63[i + 2]);
+            const float y4 = wave_shift<DPP_WAVE_SHL1>(w3, g63[i + 3]);
+            float v = ns[i];
+            a0 = __builtin_fmaf(w0, v, a0); a1 = __builtin_fmaf(w1, v, a1);
+            a2 = __builtin_fmaf(w2, v, a2); a3 = __builtin_fmaf(w3, v, a3);
+            v = ns[i + 1];
+            a0 = __builtin_fmaf(w1, v, a0); a1 = __builtin_fmaf(w2, v, a1);
+            a2 = __builtin_fmaf(w3, v, a2); a3 = __builtin_fmaf(y1, v, a3);
+            v = ns[i + 2];
+            a0 = __builtin_fmaf(w2, v, a0); a1 = __builtin_fmaf(w3, v, a1);
+            a2 = __builtin_fmaf(y1, v, a2); a3 = __builtin_fmaf(y2, v, a3);
+            v = ns[i + 3];
+            a0 = __builtin_fmaf(w3, v, a0); a1 = __builtin_fmaf(y1, v, a1);
+            a2 = __builtin_fmaf(y2, v, a2); a3 = __builtin_fmaf(y3, v, a3);
+            w0 = y1; w1 = y2; w2 = y3; w3 = y4;
         }
-        if (i < hop) acc0 = __builtin_fmaf(gus[i + k], ns[i], acc0);
-        gCq[k] = acc0 + acc1;
+        for (; i < hop; ++i) {
+            const float y1 = wave_shift<DPP_WAVE_SHL1>(w0, g63[i]);
+            const float v = ns[i];
+            a0 = __builtin_fmaf(w0, v, a0); a1 = __builtin_fmaf(w1, v, a1);
+            a2 = __builtin_fmaf(w2, v, a2); a3 = __builtin_fmaf(w3, v, a3);
+            w0 = w1; w1 = w2; w2 = w3; w3 = y1;
+        }
+        float *gCq = gC + (b * F + q) * K;
+        const float acc[RB] = {a0, a1, a2, a3};
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+            if (k0 + r < K) gCq[k0 + r] = acc[r];
     }
     // the frame's gain
     double acc = 0.0;
@@ -253,9 +409,14 @@ int lp_sf_source(int64_t B, int64_t T, int64_t hop, int64_t K, const float *p, c
     if (!p || !n || !C || !gain || !u || !x) return fail(LP_EINVAL, "lp_sf_source: null pointer");
     if (B > 65535) return fail(LP_EINVAL, "lp_sf_source: B > 65535");
     const int64_t F = (T - 1) / hop + 2;
-    hipLaunchKernelGGL(k_sf_source, dim3((unsigned)ceil_div(T, TT), (unsigned)B), dim3(TT),
-                       (size_t)(TT + K - 1) * sizeof(float), (hipStream_t)stream, T, (int)hop, (int)K, F, p, n, C,
-                       gain, u, x);
+    if (const size_t lds = source_rb_lds((int)hop, (int)K))
+        hipLaunchKernelGGL(k_sf_source_rb, dim3((unsigned)ceil_div(T, SW_WAVES * TT), (unsigned)B),
+                           dim3(64 * SW_WAVES), lds, (hipStream_t)stream, T, (int)hop, (int)K, F, p, n, C, gain, u,
+                           x);
+    else  // short frames: too many tap rows per tile to stage
+        hipLaunchKernelGGL(k_sf_source, dim3((unsigned)ceil_div(T, TT), (unsigned)B), dim3(TT),
+                           (size_t)(TT + K - 1) * sizeof(float), (hipStream_t)stream, T, (int)hop, (int)K, F, p, n,
+                           C, gain, u, x);
     return launched("lp_sf_source");
 }
 
@@ -302,8 +463,7 @@ int lp_sf_source_adjoint(int64_t B, int64_t T, int64_t hop, int64_t K, const flo
     hipLaunchKernelGGL(k_sf_gu, dim3((unsigned)ceil_div(B * T, 256)), dim3(256), 0, st, B, T, (int)hop, F, gx, gain,
                        gu);
     hipLaunchKernelGGL(k_sf_frame_grads, dim3((unsigned)F, (unsigned)B), dim3(256),
-                       (size_t)(4 * hop + K - 1) * sizeof(float), st, T, (int)hop, (int)K, F, n, gu, gx, u, gC,
-                       ggain);
+                       (size_t)(4 * hop + GUW) * sizeof(float), st, T, (int)hop, (int)K, F, n, gu, gx, u, gC, ggain);
     return launched("lp_sf_source_adjoint");
 }
 
