@@ -32,12 +32,12 @@ FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published
 # plain 256 MiB device copy) for the training workload, per chunk length; valid only for the
 # kernel sources (hash below) they were measured with, otherwise reported as null.
 TRAFFIC = {
-    "sources_sha256": "5d3b181c94b8747b4122b41ef8d8a28989f45ebf690e848bd2e21a2833592d3b",
+    "sources_sha256": "f191d16111d648a8dc183d0b5bee67a3722ba7f3d756b8dfb1a9ad51dab3237d",
     "bytes_by_chunk": {
-        396: {"fwd_scan": 324527125, "fwd_emit": 298715267, "bwd_scan": 622986201, "bwd_emit": 582633733},
-        418: {"fwd_scan": 320113421, "fwd_emit": 298772315, "bwd_scan": 621053607, "bwd_emit": 582591922},
-        506: {"fwd_scan": 311577229, "fwd_emit": 297905204, "bwd_scan": 610797105, "bwd_emit": 581765403},
-        528: {"fwd_scan": 309550867, "fwd_emit": 296563348, "bwd_scan": 605901313, "bwd_emit": 580395217},
+        396: {"fwd_scan": 324805158, "fwd_emit": 298723397, "bwd_scan": 623040382, "bwd_emit": 582640980},
+        418: {"fwd_scan": 320048087, "fwd_emit": 298723848, "bwd_scan": 620960147, "bwd_emit": 582577981},
+        506: {"fwd_scan": 311561007, "fwd_emit": 297906089, "bwd_scan": 610829156, "bwd_emit": 581765767},
+        528: {"fwd_scan": 309554088, "fwd_emit": 296567500, "bwd_scan": 605927092, "bwd_emit": 580396459},
     },
 }
 
