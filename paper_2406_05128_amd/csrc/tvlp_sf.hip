@@ -188,45 +188,59 @@ size_t source_rb_lds(int hop, int K) {
     return bytes <= 128 * 1024 ? bytes : 0;
 }
 
-// y(t) = sum_k h[k] s(t-k) (corr = 0), or the adjoint in s,
-// g_s(t) = sum_k h[k] g_y(t+k) (corr = 1).  LDS: the K taps, then the input over
-// [t0 - K + 1, t0 + TT) (convolution) or [t0, t0 + TT + K - 1) (correlation).
-__global__ __launch_bounds__(TT) void k_fir(int64_t T, int K, const float *__restrict__ in,
-                                            const float *__restrict__ h, float *__restrict__ out, int corr) {
+// The output FIR register-blocked: a block of SW_WAVES waves covers
+// SW_WAVES * TT outputs, RB per lane (lane j: t_j = t0 + RB j ..); per tap k every
+// lane updates its RB outputs from a window of RB input samples, which slides by
+// one sample per tap: the entering sample is the one leaving the neighbouring
+// lane's window (wave-wide DPP shift; the edge lane reads it from LDS).
+// Convolution (CORR = false): y(t) = sum_k h[k] s(t - k), window s(t_j + r - k),
+// entering from lane j-1.  Correlation (CORR = true): g_s(t) = sum_k h[k] g_y(t + k),
+// window g_y(t_j + r + k), entering from lane j+1.  LDS: the K taps, then the
+// input over [t0 - K + 1, t0 + BT) or [t0, t0 + BT + K - 1), zeros outside the
+// signal, plus RB floats of slack.
+template <bool CORR>
+__global__ __launch_bounds__(64 * SW_WAVES) void k_fir_rb(int64_t T, int K, const float *__restrict__ in,
+                                                          const float *__restrict__ h, float *__restrict__ out) {
     extern __shared__ float sh[];
+    constexpr int BT = SW_WAVES * TT;
     float *hs = sh;
     float *xs = sh + K;
     const int64_t b = blockIdx.y;
-    const int64_t t0 = (int64_t)blockIdx.x * TT;
-    const int64_t base = corr ? t0 : t0 - (K - 1);
+    const int64_t t0b = (int64_t)blockIdx.x * BT;
+    const int64_t base = CORR ? t0b : t0b - (K - 1);  // input sample of xs[0]
     const float *ib = in + b * T;
-    for (int i = threadIdx.x; i < K; i += TT) hs[i] = h[i];
-    for (int i = threadIdx.x; i < TT + K - 1; i += TT) {
+    for (int i = threadIdx.x; i < K; i += 64 * SW_WAVES) hs[i] = h[i];
+    for (int i = threadIdx.x; i < BT + K - 1 + RB; i += 64 * SW_WAVES) {
         const int64_t tau = base + i;
         xs[i] = (tau >= 0 && tau < T) ? ib[tau] : 0.f;
     }
     __syncthreads();
-    const int64_t t = t0 + threadIdx.x;
-    if (t >= T) return;
-    float acc0 = 0.f, acc1 = 0.f;
-    const int li = threadIdx.x;
-    if (corr) {
-        int k = 0;
-        for (; k + 1 < K; k += 2) {
-            acc0 = __builtin_fmaf(hs[k], xs[li + k], acc0);
-            acc1 = __builtin_fmaf(hs[k + 1], xs[li + k + 1], acc1);
+    const int lane = threadIdx.x & 63;
+    const int64_t t0 = t0b + (int64_t)TT * (threadIdx.x >> 6);
+    if (t0 >= T) return;
+    const int o0 = (int)(t0 - base);  // xs index of input sample t0 (convolution) / t0 (correlation)
+    const int oj = o0 + RB * lane;    // this lane's t_j
+    float w0 = xs[oj], w1 = xs[oj + 1], w2 = xs[oj + 2], w3 = xs[oj + 3];  // window at k = 0
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+    for (int k = 0; k < K; ++k) {
+        const float hk = hs[k];
+        a0 = __builtin_fmaf(hk, w0, a0); a1 = __builtin_fmaf(hk, w1, a1);
+        a2 = __builtin_fmaf(hk, w2, a2); a3 = __builtin_fmaf(hk, w3, a3);
+        if constexpr (CORR) {
+            // next window g_y(t_j + r + k + 1): w0..w2 <- w1..w3, w3 <- lane j+1's w0
+            const float e = wave_shift<DPP_WAVE_SHL1>(w0, xs[o0 + 256 + k]);
+            w0 = w1; w1 = w2; w2 = w3; w3 = e;
+        } else {
+            // next window s(t_j + r - k - 1): w1..w3 <- w0..w2, w0 <- lane j-1's w3
+            const float e = wave_shift<DPP_WAVE_SHR1>(w3, xs[o0 - 1 - k]);
+            w3 = w2; w2 = w1; w1 = w0; w0 = e;
         }
-        if (k < K) acc0 = __builtin_fmaf(hs[k], xs[li + k], acc0);
-    } else {
-        const int c = li + K - 1;  // xs index of s(t)
-        int k = 0;
-        for (; k + 1 < K; k += 2) {
-            acc0 = __builtin_fmaf(hs[k], xs[c - k], acc0);
-            acc1 = __builtin_fmaf(hs[k + 1], xs[c - k - 1], acc1);
-        }
-        if (k < K) acc0 = __builtin_fmaf(hs[k], xs[c - k], acc0);
     }
-    out[b * T + t] = acc0 + acc1;
+    const float acc[RB] = {a0, a1, a2, a3};
+    const int64_t tj = t0 + RB * lane;
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+        if (tj + r < T) out[b * T + tj + r] = acc[r];
 }
 
 constexpr int GT = 1024;  // samples per tile of the output-FIR gradient
@@ -424,8 +438,9 @@ int lp_fir(int64_t B, int64_t T, int64_t K, const float *s, const float *h, floa
     if (B < 1 || T < 1 || K < 1 || K > KMAX || B > 65535)
         return fail(LP_EINVAL, "lp_fir: need B in [1, 65535], T >= 1, 1 <= K <= 1024");
     if (!s || !h || !y) return fail(LP_EINVAL, "lp_fir: null pointer");
-    hipLaunchKernelGGL(k_fir, dim3((unsigned)ceil_div(T, TT), (unsigned)B), dim3(TT),
-                       (size_t)(TT + 2 * K - 1) * sizeof(float), (hipStream_t)stream, T, (int)K, s, h, y, 0);
+    hipLaunchKernelGGL(k_fir_rb<false>, dim3((unsigned)ceil_div(T, SW_WAVES * TT), (unsigned)B),
+                       dim3(64 * SW_WAVES), (size_t)(SW_WAVES * TT + 2 * K - 1 + RB) * sizeof(float),
+                       (hipStream_t)stream, T, (int)K, s, h, y);
     return launched("lp_fir");
 }
 
@@ -441,8 +456,9 @@ int lp_fir_adjoint(int64_t B, int64_t T, int64_t K, const float *gy, const float
     if (!gy || !h || (gh && (!s || !work))) return fail(LP_EINVAL, "lp_fir_adjoint: null pointer");
     hipStream_t st = (hipStream_t)stream;
     if (gs)
-        hipLaunchKernelGGL(k_fir, dim3((unsigned)ceil_div(T, TT), (unsigned)B), dim3(TT),
-                           (size_t)(TT + 2 * K - 1) * sizeof(float), st, T, (int)K, gy, h, gs, 1);
+        hipLaunchKernelGGL(k_fir_rb<true>, dim3((unsigned)ceil_div(T, SW_WAVES * TT), (unsigned)B),
+                           dim3(64 * SW_WAVES), (size_t)(SW_WAVES * TT + 2 * K - 1 + RB) * sizeof(float), st, T,
+                           (int)K, gy, h, gs);
     if (gh) {
         const int64_t nt = ceil_div(T, GT);
         float *part = (float *)work;
