@@ -69,3 +69,68 @@ def lp(e: torch.Tensor, a: torch.Tensor, zi: Optional[torch.Tensor] = None, chun
     store_s=True keeps s for the backward instead of recomputing it per chunk.
     """
     return LPFunction.apply(e, a, zi, chunk, store_s)
+
+
+class LPFramesFunction(torch.autograd.Function):
+    """The filter with frame-rate coefficients interpolated in the kernels (Sec. 4.3)."""
+
+    @staticmethod
+    def forward(ctx, e: torch.Tensor, A: torch.Tensor, hop: int, zi: Optional[torch.Tensor],
+                chunk: Optional[int], store_s: bool):
+        e = e.contiguous()
+        A = A.contiguous()
+        plan = get_plan(A.shape[-1], e.device, chunk)
+        s, _, saved = plan.forward_frames(e, A, hop, zi, save=True)
+        ctx.plan, ctx.hop, ctx.store_s = plan, hop, store_s
+        ctx.save_for_backward(e, A, zi, saved, s if store_s else None)
+        return s
+
+    @staticmethod
+    def backward(ctx, g: torch.Tensor):
+        e, A, zi, saved, s = ctx.saved_tensors
+        need_e, need_a, need_zi = ctx.needs_input_grad[0], ctx.needs_input_grad[1], ctx.needs_input_grad[3]
+        if not (need_e or need_a or need_zi):
+            return None, None, None, None, None, None
+        ge, gA, gz = ctx.plan.backward_frames(g.contiguous().float(), A, ctx.hop, e, saved, s=s, zi=zi,
+                                              need_e=need_e, need_a=need_a,
+                                              need_zi=bool(need_zi and zi is not None))
+        return ge, gA, None, gz, None, None
+
+
+def lp_frames(e: torch.Tensor, A: torch.Tensor, hop: int, zi: Optional[torch.Tensor] = None,
+              chunk: Optional[int] = None, store_s: bool = False) -> torch.Tensor:
+    """The filter with frame-rate LP coefficients A [B,F,M] (frame q at sample q*hop,
+    F = coef_frames_count(T, hop)) linearly upsampled inside the kernels;
+    differentiable in e, A and zi."""
+    return LPFramesFunction.apply(e, A, hop, zi, chunk, store_s)
+
+
+class SFSynthFunction(torch.autograd.Function):
+    """y = h * LP_A(gamma (p + C * n)) (Eq. 5 with the output FIR), differentiable in
+    p, C, gain, A and h (the noise n is a fixed input)."""
+
+    @staticmethod
+    def forward(ctx, p, n, C, gain, A, h, hop: int, chunk: Optional[int]):
+        from .sf import SFSynth
+        key = (A.shape[-1], hop, C.shape[-1], h.shape[0], p.device, chunk)
+        syn = _SF_CACHE.get(key)
+        if syn is None:
+            syn = _SF_CACHE[key] = SFSynth(A.shape[-1], hop, C.shape[-1], h.shape[0], p.device, chunk)
+        y, inner = syn.forward(*(t.contiguous() for t in (p, n, C, gain, A, h)))
+        ctx.syn, ctx.inner = syn, inner
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        gp, gC, gg, gA, gh = ctx.syn.backward(gy.contiguous().float(), ctx.inner)
+        need = ctx.needs_input_grad
+        return (gp if need[0] else None, None, gC if need[2] else None, gg if need[3] else None,
+                gA if need[4] else None, gh if need[5] else None, None, None)
+
+
+_SF_CACHE: dict = {}
+
+
+def sf_synth(p, n, C, gain, A, h, hop: int, chunk: Optional[int] = None) -> torch.Tensor:
+    """Source-filter synthesiser around the LP filter; see SFSynth for the layouts."""
+    return SFSynthFunction.apply(p, n, C, gain, A, h, hop, chunk)

@@ -722,3 +722,38 @@ def test_sf_rejects_out_of_range_sizes(tv):
     assert lib.lp_fir(1, 4, 1025, P, P, P, None) == -1
     assert b"K" in lib.lp_sf_last_error()
     assert lib.lp_sf_source(1, 4, 5000, 2, P, P, P, P, P, P, None) == -1
+
+
+def test_autograd_frame_rate_and_synthesiser(tv):
+    """torch.autograd wrappers: lp_frames (grads of e, A and zi) and sf_synth (grads
+    of p, C, gain, A, h) against the oracle."""
+    B, T, M, hop = 2, 2500, 16, 120
+    e, A, g = _frame_inputs(B, T, M, hop, seed=88)
+    zi = np.random.default_rng(3).standard_normal((B, M))
+    e_d = to_dev(e).requires_grad_(True)
+    A_d = to_dev(A).requires_grad_(True)
+    zi_d = to_dev(zi).requires_grad_(True)
+    s = tv.lp_frames(e_d, A_d, hop, zi_d, chunk=160)
+    s.backward(to_dev(g))
+    torch.cuda.synchronize()
+    s_ref, _ = oracle.lp_forward_frames(e, A, hop, zi)
+    ge_ref, gA_ref, gz_ref = oracle.lp_backward_frames(g, A, s_ref, hop, zi, need_grad_zi=True)
+    assert per_seq_err(host(s), s_ref) <= TOL
+    assert per_seq_err(host(e_d.grad), ge_ref) <= TOL
+    assert max(rms_rel(host(A_d.grad)[b], gA_ref[b]) for b in range(B)) <= TOL
+    assert rms_rel(host(zi_d.grad), gz_ref) <= TOL
+
+    K, K2 = 40, 9
+    p, n, C, gain, A, h, gy = _sf_inputs(B, T, M, hop, K, K2, seed=89)
+    leaves = [to_dev(x).requires_grad_(True) for x in (p, C, gain, A, h)]
+    p_d, C_d, g_d, A_d, h_d = leaves
+    y = tv.sf_synth(p_d, to_dev(n), C_d, g_d, A_d, h_d, hop)
+    y.backward(to_dev(gy))
+    torch.cuda.synchronize()
+    y_ref, inter = oracle.sf_forward(p, n, C, gain, A, h, hop)
+    refs = oracle.sf_backward(gy, n, C, gain, A, h, inter, hop)
+    assert per_seq_err(host(y), y_ref) <= TOL
+    for leaf, ref, name in zip(leaves, refs, ("p", "C", "gain", "A", "h")):
+        got = host(leaf.grad)
+        err = rms_rel(got, ref) if name == "h" else max(rms_rel(got[b], ref[b]) for b in range(B))
+        assert err <= TOL, (name, err)
