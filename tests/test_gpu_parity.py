@@ -757,3 +757,45 @@ def test_autograd_frame_rate_and_synthesiser(tv):
         got = host(leaf.grad)
         err = rms_rel(got, ref) if name == "h" else max(rms_rel(got[b], ref[b]) for b in range(B))
         assert err <= TOL, (name, err)
+
+
+def test_frame_rate_hop1_equals_per_sample_rows(tv):
+    """hop 1: every sample is a frame sample, so the frame-rate path must give the
+    per-sample path's results for rows A[:, :T] (and a zero gradient for the extra
+    row), through different kernel instantiations."""
+    B, T, M, hop, L = 2, 3000, 22, 1, 44
+    e, A, g = _frame_inputs(B, T, M, hop, seed=12)
+    plan = tv.Plan(M, dev(), L)
+    e_d, A_d, g_d = to_dev(e), to_dev(A), to_dev(g)
+    a_d = A_d[:, :T].contiguous()
+    s_f, _, sv_f = plan.forward_frames(e_d, A_d, hop)
+    ge_f, gA_f, _ = plan.backward_frames(g_d, A_d, hop, e_d, sv_f)
+    s_p, _, sv_p = plan.forward(e_d, a_d)
+    ge_p, ga_p, _ = plan.backward(g_d, a_d, e_d, sv_p)
+    plan.check_status()
+    torch.cuda.synchronize()
+    assert per_seq_err(host(s_f), host(s_p).astype(np.float64)) <= 1e-6
+    assert per_seq_err(host(ge_f), host(ge_p).astype(np.float64)) <= 1e-6
+    for b in range(B):
+        assert rms_rel(host(gA_f)[b, :T], host(ga_p)[b].astype(np.float64)) <= 1e-5, b
+    assert np.all(host(gA_f)[:, T] == 0.0)
+
+
+@pytest.mark.parametrize("T", [100, 239, 241, 700])
+def test_sf_synth_short_signals(tv, T):
+    """The synthesiser on signals shorter than a frame (hop 240) and than the noise
+    filter (510 taps), against the oracle."""
+    B, M, hop, K, K2 = 2, 22, 240, 510, 128
+    p, n, C, gain, A, h, gy = _sf_inputs(B, T, M, hop, K, K2, seed=T)
+    syn = tv.SFSynth(M, hop, K, K2, dev(), chunk=264)
+    y, ctx = syn.forward(*map(to_dev, (p, n, C, gain, A, h)))
+    gp, gC, gg, gA, gh = syn.backward(to_dev(gy), ctx)
+    syn.plan.check_status()
+    torch.cuda.synchronize()
+    y_ref, inter = oracle.sf_forward(p, n, C, gain, A, h, hop)
+    refs = oracle.sf_backward(gy, n, C, gain, A, h, inter, hop)
+    assert per_seq_err(host(y), y_ref) <= TOL
+    for got, ref, name in zip((gp, gC, gg, gA, gh), refs, ("p", "C", "gain", "A", "h")):
+        got = host(got)
+        err = rms_rel(got, ref) if name == "h" else max(rms_rel(got[b], ref[b]) for b in range(B))
+        assert err <= TOL, (name, err)
