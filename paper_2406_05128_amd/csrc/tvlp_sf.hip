@@ -245,33 +245,56 @@ __global__ __launch_bounds__(64 * SW_WAVES) void k_fir_rb(int64_t T, int K, cons
 
 constexpr int GT = 1024;  // samples per tile of the output-FIR gradient
 
-// Partial dL/dh[k] = sum over one tile of sum_t g_y(t) s(t-k), per (sequence,
-// tile); LDS: g_y over the tile, s over [t0 - K + 1, t0 + GT).
+// Partial dL/dh[k] = sum_t g_y(t) s(t-k) over one quarter of a tile (wave w of
+// the block takes samples t0 + 256 w .. + 255), per (sequence, tile, wave).
+// Lane j owns taps k = 64 RT g + RT j + r (r < RT) of tap group g and keeps the
+// window s(t - k); when t advances, the element entering lane j's window is the
+// one leaving lane j-1's (wave-wide DPP shift; lane 0 reads it from LDS).
+// LDS: g_y over the tile, s over [t0 - K + 1, t0 + GT] (zeros outside the signal;
+// the last element is only read as the window's unused look-ahead).
+template <int RT>
 __global__ __launch_bounds__(256) void k_fir_gh_part(int64_t T, int K, const float *__restrict__ gy,
                                                      const float *__restrict__ s, float *__restrict__ part) {
     extern __shared__ float sh[];
     float *gs = sh;        // GT
-    float *ss = sh + GT;   // GT + K - 1
+    float *ss = sh + GT;   // GT + K
     const int64_t b = blockIdx.y;
     const int64_t t0 = (int64_t)blockIdx.x * GT;
     for (int i = threadIdx.x; i < GT; i += blockDim.x) {
         const int64_t t = t0 + i;
         gs[i] = t < T ? gy[b * T + t] : 0.f;
     }
-    for (int i = threadIdx.x; i < GT + K - 1; i += blockDim.x) {
+    for (int i = threadIdx.x; i < GT + K; i += blockDim.x) {
         const int64_t tau = t0 - (K - 1) + i;
         ss[i] = (tau >= 0 && tau < T) ? s[b * T + tau] : 0.f;
     }
     __syncthreads();
-    float *pb = part + ((int64_t)b * gridDim.x + blockIdx.x) * K;
-    for (int k = threadIdx.x; k < K; k += blockDim.x) {
-        float acc0 = 0.f, acc1 = 0.f;
-        const float *sk = ss + (K - 1 - k);  // sk[i] = s(t0 + i - k)
-        for (int i = 0; i < GT; i += 2) {
-            acc0 = __builtin_fmaf(gs[i], sk[i], acc0);
-            acc1 = __builtin_fmaf(gs[i + 1], sk[i + 1], acc1);
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i0 = 256 * wv;  // the wave's first sample in the tile
+    float *pb = part + (((int64_t)b * gridDim.x + blockIdx.x) * 4 + wv) * K;
+    for (int kg = 0; kg < K; kg += 64 * RT) {
+        const int k0 = kg + RT * lane;
+        // ss index of s(t0 + i - k) is i - k + K - 1
+        float w[RT], acc[RT];
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+            const int k = k0 + r;
+            w[r] = k < K ? ss[i0 - k + K - 1] : 0.f;
+            acc[r] = 0.f;
         }
-        pb[k] = acc0 + acc1;
+        for (int i = i0; i < i0 + 256; ++i) {
+            const float gv = gs[i];
+#pragma unroll
+            for (int r = 0; r < RT; ++r) acc[r] = __builtin_fmaf(gv, w[r], acc[r]);
+            // next window s(t0 + i + 1 - k): w[r] <- w[r-1], w[0] <- lane j-1's w[RT-1]
+            const float e = wave_shift<DPP_WAVE_SHR1>(w[RT - 1], ss[i + 1 - kg + K - 1]);
+#pragma unroll
+            for (int r = RT - 1; r > 0; --r) w[r] = w[r - 1];
+            w[0] = e;
+        }
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+            if (k0 + r < K) pb[k0 + r] = acc[r];
     }
 }
 
@@ -446,7 +469,7 @@ int lp_fir(int64_t B, int64_t T, int64_t K, const float *s, const float *h, floa
 
 size_t lp_fir_adjoint_work_bytes(int64_t B, int64_t T, int64_t K) {
     if (B < 1 || T < 1 || K < 1) return 0;
-    return (size_t)B * ceil_div(T, GT) * K * sizeof(float);
+    return (size_t)B * ceil_div(T, GT) * 4 * K * sizeof(float);  // one partial row per wave of each tile
 }
 
 int lp_fir_adjoint(int64_t B, int64_t T, int64_t K, const float *gy, const float *s, const float *h, float *gs,
@@ -462,9 +485,14 @@ int lp_fir_adjoint(int64_t B, int64_t T, int64_t K, const float *gy, const float
     if (gh) {
         const int64_t nt = ceil_div(T, GT);
         float *part = (float *)work;
-        hipLaunchKernelGGL(k_fir_gh_part, dim3((unsigned)nt, (unsigned)B), dim3(256),
-                           (size_t)(2 * GT + K - 1) * sizeof(float), st, T, (int)K, gy, s, part);
-        hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)K), dim3(256), 0, st, B * nt, (int)K, part, gh);
+        const size_t lds = (size_t)(2 * GT + K) * sizeof(float);
+        if (K <= 128)
+            hipLaunchKernelGGL(k_fir_gh_part<2>, dim3((unsigned)nt, (unsigned)B), dim3(256), lds, st, T, (int)K, gy,
+                               s, part);
+        else
+            hipLaunchKernelGGL(k_fir_gh_part<4>, dim3((unsigned)nt, (unsigned)B), dim3(256), lds, st, T, (int)K, gy,
+                               s, part);
+        hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)K), dim3(256), 0, st, B * nt * 4, (int)K, part, gh);
     }
     return launched("lp_fir_adjoint");
 }
