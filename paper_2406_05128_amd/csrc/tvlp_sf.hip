@@ -245,19 +245,22 @@ __global__ __launch_bounds__(64 * SW_WAVES) void k_fir_rb(int64_t T, int K, cons
 
 constexpr int GT = 1024;  // samples per tile of the output-FIR gradient
 
-// Partial dL/dh[k] = sum_t g_y(t) s(t-k) over one quarter of a tile (wave w of
-// the block takes samples t0 + 256 w .. + 255), per (sequence, tile, wave).
+// Partial dL/dh[k] = sum_t g_y(t) s(t-k) over one tile, per (sequence, tile):
+// wave w of the block takes samples t0 + 256 w .. + 255 and the four waves'
+// sums are added in LDS.
 // Lane j owns taps k = 64 RT g + RT j + r (r < RT) of tap group g and keeps the
 // window s(t - k); when t advances, the element entering lane j's window is the
 // one leaving lane j-1's (wave-wide DPP shift; lane 0 reads it from LDS).
 // LDS: g_y over the tile, s over [t0 - K + 1, t0 + GT] (zeros outside the signal;
-// the last element is only read as the window's unused look-ahead).
+// the last element is only read as the window's unused look-ahead), then the
+// waves' sums [4][K].
 template <int RT>
 __global__ __launch_bounds__(256) void k_fir_gh_part(int64_t T, int K, const float *__restrict__ gy,
                                                      const float *__restrict__ s, float *__restrict__ part) {
     extern __shared__ float sh[];
     float *gs = sh;        // GT
     float *ss = sh + GT;   // GT + K
+    float *wsum = ss + GT + K;  // 4 x K
     const int64_t b = blockIdx.y;
     const int64_t t0 = (int64_t)blockIdx.x * GT;
     for (int i = threadIdx.x; i < GT; i += blockDim.x) {
@@ -271,7 +274,6 @@ __global__ __launch_bounds__(256) void k_fir_gh_part(int64_t T, int K, const flo
     __syncthreads();
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i0 = 256 * wv;  // the wave's first sample in the tile
-    float *pb = part + (((int64_t)b * gridDim.x + blockIdx.x) * 4 + wv) * K;
     for (int kg = 0; kg < K; kg += 64 * RT) {
         const int k0 = kg + RT * lane;
         // ss index of s(t0 + i - k) is i - k + K - 1
@@ -294,8 +296,12 @@ __global__ __launch_bounds__(256) void k_fir_gh_part(int64_t T, int K, const flo
         }
 #pragma unroll
         for (int r = 0; r < RT; ++r)
-            if (k0 + r < K) pb[k0 + r] = acc[r];
+            if (k0 + r < K) wsum[wv * K + k0 + r] = acc[r];
     }
+    __syncthreads();
+    float *pb = part + ((int64_t)b * gridDim.x + blockIdx.x) * K;
+    for (int k = threadIdx.x; k < K; k += blockDim.x)
+        pb[k] = (wsum[k] + wsum[K + k]) + (wsum[2 * K + k] + wsum[3 * K + k]);
 }
 
 // dL/dh[k] = sum of the npart partials (float64, fixed order); one block per k.
@@ -469,7 +475,7 @@ int lp_fir(int64_t B, int64_t T, int64_t K, const float *s, const float *h, floa
 
 size_t lp_fir_adjoint_work_bytes(int64_t B, int64_t T, int64_t K) {
     if (B < 1 || T < 1 || K < 1) return 0;
-    return (size_t)B * ceil_div(T, GT) * 4 * K * sizeof(float);  // one partial row per wave of each tile
+    return (size_t)B * ceil_div(T, GT) * K * sizeof(float);  // one partial row per tile
 }
 
 int lp_fir_adjoint(int64_t B, int64_t T, int64_t K, const float *gy, const float *s, const float *h, float *gs,
@@ -485,14 +491,14 @@ int lp_fir_adjoint(int64_t B, int64_t T, int64_t K, const float *gy, const float
     if (gh) {
         const int64_t nt = ceil_div(T, GT);
         float *part = (float *)work;
-        const size_t lds = (size_t)(2 * GT + K) * sizeof(float);
+        const size_t lds = (size_t)(2 * GT + 5 * K) * sizeof(float);
         if (K <= 128)
             hipLaunchKernelGGL(k_fir_gh_part<2>, dim3((unsigned)nt, (unsigned)B), dim3(256), lds, st, T, (int)K, gy,
                                s, part);
         else
             hipLaunchKernelGGL(k_fir_gh_part<4>, dim3((unsigned)nt, (unsigned)B), dim3(256), lds, st, T, (int)K, gy,
                                s, part);
-        hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)K), dim3(256), 0, st, B * nt * 4, (int)K, part, gh);
+        hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)K), dim3(256), 0, st, B * nt, (int)K, part, gh);
     }
     return launched("lp_fir_adjoint");
 }
