@@ -232,7 +232,8 @@ def time_invariant_bench(tv, B: int, T: int, M: int, L: int, steps: int, warmup:
                     "chunked rerun and adjoint kernels"}
 
 
-def frame_rate_bench(tv, B: int, T: int, M: int, L: int, steps: int, warmup: int, ms_samplewise: float):
+def frame_rate_bench(tv, B: int, T: int, M: int, L: int, steps: int, warmup: int, ms_samplewise: float,
+                     fixed_chunk: int = 0):
     """Training shape with frame-rate LP coefficients (Sec. 4.3: one row per
     240-sample frame, linearly upsampled to the sample rate) interpolated inside
     the kernels: forward + recompute adjoint through lp_forward_frames /
@@ -270,7 +271,9 @@ def frame_rate_bench(tv, B: int, T: int, M: int, L: int, steps: int, warmup: int
     # chunk length: a short sweep around the per-sample choice (the frame-rate kernels
     # hold more LDS per wave, which moves the occupancy steps)
     sweep = {}
-    for Lc in sorted({L} | {k * M for k in range(max(1, (L - 5 * M) // M), (L + 6 * M) // M + 1)}):
+    cands = [fixed_chunk] if fixed_chunk else sorted({L} | {k * M for k in range(max(1, (L - 5 * M) // M),
+                                                                                  (L + 6 * M) // M + 1)})
+    for Lc in cands:
         try:
             pc = tv.Plan(M, dev, Lc)
             for _ in range(2):
@@ -555,6 +558,8 @@ def main():
     ap.add_argument("--no-framewise", action="store_true", help="skip the frame-wise approximation section")
     ap.add_argument("--no-frame-rate", action="store_true", help="skip the frame-rate coefficient section")
     ap.add_argument("--no-sf", action="store_true", help="skip the source-filter synthesiser section")
+    ap.add_argument("--frame-rate-chunk", type=int, default=0,
+                    help="chunk length of the frame-rate section (default: a short sweep)")
     ap.add_argument("--serve-requests", type=int, default=100)
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-batch", type=int, default=8)
@@ -725,7 +730,7 @@ def main():
     frame_rate = None
     if not args.no_frame_rate:
         log("frame-rate coefficients (hop 240, interpolated in the kernels)")
-        frame_rate = frame_rate_bench(tv, B, T, M, L, args.steps, args.warmup, ms_step)
+        frame_rate = frame_rate_bench(tv, B, T, M, L, args.steps, args.warmup, ms_step, args.frame_rate_chunk)
         log(f"frame-rate: {frame_rate['ms_per_step']:.3f} ms/step")
         torch.cuda.empty_cache()
 
