@@ -613,6 +613,16 @@ def test_frame_rate_rejects_hop_too_short_for_lds(tv):
     A = torch.zeros((B, tv.coef_frames_count(T, 1), M), dtype=torch.float32, device=dev())
     with pytest.raises(Exception, match="hop"):
         plan.forward_frames(e, A, 1)
+    # argument checks of the C ABI: hop outside [1, 2^20], wrong frame count
+    from paper_2406_05128_amd import _lib
+    import ctypes
+    lib = _lib.load()
+    P = ctypes.c_void_p(e.data_ptr())
+    assert lib.lp_forward_frames(plan._h, B, T, 0, P, P, None, P, None, None, None) == -1
+    assert lib.lp_forward_frames(plan._h, B, T, (1 << 20) + 1, P, P, None, P, None, None, None) == -1
+    assert lib.lp_coef_frames_count(T, 0) == 0
+    with pytest.raises(ValueError):
+        plan.forward_frames(e, A[:, :-1].contiguous(), 1)
 
 
 # ---------------------------------------------------------------- source-filter synthesiser
