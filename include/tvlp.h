@@ -172,8 +172,9 @@ int lp_backward_ti(lp_plan *p, int64_t B, int64_t T,
  * lp_coef_frames_count(T, hop) = (T - 1) / hop + 2 (the last sample has a right
  * neighbour).  Sample t = q*hop + n (0 <= n < hop) uses
  *   a(t) = A[q] + n (A[q+1] - A[q]) / hop,
- * interpolated inside the kernels (float32), so no [B,T,M] array is read or
- * written.  lp_forward_frames is lp_forward with those rows (same saved buffer,
+ * interpolated inside the kernels (evaluated in float64, rounded once to
+ * float32, the precision of the per-sample rows), so no [B,T,M] array is read
+ * or written.  lp_forward_frames is lp_forward with those rows (same saved buffer,
  * zi, zf); lp_backward_frames is lp_backward with grad_A [B,F,M] = dL/dA in place
  * of grad_a: each sample hands (1 - n/hop) of dL/da(t) = -ghat(t) s(t-i) (Eq. 13)
  * to frame q and n/hop to frame q + 1, accumulated per chunk in float64 and
