@@ -32,12 +32,12 @@ FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published
 # plain 256 MiB device copy) for the training workload, per chunk length; valid only for the
 # kernel sources (hash below) they were measured with, otherwise reported as null.
 TRAFFIC = {
-    "sources_sha256": "f191d16111d648a8dc183d0b5bee67a3722ba7f3d756b8dfb1a9ad51dab3237d",
+    "sources_sha256": "2c39e852291d2a9f7176f0a7796e46164a5bf91fcc44fb3001bd771f253d2c73",
     "bytes_by_chunk": {
-        396: {"fwd_scan": 324805158, "fwd_emit": 298723397, "bwd_scan": 623040382, "bwd_emit": 582640980},
-        418: {"fwd_scan": 320048087, "fwd_emit": 298723848, "bwd_scan": 620960147, "bwd_emit": 582577981},
-        506: {"fwd_scan": 311561007, "fwd_emit": 297906089, "bwd_scan": 610829156, "bwd_emit": 581765767},
-        528: {"fwd_scan": 309554088, "fwd_emit": 296567500, "bwd_scan": 605927092, "bwd_emit": 580396459},
+        396: {"fwd_scan": 324854361, "fwd_emit": 298722271, "bwd_scan": 623029697, "bwd_emit": 582644343},
+        418: {"fwd_scan": 320002095, "fwd_emit": 298775024, "bwd_scan": 620981114, "bwd_emit": 582589719},
+        506: {"fwd_scan": 311623379, "fwd_emit": 297938001, "bwd_scan": 610760085, "bwd_emit": 581773981},
+        528: {"fwd_scan": 309371937, "fwd_emit": 296566298, "bwd_scan": 605874429, "bwd_emit": 580402071},
     },
 }
 

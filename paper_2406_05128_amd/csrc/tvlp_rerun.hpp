@@ -202,7 +202,7 @@ struct FrameCoefs {
     static constexpr int NONE = 0x7fffffff;
     typedef __attribute__((address_space(3))) float lfloat;
     double a0[NC], sl[NC];  // frame row, slope per sample
-    float cf[NC];           // phase offset
+    double ph[NC];          // phase of the next row (an exact integer)
     int ti[NC];  // staged index of the word's current frame row
     int nx[NC];  // issue count at which the word's frame changes (NONE: never)
     int p;       // rows issued so far (wave-uniform)
@@ -253,7 +253,7 @@ struct FrameCoefs {
             const int j = 64 * i + lane;
             a0[i] = 0.0;
             sl[i] = 0.0;
-            cf[i] = 0.f;
+            ph[i] = 0.0;
             ti[i] = 0;
             nx[i] = NONE;
             if (j < CPW * M) {
@@ -266,7 +266,7 @@ struct FrameCoefs {
                     ti[i] = (k * nfr + (int)(q - fi.q0)) * M + f;
                     a0[i] = (double)st[ti[i]];
                     sl[i] = ((double)st[ti[i] + M] - a0[i]) / hop;
-                    cf[i] = (float)n;  // phase n at issue 0
+                    ph[i] = (double)n;  // phase of row 0
                     // rows until the frame changes: down to phase 0, or up to phase hop - 1
                     const int first = DESC ? n + 1 : hop - n;
                     nx[i] = first < fi.len ? first : NONE;
@@ -287,8 +287,8 @@ struct FrameCoefs {
                 ti[i] += DESC ? -M : M;
                 a0[i] = (double)rows[ti[i]];
                 sl[i] = ((double)rows[ti[i] + M] - a0[i]) / hop;
-                // phase at issue p: ascending 0, descending hop - 1
-                cf[i] = DESC ? (float)(hop - 1 + p) : -(float)p;
+                // phase of row p: ascending 0, descending hop - 1
+                ph[i] = DESC ? (double)(hop - 1) : 0.0;
                 const int64_t len = info[(64 * i + lane) / M].len;
                 nx[i] = (int64_t)p + hop < len ? p + hop : NONE;
             }
@@ -301,11 +301,11 @@ struct FrameCoefs {
     __device__ __forceinline__ void produce(lfloat *dst) {
         if (p == ev) advance();
         const int lane = threadIdx.x & 63;
-        const float pf = DESC ? -(float)p : (float)p;
 #pragma unroll
         for (int i = 0; i < NC; ++i) {
             if (64 * (i + 1) <= CPW * M || 64 * i + lane < CPW * M)
-                dst[64 * i + lane] = (float)fma((double)(pf + cf[i]), sl[i], a0[i]);
+                dst[64 * i + lane] = (float)fma(ph[i], sl[i], a0[i]);
+            ph[i] += DESC ? -1.0 : 1.0;
         }
         ++p;
     }
