@@ -32,12 +32,12 @@ FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published
 # plain 256 MiB device copy) for the training workload, per chunk length; valid only for the
 # kernel sources (hash below) they were measured with, otherwise reported as null.
 TRAFFIC = {
-    "sources_sha256": "2c39e852291d2a9f7176f0a7796e46164a5bf91fcc44fb3001bd771f253d2c73",
+    "sources_sha256": "127812db53712b4a9119f38e3bd876996e445d8c3bb13608c4b29273648e7af4",
     "bytes_by_chunk": {
-        396: {"fwd_scan": 324854361, "fwd_emit": 298722271, "bwd_scan": 623029697, "bwd_emit": 582644343},
-        418: {"fwd_scan": 320002095, "fwd_emit": 298775024, "bwd_scan": 620981114, "bwd_emit": 582589719},
-        506: {"fwd_scan": 311623379, "fwd_emit": 297938001, "bwd_scan": 610760085, "bwd_emit": 581773981},
-        528: {"fwd_scan": 309371937, "fwd_emit": 296566298, "bwd_scan": 605874429, "bwd_emit": 580402071},
+        396: {"fwd_scan": 324850734, "fwd_emit": 298709595, "bwd_scan": 623030045, "bwd_emit": 582624792},
+        418: {"fwd_scan": 320327088, "fwd_emit": 298773793, "bwd_scan": 621017877, "bwd_emit": 582576859},
+        506: {"fwd_scan": 311666920, "fwd_emit": 297911086, "bwd_scan": 610780350, "bwd_emit": 581765378},
+        528: {"fwd_scan": 309611240, "fwd_emit": 296567596, "bwd_scan": 605887926, "bwd_emit": 580391213},
     },
 }
 

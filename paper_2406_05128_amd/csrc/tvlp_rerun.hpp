@@ -684,7 +684,8 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
             // The wave walks t over the stretches between consecutive boundaries of
             // any of its chunks (a frame's end or a chunk's end), accumulating
             // without branches; at a boundary only the lanes whose boundary it is
-            // flush their shares.  Lanes past their chunk's end add zeros.
+            // flush their shares.  A lane past its chunk's end keeps accumulating
+            // (reads stay inside its LDS rows) but never flushes again.
             // Within one frame part (at most hop samples) the products and their
             // sums are float32; the parts are combined in float64.
             constexpr int NONE = 0x7fffffff;
@@ -706,7 +707,7 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
                 float nd = (float)n;
                 const int t_start = t;
                 for (; t < tb; ++t) {
-                    const float gt = t < ln ? gsh[t] : 0.f;
+                    const float gt = gsh[t];
                     const float gn = gt * nd;
 #pragma unroll
                     for (int m = 0; m < TPL; ++m) {
