@@ -74,13 +74,18 @@ const char *lp_version(void);
 /* Thread-local description of the last non-OK return on this thread. */
 const char *lp_last_error(void);
 
-/* Orders M for which the chunked kernels are compiled; returns the count and
- * writes up to `cap` of them to `out` (which may be NULL). */
+/* Orders M for which the chunked kernels are compiled (1, 2, 3, 4, 6, 8, 10,
+ * 12, 16, 20, 22, 24, 32: every order the paper's configurations use, with
+ * a register and LDS mapping tuned per order); returns the count and writes
+ * up to `cap` of them to `out` (which may be NULL).  The sequential kernels
+ * (lp_forward_plain / lp_backward_plain) take any M in [1, 64]. */
 int lp_supported_orders(int *out, int cap);
 
 /* Create a plan for filter order M on `device`.  The plan selects the chunk
  * length L (a multiple of M, at least M) used by the chunked kernels.  `flags`
- * is a combination of the LP_FLAG_* values (others: LP_EINVAL). */
+ * is a combination of the LP_FLAG_* values (others: LP_EINVAL).  M outside
+ * [1, 64], or an order with no compiled chunked kernels (lp_supported_orders),
+ * gives LP_EINVAL with the reason in lp_last_error. */
 int lp_plan_create(lp_plan **out, int device, int M, int flags);
 int lp_plan_destroy(lp_plan *p);
 
