@@ -34,8 +34,12 @@ FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published
 TRAFFIC = {
     "sources_sha256": "127812db53712b4a9119f38e3bd876996e445d8c3bb13608c4b29273648e7af4",
     "bytes_by_chunk": {
+        374: {"fwd_scan": 327982899, "fwd_emit": 299558614, "bwd_scan": 627690776, "bwd_emit": 583198674},
         396: {"fwd_scan": 324850734, "fwd_emit": 298709595, "bwd_scan": 623030045, "bwd_emit": 582624792},
         418: {"fwd_scan": 320327088, "fwd_emit": 298773793, "bwd_scan": 621017877, "bwd_emit": 582576859},
+        440: {"fwd_scan": 319243873, "fwd_emit": 297689586, "bwd_scan": 614620203, "bwd_emit": 581690705},
+        462: {"fwd_scan": 315345204, "fwd_emit": 298295835, "bwd_scan": 614618057, "bwd_emit": 581878974},
+        484: {"fwd_scan": 315631650, "fwd_emit": 297848573, "bwd_scan": 611931242, "bwd_emit": 581712205},
         506: {"fwd_scan": 311666920, "fwd_emit": 297911086, "bwd_scan": 610780350, "bwd_emit": 581765378},
         528: {"fwd_scan": 309611240, "fwd_emit": 296567596, "bwd_scan": 605887926, "bwd_emit": 580391213},
     },
