@@ -117,7 +117,10 @@ __global__ __launch_bounds__(64 * SW_WAVES) void k_sf_source_rb(int64_t T, int h
     }
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    const int64_t t0 = t0b + (int64_t)TT * (threadIdx.x >> 6);     // this wave's tile
+    // the wave index is uniform in the wave; saying so keeps the tile walk's
+    // counters and addresses in scalar registers
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t t0 = t0b + (int64_t)TT * wv;     // this wave's tile
     if (t0 >= T) return;
     const int64_t ta = t0 - (K - 1) > 0 ? t0 - (K - 1) : 0;         // the tile's first input sample
     const int64_t tb = t0 + TT - 1 < T - 1 ? t0 + TT - 1 : T - 1;   // and last
@@ -366,7 +369,7 @@ __global__ __launch_bounds__(256) void k_sf_frame_grads(int64_t T, int hop, int 
     __syncthreads();
     // the frame's taps (frames at or beyond the signal's end get zeros)
     {
-        const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
         const int kw = 256 * wv;                   // the wave's first tap
         const int k0 = kw + RB * lane;             // this lane's first tap
         float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
