@@ -135,28 +135,38 @@ __global__ __launch_bounds__(64 * SW_WAVES) void k_sf_source_rb(int64_t T, int h
         float w0 = row[bi], w1 = row[bi + 1], w2 = row[bi + 2], w3 = row[bi + 3];
         const float *nt = ns + (tau - tlo);
         int cnt = (int)(end - tau + 1);
-        while (cnt >= 4) {
-            const float x1 = wave_shift<DPP_WAVE_SHR1>(w3, row[b0 - 1]);
-            const float x2 = wave_shift<DPP_WAVE_SHR1>(w2, row[b0 - 2]);
-            const float x3 = wave_shift<DPP_WAVE_SHR1>(w1, row[b0 - 3]);
-            const float x4 = wave_shift<DPP_WAVE_SHR1>(w0, row[b0 - 4]);
+        // Four steps: each window register is shifted in place right after its
+        // last use at the current offset (w3 after the first step, w2 after the
+        // second, ...), so after the four steps w0..w3 already hold the window
+        // four samples on.  A DPP move's result cannot share its source register,
+        // so the loop runs two such blocks per pass, letting the two register
+        // sets alternate without copies.
+        auto step4 = [&]() {
             float v = nt[0];
             a0 = __builtin_fmaf(w0, v, a0); a1 = __builtin_fmaf(w1, v, a1);
             a2 = __builtin_fmaf(w2, v, a2); a3 = __builtin_fmaf(w3, v, a3);
+            w3 = wave_shift<DPP_WAVE_SHR1>(w3, row[b0 - 1]);
             v = nt[1];
-            a0 = __builtin_fmaf(x1, v, a0); a1 = __builtin_fmaf(w0, v, a1);
+            a0 = __builtin_fmaf(w3, v, a0); a1 = __builtin_fmaf(w0, v, a1);
             a2 = __builtin_fmaf(w1, v, a2); a3 = __builtin_fmaf(w2, v, a3);
+            w2 = wave_shift<DPP_WAVE_SHR1>(w2, row[b0 - 2]);
             v = nt[2];
-            a0 = __builtin_fmaf(x2, v, a0); a1 = __builtin_fmaf(x1, v, a1);
+            a0 = __builtin_fmaf(w2, v, a0); a1 = __builtin_fmaf(w3, v, a1);
             a2 = __builtin_fmaf(w0, v, a2); a3 = __builtin_fmaf(w1, v, a3);
+            w1 = wave_shift<DPP_WAVE_SHR1>(w1, row[b0 - 3]);
             v = nt[3];
-            a0 = __builtin_fmaf(x3, v, a0); a1 = __builtin_fmaf(x2, v, a1);
-            a2 = __builtin_fmaf(x1, v, a2); a3 = __builtin_fmaf(w0, v, a3);
-            w0 = x4; w1 = x3; w2 = x2; w3 = x1;
+            a0 = __builtin_fmaf(w1, v, a0); a1 = __builtin_fmaf(w2, v, a1);
+            a2 = __builtin_fmaf(w3, v, a2); a3 = __builtin_fmaf(w0, v, a3);
+            w0 = wave_shift<DPP_WAVE_SHR1>(w0, row[b0 - 4]);
             b0 -= 4;
             nt += 4;
             cnt -= 4;
+        };
+        while (cnt >= 8) {
+            step4();
+            step4();
         }
+        if (cnt >= 4) step4();
         while (cnt > 0) {
             const float x1 = wave_shift<DPP_WAVE_SHR1>(w3, row[b0 - 1]);
             const float v = nt[0];
