@@ -386,24 +386,34 @@ __global__ __launch_bounds__(256) void k_sf_frame_grads(int64_t T, int hop, int 
         float w0 = gus[k0], w1 = gus[k0 + 1], w2 = gus[k0 + 2], w3 = gus[k0 + 3];
         const float *g63 = gus + kw + 256;  // lane 63's entering elements: g63[i + s - 1] at step i + s
         int i = 0;
-        for (; i + 4 <= hop; i += 4) {
-            const float y1 = wave_shift<DPP_WAVE_SHL1>(w0, g63[i]);
-            const float y2 = wave_shift<DPP_WAVE_SHL1>(w1, g63[i + 1]);
-            const float y3 = wave_shift<DPP_WAVE_SHL1>(w2, g63[i + 2]);
-            const float y4 = wave_shift<DPP_WAVE_SHL1>(w3, g63[i + 3]);
-            float v = ns[i];
+        // Four steps with each window register shifted in place after its last
+        // use (w0 after the first step, w1 after the second, ...), two blocks
+        // per pass so that the DPP results alternate between two register sets.
+        auto step4 = [&](int i4) {
+            float v = ns[i4];
             a0 = __builtin_fmaf(w0, v, a0); a1 = __builtin_fmaf(w1, v, a1);
             a2 = __builtin_fmaf(w2, v, a2); a3 = __builtin_fmaf(w3, v, a3);
-            v = ns[i + 1];
+            w0 = wave_shift<DPP_WAVE_SHL1>(w0, g63[i4]);
+            v = ns[i4 + 1];
             a0 = __builtin_fmaf(w1, v, a0); a1 = __builtin_fmaf(w2, v, a1);
-            a2 = __builtin_fmaf(w3, v, a2); a3 = __builtin_fmaf(y1, v, a3);
-            v = ns[i + 2];
+            a2 = __builtin_fmaf(w3, v, a2); a3 = __builtin_fmaf(w0, v, a3);
+            w1 = wave_shift<DPP_WAVE_SHL1>(w1, g63[i4 + 1]);
+            v = ns[i4 + 2];
             a0 = __builtin_fmaf(w2, v, a0); a1 = __builtin_fmaf(w3, v, a1);
-            a2 = __builtin_fmaf(y1, v, a2); a3 = __builtin_fmaf(y2, v, a3);
-            v = ns[i + 3];
-            a0 = __builtin_fmaf(w3, v, a0); a1 = __builtin_fmaf(y1, v, a1);
-            a2 = __builtin_fmaf(y2, v, a2); a3 = __builtin_fmaf(y3, v, a3);
-            w0 = y1; w1 = y2; w2 = y3; w3 = y4;
+            a2 = __builtin_fmaf(w0, v, a2); a3 = __builtin_fmaf(w1, v, a3);
+            w2 = wave_shift<DPP_WAVE_SHL1>(w2, g63[i4 + 2]);
+            v = ns[i4 + 3];
+            a0 = __builtin_fmaf(w3, v, a0); a1 = __builtin_fmaf(w0, v, a1);
+            a2 = __builtin_fmaf(w1, v, a2); a3 = __builtin_fmaf(w2, v, a3);
+            w3 = wave_shift<DPP_WAVE_SHL1>(w3, g63[i4 + 3]);
+        };
+        for (; i + 8 <= hop; i += 8) {
+            step4(i);
+            step4(i + 4);
+        }
+        if (i + 4 <= hop) {
+            step4(i);
+            i += 4;
         }
         for (; i < hop; ++i) {
             const float y1 = wave_shift<DPP_WAVE_SHL1>(w0, g63[i]);
