@@ -235,7 +235,53 @@ __global__ __launch_bounds__(64 * SW_WAVES) void k_fir_rb(int64_t T, int K, cons
     const int oj = o0 + RB * lane;    // this lane's t_j
     float w0 = xs[oj], w1 = xs[oj + 1], w2 = xs[oj + 2], w3 = xs[oj + 3];  // window at k = 0
     float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-    for (int k = 0; k < K; ++k) {
+    // Four taps per block with each window register shifted in place after its
+    // last use, two blocks per pass (the DPP results alternate between two
+    // register sets); the remaining taps take the one-tap step below.
+    auto block4 = [&](int k) {
+        float h = hs[k];
+        a0 = __builtin_fmaf(h, w0, a0); a1 = __builtin_fmaf(h, w1, a1);
+        a2 = __builtin_fmaf(h, w2, a2); a3 = __builtin_fmaf(h, w3, a3);
+        if constexpr (CORR) {
+            w0 = wave_shift<DPP_WAVE_SHL1>(w0, xs[o0 + 256 + k]);
+            h = hs[k + 1];
+            a0 = __builtin_fmaf(h, w1, a0); a1 = __builtin_fmaf(h, w2, a1);
+            a2 = __builtin_fmaf(h, w3, a2); a3 = __builtin_fmaf(h, w0, a3);
+            w1 = wave_shift<DPP_WAVE_SHL1>(w1, xs[o0 + 256 + k + 1]);
+            h = hs[k + 2];
+            a0 = __builtin_fmaf(h, w2, a0); a1 = __builtin_fmaf(h, w3, a1);
+            a2 = __builtin_fmaf(h, w0, a2); a3 = __builtin_fmaf(h, w1, a3);
+            w2 = wave_shift<DPP_WAVE_SHL1>(w2, xs[o0 + 256 + k + 2]);
+            h = hs[k + 3];
+            a0 = __builtin_fmaf(h, w3, a0); a1 = __builtin_fmaf(h, w0, a1);
+            a2 = __builtin_fmaf(h, w1, a2); a3 = __builtin_fmaf(h, w2, a3);
+            w3 = wave_shift<DPP_WAVE_SHL1>(w3, xs[o0 + 256 + k + 3]);
+        } else {
+            w3 = wave_shift<DPP_WAVE_SHR1>(w3, xs[o0 - 1 - k]);
+            h = hs[k + 1];
+            a0 = __builtin_fmaf(h, w3, a0); a1 = __builtin_fmaf(h, w0, a1);
+            a2 = __builtin_fmaf(h, w1, a2); a3 = __builtin_fmaf(h, w2, a3);
+            w2 = wave_shift<DPP_WAVE_SHR1>(w2, xs[o0 - 2 - k]);
+            h = hs[k + 2];
+            a0 = __builtin_fmaf(h, w2, a0); a1 = __builtin_fmaf(h, w3, a1);
+            a2 = __builtin_fmaf(h, w0, a2); a3 = __builtin_fmaf(h, w1, a3);
+            w1 = wave_shift<DPP_WAVE_SHR1>(w1, xs[o0 - 3 - k]);
+            h = hs[k + 3];
+            a0 = __builtin_fmaf(h, w1, a0); a1 = __builtin_fmaf(h, w2, a1);
+            a2 = __builtin_fmaf(h, w3, a2); a3 = __builtin_fmaf(h, w0, a3);
+            w0 = wave_shift<DPP_WAVE_SHR1>(w0, xs[o0 - 4 - k]);
+        }
+    };
+    int k = 0;
+    for (; k + 8 <= K; k += 8) {
+        block4(k);
+        block4(k + 4);
+    }
+    if (k + 4 <= K) {
+        block4(k);
+        k += 4;
+    }
+    for (; k < K; ++k) {
         const float hk = hs[k];
         a0 = __builtin_fmaf(hk, w0, a0); a1 = __builtin_fmaf(hk, w1, a1);
         a2 = __builtin_fmaf(hk, w2, a2); a3 = __builtin_fmaf(hk, w3, a3);
