@@ -341,25 +341,3 @@ def framewise_backward(g: np.ndarray, af: np.ndarray, sf: np.ndarray, hop: int):
         if hi > lo:
             ge[:, lo:hi] += gef[:, f, lo - t0:hi - t0]
     return ge, gaf.reshape(B, F, M)
-
-
-def lp_forward_varlen(e: np.ndarray, a: np.ndarray, offsets: np.ndarray):
-    """Packed variable-length batch: sequence b spans [offsets[b], offsets[b+1])."""
-    s = np.empty(e.shape, np.float64)
-    for b in range(len(offsets) - 1):
-        lo, hi = int(offsets[b]), int(offsets[b + 1])
-        if hi > lo:
-            s[lo:hi] = lp_forward(e[None, lo:hi], a[None, lo:hi])[0][0]
-    return s
-
-
-def lp_backward_varlen(g: np.ndarray, a: np.ndarray, s: np.ndarray, offsets: np.ndarray):
-    ge = np.empty(g.shape, np.float64)
-    ga = np.empty(a.shape, np.float64)
-    for b in range(len(offsets) - 1):
-        lo, hi = int(offsets[b]), int(offsets[b + 1])
-        if hi > lo:
-            r = lp_backward(g[None, lo:hi], a[None, lo:hi], s[None, lo:hi])
-            ge[lo:hi] = r[0][0]
-            ga[lo:hi] = r[1][0]
-    return ge, ga
