@@ -29,7 +29,9 @@
  * recent failure.  Invalid arguments (B < 1, T < 1, M outside [1, 64], NULL
  * required pointers, an unsupported order for the chunked kernels) give
  * LP_EINVAL and launch nothing; device failures give LP_EDEVICE.  Non-finite
- * inputs are not errors: they propagate through the recursion.
+ * inputs are not errors: they propagate through the recursion, and
+ * lp_forward / lp_backward report per sequence whether any output is
+ * non-finite (their `nonfinite` argument).
  */
 #ifndef TVLP_H
 #define TVLP_H
@@ -62,10 +64,20 @@ enum {
  *   filters (time-varying pole radii near 1, where single transitions already
  *   have entries in the thousands); the chained carry keeps the rounding error
  *   at the level of one transition, at the cost of a serial dependency between
- *   consecutive groups of a sequence. */
+ *   consecutive groups of a sequence.
+ * LP_FLAG_HIGH_RADIUS: for inputs whose frozen poles come close to the unit
+ *   circle (radius above about 0.99, or tracks that are briefly unstable
+ *   within frames).  Implies LP_FLAG_CHAINED_CARRY, makes the plan's default
+ *   chunk length the longest its order supports (at most 2048), and restricts
+ *   lp_plan_autotune to chunk lengths of at least 1536 (or that longest one):
+ *   over short chunks single transitions of such filters have entries in the
+ *   thousands, and chaining many of them loses the result; over long chunks the
+ *   transient dies out inside the chunk.  lp_plan_set_chunk still accepts any
+ *   length. */
 enum {
     LP_FLAG_NONE = 0,
-    LP_FLAG_CHAINED_CARRY = 1
+    LP_FLAG_CHAINED_CARRY = 1,
+    LP_FLAG_HIGH_RADIUS = 2
 };
 
 /* Library version string, e.g. "tvlp 0.1 gfx950". */
@@ -87,6 +99,8 @@ int lp_supported_orders(int *out, int cap);
  * [1, 64], or an order with no compiled chunked kernels (lp_supported_orders),
  * gives LP_EINVAL with the reason in lp_last_error. */
 int lp_plan_create(lp_plan **out, int device, int M, int flags);
+/* Frees the plan and its workspace (after a device synchronisation).  LP_EINVAL,
+ * and nothing freed, while a captured graph of the plan exists. */
 int lp_plan_destroy(lp_plan *p);
 
 /* Override / query the chunk length.  L must be a positive multiple of M and
@@ -136,21 +150,28 @@ size_t lp_saved_bytes_varlen(const lp_plan *p, int64_t B, int64_t N);
  * zf: optional [B,M] final state out.
  * saved: optional, lp_saved_bytes(p,B,T) bytes, filled for lp_backward; when
  *        NULL the plan's workspace holds the intermediates.
+ * nonfinite: optional [B] device array of uint32 flags: the call sets
+ *        nonfinite[b] = 1 when some s(t) of sequence b is Inf or NaN (a
+ *        non-finite input, or a recursion that overflows), else 0.  Non-finite
+ *        values are not an error: they propagate, and other sequences are not
+ *        affected.
  */
 int lp_forward(lp_plan *p, int64_t B, int64_t T,
                const float *e, const float *a, const double *zi,
-               float *s, double *zf, void *saved, void *stream);
+               float *s, double *zf, void *saved, uint32_t *nonfinite, void *stream);
 
 /*
  * Chunked adjoint (Eqs. 12-13).  g [B,T] = dL/ds; a, e, zi as given to the
  * lp_forward call that filled `saved` (required).  s: the forward output, or
  * NULL to recompute s(t) chunk by chunk from `saved`.  Outputs (each may be
- * NULL if not wanted): grad_e [B,T], grad_a [B,T,M], grad_zi [B,M].
+ * NULL if not wanted): grad_e [B,T], grad_a [B,T,M], grad_zi [B,M], and
+ * nonfinite [B] (uint32): 1 when some dL/de(t) or dL/da_i(t) of sequence b is
+ * Inf or NaN, else 0 (as for lp_forward, not an error).
  */
 int lp_backward(lp_plan *p, int64_t B, int64_t T,
                 const float *g, const float *a, const float *e, const double *zi,
                 const float *s, const void *saved,
-                float *grad_e, float *grad_a, double *grad_zi, void *stream);
+                float *grad_e, float *grad_a, double *grad_zi, uint32_t *nonfinite, void *stream);
 
 /*
  * Time-invariant coefficients (the all-pole filter of Sec. 2.2, Eqs. 2-4, with
@@ -303,6 +324,13 @@ int lp_backward_pair(lp_plan *p, int64_t B, int64_t T, const float *g, const flo
  * pointers: refill the input buffers between replays.  store_s != 0 makes the
  * adjoint read s2 instead of recomputing it.  A plan must not be used by
  * other calls while one of its graphs is running.
+ * A graph keeps the address of its plan's workspace.  Until every graph of a
+ * plan is destroyed the plan refuses, with LP_EINVAL and nothing launched or
+ * freed, whatever would move or free that workspace or change the layout the
+ * graph was captured with: a call that needs a larger workspace, a change of
+ * chunk length (lp_plan_set_chunk, lp_plan_autotune) and lp_plan_destroy.
+ * Calls that fit the reserved workspace remain allowed between replays.
+ * lp_graph_destroy releases the graph's hold on the plan.
  */
 int lp_graph_capture_pair_step(lp_plan *p, int64_t B, int64_t T, const float *e2, const float *a2,
                                float *y, float *s2, void *saved, const float *g,
@@ -330,7 +358,11 @@ int lp_graph_destroy(lp_graph *g);
  * Returns: submit LP_EBUDGET if T exceeds the whole arena; poll / wait
  * LP_PENDING while the job runs, LP_OK once s_host_out holds the result (the
  * ticket is then retired: a second poll gives LP_ENOTFOUND), LP_EDEVICE if it
- * failed; latency_ms_out (may be NULL) receives submit-to-completion time.
+ * failed; latency_ms_out (may be NULL) receives submit-to-completion time
+ * (host clock: queueing, upload, compute and download); lp_serve_wait's
+ * device_ms_out (may be NULL) receives the job's time on the device, from the
+ * launch of its first slice to the end of its last one (shared with the other
+ * jobs in flight; no queueing, no copies).
  * lp_serve_destroy finishes every admitted and queued job, then frees all.
  * All functions are thread-safe.
  */
@@ -340,7 +372,8 @@ int lp_serve_create(lp_server **out, int device, int M, size_t hbm_budget_bytes,
 int lp_serve_submit(lp_server *srv, int64_t T, const float *e_host, const float *a_host,
                     float *s_host_out, uint64_t *ticket);
 int lp_serve_poll(lp_server *srv, uint64_t ticket, double *latency_ms_out);
-int lp_serve_wait(lp_server *srv, uint64_t ticket, double timeout_s, double *latency_ms_out);
+int lp_serve_wait(lp_server *srv, uint64_t ticket, double timeout_s, double *latency_ms_out,
+                  double *device_ms_out);
 int lp_serve_stats(lp_server *srv, int64_t *iterations, int64_t *samples, int64_t *jobs_done,
                    int64_t *queued, int64_t *active);
 int lp_serve_destroy(lp_server *srv);

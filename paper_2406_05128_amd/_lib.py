@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libtvlp.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "tvlp.h")
 
 LP_OK, LP_PENDING, LP_EINVAL, LP_ENOMEM, LP_EDEVICE, LP_ENOTFOUND, LP_EBUDGET = 0, 1, -1, -2, -3, -4, -5
-LP_FLAG_NONE, LP_FLAG_CHAINED_CARRY = 0, 1
+LP_FLAG_NONE, LP_FLAG_CHAINED_CARRY, LP_FLAG_HIGH_RADIUS = 0, 1, 2
 _CODES = {LP_EINVAL: "LP_EINVAL", LP_ENOMEM: "LP_ENOMEM", LP_EDEVICE: "LP_EDEVICE",
           LP_ENOTFOUND: "LP_ENOTFOUND", LP_EBUDGET: "LP_EBUDGET"}
 
@@ -48,8 +48,8 @@ SIGNATURES = {
     "lp_plan_status": (_INT, [_P]),
     "lp_saved_bytes": (_SZ, [_P, _I64, _I64]),
     "lp_saved_bytes_varlen": (_SZ, [_P, _I64, _I64]),
-    "lp_forward": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P]),
-    "lp_backward": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "lp_forward": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "lp_backward": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "lp_forward_ti": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P]),
     "lp_backward_ti": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "lp_frames_count": (_I64, [_I64, _I64]),
@@ -70,7 +70,7 @@ SIGNATURES = {
     "lp_serve_create": (_INT, [ctypes.POINTER(_P), ctypes.c_int, ctypes.c_int, ctypes.c_size_t, ctypes.c_int, _I64, ctypes.c_int]),
     "lp_serve_submit": (_INT, [_P, _I64, _P, _P, _P, _P]),
     "lp_serve_poll": (_INT, [_P, ctypes.c_uint64, _P]),
-    "lp_serve_wait": (_INT, [_P, ctypes.c_uint64, ctypes.c_double, _P]),
+    "lp_serve_wait": (_INT, [_P, ctypes.c_uint64, ctypes.c_double, _P, _P]),
     "lp_serve_stats": (_INT, [_P, _P, _P, _P, _P, _P]),
     "lp_serve_destroy": (_INT, [_P]),
     "lp_saved_bytes_pair": (_SZ, [_P, _I64, _I64]),

@@ -1,10 +1,7 @@
 // Host side of the C ABI declared in include/tvlp.h: plans, argument checks,
 // workspace management and kernel dispatch over the compiled filter orders.
 #include "tvlp.h"
-#include "tvlp_device.hpp"
-#include "tvlp_systolic.hpp"
-#include "tvlp_scan.hpp"
-#include "tvlp_carry.hpp"
+#include "tvlp_ops.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -17,23 +14,7 @@
 #include <vector>
 
 using namespace tvlp;
-
-struct TimingRecord {
-    const char *name;
-    hipEvent_t start, stop;
-};
-
-struct lp_plan {
-    int device;
-    int M;
-    int L;
-    int flags;
-    void *ws;
-    size_t ws_bytes;
-    bool timing;
-    std::vector<TimingRecord> pending;
-    std::map<std::string, std::pair<double, int64_t>> totals;  // name -> (ms, launches)
-};
+using namespace tvlp_host;
 
 namespace {
 
@@ -63,29 +44,6 @@ int check_hip(hipError_t e, const char *what) {
     return fail(LP_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-// Brackets kernel launches with hipEvents on their stream when the plan's
-// timing switch is on (events are read back by lp_plan_timings).
-struct Timer {
-    lp_plan *p;
-    hipStream_t st;
-    TimingRecord cur{};
-    void begin(const char *name) {
-        if (!p || !p->timing) return;
-        cur.name = name;
-        if (hipEventCreate(&cur.start) != hipSuccess || hipEventCreate(&cur.stop) != hipSuccess) {
-            cur.name = nullptr;
-            return;
-        }
-        (void)hipEventRecord(cur.start, st);
-    }
-    void end() {
-        if (!p || !p->timing || !cur.name) return;
-        (void)hipEventRecord(cur.stop, st);
-        p->pending.push_back(cur);
-        cur.name = nullptr;
-    }
-};
-
 // Restores the caller's current device on scope exit.
 struct DeviceGuard {
     int prev = -1;
@@ -108,14 +66,14 @@ bool order_supported(int M) {
     return false;
 }
 
-constexpr int kMaxChunk = 2048;
+// shortest chunk length the autotuner considers for LP_FLAG_HIGH_RADIUS plans
+constexpr int kAccurateChunk = 1536;
 
 int default_chunk(int M) {
     int mult = (256 + M - 1) / M;
     return std::max(1, mult) * M;
 }
 
-int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Lanes per chunk and columns per lane of the basis pass for order M.
 template <int M>
@@ -170,6 +128,11 @@ WsLayout ws_layout(int M, int64_t nch, int64_t B, int64_t ngf, int64_t ngb, int6
 
 int ensure_ws(lp_plan *p, size_t need, hipStream_t stream) {
     if (p->ws_bytes >= need) return LP_OK;
+    if (p->live_graphs > 0)
+        return fail(LP_EINVAL,
+                    "workspace of %zu bytes needed but %d captured graph(s) hold the current one (%zu bytes); "
+                    "destroy them first or reserve a larger workspace before capturing",
+                    need, p->live_graphs, p->ws_bytes);
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (stream && hipStreamIsCapturing(stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
         return fail(LP_ENOMEM, "workspace of %zu bytes needed during graph capture; call lp_plan_reserve first", need);
@@ -318,202 +281,6 @@ __global__ __launch_bounds__(256) void k_pair_sum(float *__restrict__ y, const f
     }
 }
 
-// Basis-pass mapping of the forward scan for order M: LPC lanes per chunk,
-// CPL float64 columns per lane (LPC*CPL >= M+1), R coefficient rows per LDS
-// slab (R divides M).
-template <int M> struct FwdShape;
-#define TVLP_FWD_SHAPE(m, lpc, cpl, r)          \
-    template <> struct FwdShape<m> {           \
-        static constexpr int LPC = lpc, CPL = cpl, R = r; \
-        static constexpr int CPW = 64 / lpc;   \
-    };
-TVLP_FWD_SHAPE(1, 1, 2, 1)
-TVLP_FWD_SHAPE(2, 1, 3, 2)
-TVLP_FWD_SHAPE(3, 2, 2, 3)
-TVLP_FWD_SHAPE(4, 2, 3, 4)
-TVLP_FWD_SHAPE(6, 4, 2, 6)
-TVLP_FWD_SHAPE(8, 3, 3, 8)
-TVLP_FWD_SHAPE(10, 4, 3, 10)
-TVLP_FWD_SHAPE(12, 5, 3, 4)
-TVLP_FWD_SHAPE(16, 6, 3, 2)
-TVLP_FWD_SHAPE(20, 7, 3, 2)
-TVLP_FWD_SHAPE(22, 8, 3, 2)
-TVLP_FWD_SHAPE(24, 13, 2, 3)
-TVLP_FWD_SHAPE(32, 17, 2, 2)
-#undef TVLP_FWD_SHAPE
-
-// Lanes per chunk of the systolic reruns and rows per LDS slab.
-template <int M>
-struct RerunShape {
-    static constexpr int G = M >= 8 ? 8 : 4;
-    static constexpr int R = 16;
-    static constexpr int CPW = 64 / G;
-};
-
-template <int M>
-struct Ops {
-    using FS = FwdShape<M>;
-    // dynamic LDS of the adjoint emit kernel: s and ghat of each of its chunks
-    static size_t emit_lds_bytes(int L) { return (size_t)RerunShape<M>::CPW * (M + 2 * (size_t)L) * sizeof(float); }
-    // longest chunk whose emit kernel fits the 160 KiB LDS of a CU (with its row ring)
-    static int max_chunk() {
-        constexpr size_t lds = 160 * 1024;
-        constexpr size_t ring = RowRing<M, RerunShape<M>::CPW, false>::FLOATS * sizeof(float);
-        const size_t per_l = 2 * RerunShape<M>::CPW * sizeof(float);
-        const size_t fixed = ring + (size_t)RerunShape<M>::CPW * M * sizeof(float);
-        int L = (int)((lds - fixed) / per_l);
-        L = std::min(L, kMaxChunk);
-        return L / M * M;
-    }
-    using RS = RerunShape<M>;
-
-    // Everything one call needs, resolved by the host driver.
-    struct Bufs {
-        Seqs S;
-        Groups gf, gb;
-        int64_t nch;
-        double *xs, *phiT, *yend, *zbuf, *qbuf;
-        double *aggf, *inclf, *aggb, *inclb;  // group maps and group carries
-        int *status;
-        const float *zero;  // 64 floats of 0 in device memory
-        float *sbuf;        // s recomputed by the adjoint (one float per sample slot)
-        double *fpart;      // frame-rate coefficients: chunk shares of dL/dA [nch][nf][M]
-        int chain;  // chained carry: no matrix products between chunk transitions
-    };
-
-    // Frame-rate coefficients with chunk length L and nf staged frame rows per
-    // chunk: whether every kernel's LDS (ring, staging, emit buffers) fits a CU.
-    static bool frames_lds_ok(int L, int nf) {
-        constexpr size_t lds = 160 * 1024;
-        using FSH = FwdScanShape<M, FS::LPC, FS::CPL, FS::R, true>;
-        const size_t ff = frame_lds_bytes(FS::CPW, M, nf), fr = frame_lds_bytes(RS::CPW, M, nf);
-        const size_t front = std::max<size_t>(BwdScanShape<M, RS::G, RS::R, true>::LDS_BYTES,
-                                              RerunLds<M, RS::G, true>::BYTES);
-        const size_t emit = FrameRing<M, RS::CPW, true, 12>::FLOATS * sizeof(float) +
-                            emit_frame_lds_offset(RS::CPW, M, L) + fr;
-        return FSH::LDS_BYTES + ff <= lds && front + fr <= lds && emit <= lds;
-    }
-
-    static void forward(const Bufs &w, const float *e, const float *a, const double *zi, float *s, double *zf,
-                        hipStream_t st, Timer &tm) {
-        forward_t<false>(w, e, a, zi, s, zf, st, tm);
-    }
-
-    // FR: a holds frame-rate rows [B][F][M] (w.S.hop, nf, F set), interpolated in the kernels.
-    template <bool FR>
-    static void forward_t(const Bufs &w, const float *e, const float *a, const double *zi, float *s, double *zf,
-                          hipStream_t st, Timer &tm) {
-        if (w.nch <= 0) return;
-        // time-invariant coefficients: one transition per sequence (a matrix power)
-        // and the chunks' zero-state offsets; the carry then runs chained
-        const bool ti = !FR && w.S.ti;
-        const int chain = ti ? 1 : w.chain;
-        const size_t dynf = FR ? frame_lds_bytes(FS::CPW, M, w.S.nf) : 0;
-        const size_t dynr = FR ? frame_lds_bytes(RS::CPW, M, w.S.nf) : 0;
-        tm.begin("fwd_scan");
-        if (ti) {
-            if (w.S.T > w.S.L) {  // some chunk carries a transition (uniform batches)
-                hipLaunchKernelGGL((k_ti_zs<M, RS::G>), dim3((unsigned)ceil_div(w.nch, RS::CPW)), dim3(64), 0, st,
-                                   w.S, e, a, w.zbuf, w.zero, w.nch);
-                hipLaunchKernelGGL((k_ti_phi<M>), dim3((unsigned)w.S.n), dim3(256), 0, st, w.S, a, w.phiT);
-            }
-        } else {
-            hipLaunchKernelGGL((k_fwd_local<M, FS::LPC, FS::CPL, FS::R, FR>), dim3((unsigned)w.gf.ngroups), dim3(64),
-                               dynf, st, w.S, w.gf, e, a, w.phiT, w.zbuf, w.aggf, w.chain);
-        }
-        tm.end();
-        tm.begin("fwd_carry");
-        const dim3 ct(CarryShape<M>::THREADS);
-        hipLaunchKernelGGL((k_fwd_chain<M>), dim3((unsigned)w.S.n), ct, 0, st, w.S, w.gf, zi, w.phiT, w.zbuf, w.aggf,
-                           w.inclf, w.xs, chain);
-        if (!chain)
-            hipLaunchKernelGGL((k_fwd_expand<M, FS::CPW>), dim3((unsigned)w.gf.ngroups), ct, 0, st, w.S, w.gf, w.phiT,
-                               w.zbuf, w.inclf, w.xs);
-        tm.end();
-        tm.begin("fwd_emit");
-        hipLaunchKernelGGL((k_fwd_rerun2<M, RS::G, FR>), dim3((unsigned)ceil_div(w.nch, RS::CPW)), dim3(64), dynr,
-                           st, w.S, e, a, w.xs, s, zf, w.zero, w.nch);
-        tm.end();
-    }
-
-    static void backward(const Bufs &w, const float *g, const float *a, const float *e, const float *s_in,
-                         float *ge, float *ga, double *gzi, hipStream_t st, Timer &tm) {
-        backward_t<false>(w, g, a, e, s_in, ge, ga, gzi, st, tm);
-    }
-
-    // FR: a holds frame-rate rows and ga receives dL/dA [B][F][M] (chunk shares in
-    // w.fpart, then summed per frame).
-    template <bool FR>
-    static void backward_t(const Bufs &w, const float *g, const float *a, const float *e, const float *s_in,
-                           float *ge, float *ga, double *gzi, hipStream_t st, Timer &tm) {
-        if (w.nch <= 0) return;
-        // without a stored s the emit kernel reads s recomputed alongside the local scan
-        const bool emit = ge || ga;
-        const float *s_use = s_in ? s_in : w.sbuf;
-        const size_t dynr = FR ? frame_lds_bytes(RS::CPW, M, w.S.nf) : 0;
-        tm.begin("bwd_scan");
-        if (emit && !s_in) {
-            const int64_t nrun = ceil_div(w.nch, RS::CPW);
-            hipLaunchKernelGGL((k_bwd_front<M, RS::G, RS::R, FR>), dim3((unsigned)(w.gb.ngroups + nrun)), dim3(64),
-                               dynr, st, w.S, w.gb, g, a, w.phiT, w.qbuf, w.aggb, w.zero, w.chain, e, w.xs, w.sbuf,
-                               w.nch);
-        } else {
-            hipLaunchKernelGGL((k_bwd_local<M, RS::G, RS::R, FR>), dim3((unsigned)w.gb.ngroups), dim3(64), dynr, st,
-                               w.S, w.gb, g, a, w.phiT, w.qbuf, w.aggb, w.zero, w.chain);
-        }
-        tm.end();
-        tm.begin("bwd_carry");
-        const dim3 ct(CarryShape<M>::THREADS);
-        hipLaunchKernelGGL((k_bwd_chain<M>), dim3((unsigned)w.S.n), ct, 0, st, w.S, w.gb, w.phiT, w.qbuf, w.aggb,
-                           w.inclb, w.yend, gzi, w.chain);
-        if (!w.chain)
-            hipLaunchKernelGGL((k_bwd_expand<M, RS::CPW>), dim3((unsigned)w.gb.ngroups), ct, 0, st, w.S, w.gb, w.phiT,
-                               w.qbuf, w.inclb, w.yend, gzi);
-        tm.end();
-        if (emit && FR) {
-            const unsigned grid = (unsigned)ceil_div(w.nch, RS::CPW);
-            const size_t dyn = emit_frame_lds_offset(RS::CPW, M, w.S.L) + dynr;
-            tm.begin("bwd_emit");
-            hipLaunchKernelGGL((k_adj_emit2<M, RS::G, true>), dim3(grid), dim3(64), dyn, st, w.S, g, a, s_use, w.xs,
-                               w.yend, ge, nullptr, ga ? w.fpart : nullptr, w.zero, w.nch);
-            if (ga) {
-                const int64_t nout = w.S.n * w.S.F * M;
-                hipLaunchKernelGGL((k_frames_reduce<M>), dim3((unsigned)ceil_div(nout, 256)), dim3(256), 0, st, w.S,
-                                   w.fpart, ga);
-            }
-            tm.end();
-        } else if (emit) {
-            const unsigned grid = (unsigned)ceil_div(w.nch, RS::CPW);
-            const size_t dyn = emit_lds_bytes(w.S.L);
-            tm.begin("bwd_emit");
-            // time-invariant coefficients: per-chunk shares of dL/da (in the q buffer, free
-            // once the carry has run) instead of per-sample rows, then a sum per sequence
-            const bool ti = w.S.ti && ga;
-            hipLaunchKernelGGL((k_adj_emit2<M, RS::G>), dim3(grid), dim3(64), dyn, st, w.S, g, a, s_use,
-                               w.xs, w.yend, ge, w.S.ti ? nullptr : ga, ti ? w.qbuf : nullptr, w.zero, w.nch);
-            if (ti)
-                hipLaunchKernelGGL((k_ti_reduce<M>), dim3((unsigned)w.S.n), dim3(64), 0, st, w.S, w.qbuf, ga);
-            tm.end();
-        }
-    }
-
-    static void plain_fwd(int64_t B, int64_t T, const float *e, const float *a, const double *zi, float *s,
-                          double *zf, hipStream_t st) {
-        hipLaunchKernelGGL((k_plain_fwd<M>), dim3((unsigned)ceil_div(B, 64)), dim3(64), 0, st, B, T, e, a, zi, s,
-                           zf);
-    }
-
-    static void plain_bwd(int64_t B, int64_t T, const float *g, const float *a, const double *zi, const float *s,
-                          float *ge, float *ga, double *gzi, hipStream_t st) {
-        if (ga)
-            hipLaunchKernelGGL((k_plain_bwd<M, true>), dim3((unsigned)ceil_div(B, 64)), dim3(64), 0, st, B, T, g,
-                               a, zi, s, ge, ga, gzi);
-        else
-            hipLaunchKernelGGL((k_plain_bwd<M, false>), dim3((unsigned)ceil_div(B, 64)), dim3(64), 0, st, B, T, g,
-                               a, zi, s, ge, ga, gzi);
-    }
-};
-
 // Forward / adjoint scan group sizes (chunks per wave) of order M.
 int scan_cpw(int M, bool fwd) {
     int r = 0;
@@ -628,6 +395,7 @@ int prepare(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, const
     w.sbuf = (float *)(ws + lay.sbuf);
     w.fpart = (double *)(ws + lay.fpart);
     w.chain = (p->flags & LP_FLAG_CHAINED_CARRY) ? 1 : 0;
+    w.nonfinite = nullptr;
     return LP_OK;
 }
 
@@ -635,7 +403,7 @@ int prepare(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, const
 int forward_impl(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, const float *e, const float *a,
                  const double *zi, float *s, double *zf, void *saved, void *stream,
                  const int64_t *starts = nullptr, const int64_t *lens = nullptr, int64_t bound = 0,
-                 bool ti = false) {
+                 bool ti = false, uint32_t *nonfinite = nullptr) {
     if (int r = check_plan(p)) return r;
     if (B < 1) return fail(LP_EINVAL, "B must be >= 1 (got %lld)", (long long)B);
     if (T_or_N < 1) return fail(LP_EINVAL, "T (or N) must be >= 1 (got %lld)", (long long)T_or_N);
@@ -650,6 +418,7 @@ int forward_impl(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, 
         typename O::Bufs w;
         rc = prepare<O>(p, B, offsets, T_or_N, saved, st, w, starts, lens, bound);
         w.S.ti = ti ? 1 : 0;
+        w.nonfinite = nonfinite;
         if (rc == LP_OK) O::forward(w, e, a, zi, s, zf, st, tm);
     });
     if (rc != LP_OK) return rc;
@@ -658,13 +427,13 @@ int forward_impl(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, 
 
 int backward_impl(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, const float *g, const float *a,
                   const float *e, const double *zi, const float *s, const void *saved, float *ge, float *ga,
-                  double *gzi, void *stream, int64_t gshare = 0, bool ti = false) {
+                  double *gzi, void *stream, int64_t gshare = 0, bool ti = false, uint32_t *nonfinite = nullptr) {
     if (int r = check_plan(p)) return r;
     if (B < 1) return fail(LP_EINVAL, "B must be >= 1 (got %lld)", (long long)B);
     if (T_or_N < 1) return fail(LP_EINVAL, "T (or N) must be >= 1 (got %lld)", (long long)T_or_N);
     if (!g || !a || !saved) return fail(LP_EINVAL, "g, a and saved are required");
     if ((ga || ge) && !s && !e) return fail(LP_EINVAL, "the adjoint needs s or e (to recompute s)");
-    if (!ge && !ga && !gzi) return LP_OK;
+    if (!ge && !ga && !gzi && !nonfinite) return LP_OK;
     (void)zi;
     DeviceGuard dg(p->device);
     if (!dg.ok) return fail(LP_EDEVICE, "cannot select device %d", p->device);
@@ -677,6 +446,7 @@ int backward_impl(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N,
         rc = prepare<O>(p, B, offsets, T_or_N, saved, st, w);
         w.S.gshare = gshare;
         w.S.ti = ti ? 1 : 0;
+        w.nonfinite = nonfinite;
         if (rc == LP_OK) O::backward(w, g, a, e, s, ge, ga, gzi, st, tm);
     });
     if (rc != LP_OK) return rc;
@@ -703,7 +473,8 @@ int lp_plan_create(lp_plan **out, int device, int M, int flags) {
     *out = nullptr;
     if (M < 1 || M > 64) return fail(LP_EINVAL, "order M must be in [1, 64] (got %d)", M);
     if (!order_supported(M)) return fail(LP_EINVAL, "order M = %d has no compiled chunked kernels", M);
-    if (flags & ~LP_FLAG_CHAINED_CARRY) return fail(LP_EINVAL, "unknown plan flags 0x%x", flags);
+    if (flags & ~(LP_FLAG_CHAINED_CARRY | LP_FLAG_HIGH_RADIUS)) return fail(LP_EINVAL, "unknown plan flags 0x%x", flags);
+    if (flags & LP_FLAG_HIGH_RADIUS) flags |= LP_FLAG_CHAINED_CARRY;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
         return fail(LP_EINVAL, "device %d not available", device);
@@ -712,6 +483,7 @@ int lp_plan_create(lp_plan **out, int device, int M, int flags) {
     p->device = device;
     p->M = M;
     p->L = default_chunk(M);
+    if (flags & LP_FLAG_HIGH_RADIUS) dispatch(M, [&](auto ops) { p->L = decltype(ops)::max_chunk(); });
     p->flags = flags;
     *out = p;
     return LP_OK;
@@ -719,6 +491,8 @@ int lp_plan_create(lp_plan **out, int device, int M, int flags) {
 
 int lp_plan_destroy(lp_plan *p) {
     if (!p) return LP_OK;
+    if (p->live_graphs > 0)
+        return fail(LP_EINVAL, "plan still has %d captured graph(s); destroy them first", p->live_graphs);
     for (auto &r : p->pending) {
         (void)hipEventDestroy(r.start);
         (void)hipEventDestroy(r.stop);
@@ -739,6 +513,8 @@ int lp_plan_set_chunk(lp_plan *p, int L) {
     int maxL = 0;
     dispatch(p->M, [&](auto ops) { maxL = decltype(ops)::max_chunk(); });
     if (L > maxL) return fail(LP_EINVAL, "chunk length %d exceeds the maximum %d for M = %d", L, maxL, p->M);
+    if (p->live_graphs > 0 && L != p->L)
+        return fail(LP_EINVAL, "chunk length is fixed while %d captured graph(s) use the plan", p->live_graphs);
     p->L = L;
     return LP_OK;
 }
@@ -827,13 +603,15 @@ size_t lp_saved_bytes_varlen(const lp_plan *p, int64_t B, int64_t N) {
 }
 
 int lp_forward(lp_plan *p, int64_t B, int64_t T, const float *e, const float *a, const double *zi, float *s,
-               double *zf, void *saved, void *stream) {
-    return forward_impl(p, B, nullptr, T, e, a, zi, s, zf, saved, stream);
+               double *zf, void *saved, uint32_t *nonfinite, void *stream) {
+    return forward_impl(p, B, nullptr, T, e, a, zi, s, zf, saved, stream, nullptr, nullptr, 0, false, nonfinite);
 }
 
 int lp_backward(lp_plan *p, int64_t B, int64_t T, const float *g, const float *a, const float *e, const double *zi,
-                const float *s, const void *saved, float *grad_e, float *grad_a, double *grad_zi, void *stream) {
-    return backward_impl(p, B, nullptr, T, g, a, e, zi, s, saved, grad_e, grad_a, grad_zi, stream);
+                const float *s, const void *saved, float *grad_e, float *grad_a, double *grad_zi,
+                uint32_t *nonfinite, void *stream) {
+    return backward_impl(p, B, nullptr, T, g, a, e, zi, s, saved, grad_e, grad_a, grad_zi, stream, 0, false,
+                         nonfinite);
 }
 
 int lp_forward_ti(lp_plan *p, int64_t B, int64_t T, const float *e, const float *a, const double *zi, float *s,
@@ -957,6 +735,8 @@ int lp_plan_autotune(lp_plan *p, int64_t B, int64_t T, int reps, int *chosen, do
     if (int r = check_plan(p)) return r;
     if (B < 1 || T < 1) return fail(LP_EINVAL, "B and T must be >= 1");
     if (reps < 1) reps = 3;
+    if (p->live_graphs > 0)
+        return fail(LP_EINVAL, "cannot autotune while %d captured graph(s) use the plan", p->live_graphs);
     const int M = p->M;
     // the timed batch keeps T and at most ~32 M samples (beyond that every candidate fills the chip)
     const int64_t Bt = std::max<int64_t>(1, std::min<int64_t>(B, (int64_t(1) << 25) / T));
@@ -967,9 +747,19 @@ int lp_plan_autotune(lp_plan *p, int64_t B, int64_t T, int reps, int *chosen, do
     // time is not smooth in L (the chunk stride meets the memory interleave
     // differently at neighbouring lengths), so the grid is dense
     std::vector<int> cands;
-    for (double target = 64.0; target <= 1024.0 * 1.001; target *= 1.06) {
-        const int L = std::max(1, (int(target) + M / 2) / M) * M;
-        if (L <= maxL && std::find(cands.begin(), cands.end(), L) == cands.end()) cands.push_back(L);
+    if (p->flags & LP_FLAG_HIGH_RADIUS) {
+        // high-radius plans: only chunk lengths long enough for the chained carry's accuracy
+        const int lo = std::min(kAccurateChunk, maxL);
+        for (double target = lo; target <= maxL * 1.001; target *= 1.06) {
+            const int L = std::min(maxL, std::max(1, (int(target) + M - 1) / M) * M);
+            if (std::find(cands.begin(), cands.end(), L) == cands.end()) cands.push_back(L);
+        }
+        if (std::find(cands.begin(), cands.end(), maxL) == cands.end()) cands.push_back(maxL);
+    } else {
+        for (double target = 64.0; target <= 1024.0 * 1.001; target *= 1.06) {
+            const int L = std::max(1, (int(target) + M / 2) / M) * M;
+            if (L <= maxL && std::find(cands.begin(), cands.end(), L) == cands.end()) cands.push_back(L);
+        }
     }
     const int oldL = p->L;
     size_t saved_bytes = 0;  // the smallest chunk length needs the most saved state
@@ -1002,8 +792,8 @@ int lp_plan_autotune(lp_plan *p, int64_t B, int64_t T, int reps, int *chosen, do
         float bestL_ms = 1e30f;
         for (int r = 0; r <= reps && rc == LP_OK; ++r) {  // r = 0 warms up (and sizes the workspace)
             (void)hipEventRecord(e0, st);
-            rc = lp_forward(p, Bt, T, e, a, nullptr, s, nullptr, saved, st);
-            if (rc == LP_OK) rc = lp_backward(p, Bt, T, g, a, e, nullptr, nullptr, saved, ge, ga, nullptr, st);
+            rc = lp_forward(p, Bt, T, e, a, nullptr, s, nullptr, saved, nullptr, st);
+            if (rc == LP_OK) rc = lp_backward(p, Bt, T, g, a, e, nullptr, nullptr, saved, ge, ga, nullptr, nullptr, st);
             (void)hipEventRecord(e1, st);
             if (rc == LP_OK) rc = check_hip(hipEventSynchronize(e1), "autotune sync");
             float ms = 0.f;
@@ -1101,6 +891,7 @@ struct lp_graph {
     int device;
     hipGraph_t graph;
     hipGraphExec_t exec;
+    lp_plan *plan;  // whose workspace the graph's kernels address
 };
 
 extern "C" {
@@ -1133,7 +924,7 @@ int lp_graph_capture_pair_step(lp_plan *p, int64_t B, int64_t T, const float *e2
     p->timing = timing;
     lp_graph *gr = nullptr;
     if (rc == LP_OK) {
-        gr = new (std::nothrow) lp_graph{p->device, graph, nullptr};
+        gr = new (std::nothrow) lp_graph{p->device, graph, nullptr, p};
         if (!gr) rc = fail(LP_ENOMEM, "out of host memory");
     }
     if (rc == LP_OK && hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0) != hipSuccess)
@@ -1144,6 +935,7 @@ int lp_graph_capture_pair_step(lp_plan *p, int64_t B, int64_t T, const float *e2
         delete gr;
         return rc;
     }
+    ++p->live_graphs;
     *out = gr;
     return LP_OK;
 }
@@ -1159,6 +951,7 @@ int lp_graph_destroy(lp_graph *gr) {
     DeviceGuard dg(gr->device);
     if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
     if (gr->graph) (void)hipGraphDestroy(gr->graph);
+    if (gr->plan && gr->plan->live_graphs > 0) --gr->plan->live_graphs;
     delete gr;
     return LP_OK;
 }

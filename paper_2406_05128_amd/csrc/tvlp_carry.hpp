@@ -1,20 +1,19 @@
 // Carries across chunks (gfx950).
 //
-// Forward.  k_fwd_chain (one wave per sequence) runs the sequence's group maps
-// in order, x(g+1) = P_g x(g) + r_g from x(0) = zi, giving every group's entry
-// state; k_fwd_expand (one wave per group) then applies the group's chunk
-// transitions, x(c+1) = Phi_c x(c) + z_c, and writes every chunk's entry state
-// x_c (the state the reruns start from).
+// Forward.  The group maps x(g+1) = P_g x(g) + r_g, applied from x(0) = zi,
+// give every group's entry state; the group's chunk transitions x(c+1) =
+// Phi_c x(c) + z_c then give every chunk's entry state x_c (the state the
+// reruns start from).  k_fwd_carry does both, one block per group.
 //
-// Adjoint.  The mirror image, right to left: k_bwd_chain runs the reverse
-// group maps y(g) = Psi_g y(g+1) + w_g from y = 0 at the sequence end;
-// k_bwd_expand applies y(c) = Phi_c^T y(c+1) + q_c inside each group, writing
-// the pending vector entering every chunk from the right, yend[c] = y(c+1),
-// and dL/dzi = y(0).
+// Adjoint.  The mirror image, right to left: k_bwd_chain (one block per
+// sequence) runs the reverse group maps y(g) = Psi_g y(g+1) + w_g from y = 0 at
+// the sequence end; k_bwd_expand (one block per group) applies y(c) = Phi_c^T
+// y(c+1) + q_c inside each group, writing the pending vector entering every
+// chunk from the right, yend[c] = y(c+1), and dL/dzi = y(0).
 //
-// Chained mode: the chain kernels apply every chunk's transition in turn (no
-// group maps, hence no matrix products) and write the per-chunk vectors
-// themselves; no expansion follows.
+// Chained mode: k_fwd_chain / k_bwd_chain (one block per sequence) apply every
+// chunk's transition in turn (no group maps, hence no matrix products) and
+// write the per-chunk vectors themselves.
 //
 // Matrices are staged through LDS in batches by several waves with many loads
 // in flight; in the chain kernels three waves stage the next batch while the
@@ -102,12 +101,14 @@ __global__ __launch_bounds__(256) void k_fwd_chain(Seqs S, Groups GR, const doub
                                                    const double *__restrict__ phiT,
                                                    const double *__restrict__ zbuf,
                                                    const double *__restrict__ aggbuf, double *__restrict__ ginc,
-                                                   double *__restrict__ xs, int chain) {
+                                                   double *__restrict__ xs, int chain,
+                                                   uint32_t *__restrict__ nonfinite) {
     using CS = CarryShape<M>;
     constexpr int MM = M * M;
     __shared__ double lds[2 * CS::BUF_DOUBLES + M];
     double *v = lds + 2 * CS::BUF_DOUBLES;
     const int64_t b = blockIdx.x;
+    if (nonfinite && threadIdx.x == 0) nonfinite[b] = 0u;  // the forward emit sets it
     const SeqView sv = seq_view(S, b);
     if (sv.C <= 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -149,34 +150,6 @@ __global__ __launch_bounds__(256) void k_fwd_chain(Seqs S, Groups GR, const doub
     }
 }
 
-template <int M, int CPW>
-__global__ __launch_bounds__(256) void k_fwd_expand(Seqs S, Groups GR, const double *__restrict__ phiT,
-                                                    const double *__restrict__ zbuf,
-                                                    const double *__restrict__ ginc, double *__restrict__ xs) {
-    constexpr int MM = M * M;
-    __shared__ double lds[CPW * (MM + M) + M];
-    double *v = lds + CPW * (MM + M);
-    const int64_t gid = blockIdx.x;
-    if (gid >= GR.ngroups) return;
-    int64_t b, g;
-    group_at(S, GR, gid, b, g);
-    const SeqView sv = seq_view(S, b);
-    if (g >= groups_of(sv.C, CPW)) return;
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int64_t c0 = g * CPW;
-    const int nk = (int)min((int64_t)CPW, sv.C - c0);
-    const int nt = nk - 1;  // transitions needed inside the group
-    stage_doubles(lds, phiT + (sv.cbase + c0) * MM, (int64_t)nt * MM, tid, blockDim.x);
-    stage_doubles(lds + CPW * MM, zbuf + (sv.cbase + c0) * M, (int64_t)nt * M, tid, blockDim.x);
-    if (tid < M) v[tid] = ginc[gid * M + tid];
-    __syncthreads();
-    if (tid >= 64) return;
-    for (int k = 0; k < nk; ++k) {
-        if (lane < M) xs[(sv.cbase + c0 + k) * M + lane] = v[lane];
-        if (k < nt) lds_step<M>(lds + k * MM, 1, M, v, lane < M ? lds[CPW * MM + k * M + lane] : 0.0, lane);
-    }
-}
-
 // ---------------------------------------------------------------- adjoint
 
 // Chained: items are chunks (Phi_c^T, q_c; output yend per chunk; the last
@@ -188,12 +161,13 @@ __global__ __launch_bounds__(256) void k_bwd_chain(Seqs S, Groups GR, const doub
                                                    const double *__restrict__ qbuf,
                                                    const double *__restrict__ aggbuf, double *__restrict__ ginc,
                                                    double *__restrict__ yend, double *__restrict__ grad_zi,
-                                                   int chain) {
+                                                   int chain, uint32_t *__restrict__ nonfinite) {
     using CS = CarryShape<M>;
     constexpr int MM = M * M;
     __shared__ double lds[2 * CS::BUF_DOUBLES + M];
     double *v = lds + 2 * CS::BUF_DOUBLES;
     const int64_t b = blockIdx.x;
+    if (nonfinite && threadIdx.x == 0) nonfinite[b] = 0u;  // the adjoint emit sets it
     const SeqView sv = seq_view(S, b);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (sv.C <= 0) {  // no samples: no dependence on the initial state
@@ -287,6 +261,78 @@ __global__ __launch_bounds__(256) void k_bwd_expand(Seqs S, Groups GR, const dou
             lds_step<M>(lds + k * MM, M, 1, v, q, lane);
     }
     if (need_first && lane < M) grad_zi[b * M + lane] = v[lane];
+}
+
+// ---------------------------------------------------------------- fused forward carry (grouped mode)
+//
+// One launch in place of a chain and an expansion: one block per group.  A
+// block first forms its group's entry state by applying the maps of the groups
+// before it (groups 0 .. g-1, from zi), then expands it through the group's own
+// chunk transitions.  The prefix is recomputed by every block (at most n-1
+// small matrix-vector products), so no block waits on another.  Maps and
+// transitions are staged into LDS by all four waves; wave 0 applies them.
+// (The same fusion of the adjoint carry was measured slower overall: the
+// adjoint emit that follows it ran about 20 % longer.)
+
+template <int M, int CPW>
+struct FusedCarryShape {
+    static constexpr int MM = M * M;
+    // maps (with offsets) per staged batch, about 32 KiB, and at least a group's
+    // transitions
+    static constexpr int FIT = 4096 / (MM + M) > 0 ? 4096 / (MM + M) : 1;
+    static constexpr int NBM = (FIT < 8 ? FIT : 8) > CPW ? (FIT < 8 ? FIT : 8) : CPW;
+    static constexpr int BUF = NBM * (MM + M);
+};
+
+template <int M, int CPW>
+__global__ __launch_bounds__(256) void k_fwd_carry(Seqs S, Groups GR, const double *__restrict__ zi,
+                                                   const double *__restrict__ phiT,
+                                                   const double *__restrict__ zbuf,
+                                                   const double *__restrict__ aggbuf, double *__restrict__ xs,
+                                                   uint32_t *__restrict__ nonfinite) {
+    using FS = FusedCarryShape<M, CPW>;
+    constexpr int MM = M * M;
+    static_assert(CPW <= FS::NBM, "a group's transitions must fit one staged batch");
+    __shared__ double lds[FS::BUF + M];
+    double *v = lds + FS::BUF;
+    const int64_t gid = blockIdx.x;
+    // the forward emit sets the flags; block gid clears sequence gid's (every
+    // launch has at least one group slot per sequence)
+    if (nonfinite && gid < S.n && threadIdx.x == 0) nonfinite[gid] = 0u;
+    if (gid >= GR.ngroups) return;
+    int64_t b, g;
+    group_at(S, GR, gid, b, g);
+    const SeqView sv = seq_view(S, b);
+    if (g >= groups_of(sv.C, CPW)) return;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int64_t gid0 = group_id(S, GR, b, 0);
+    if (tid < M) v[tid] = zi ? zi[b * M + tid] : 0.0;
+    // x(g) = P_{g-1} ... P_0 zi + ... : the maps of the groups before g, in batches
+    for (int64_t k0 = 0; k0 < g; k0 += FS::NBM) {
+        const int nb = (int)min((int64_t)FS::NBM, g - k0);
+        __syncthreads();
+        stage_doubles(lds, aggbuf + (gid0 + k0) * (MM + M), (int64_t)nb * (MM + M), tid, blockDim.x);
+        __syncthreads();
+        if (tid < 64) {
+            for (int k = 0; k < nb; ++k) {
+                const double *A = lds + k * (MM + M);  // column-major map, then its offset
+                lds_step<M>(A, 1, M, v, lane < M ? A[MM + lane] : 0.0, lane);
+            }
+        }
+    }
+    // the group's chunks: x(c+1) = Phi_c x(c) + z_c
+    const int64_t c0 = g * CPW;
+    const int nk = (int)min((int64_t)CPW, sv.C - c0);
+    const int nt = nk - 1;
+    __syncthreads();
+    stage_doubles(lds, phiT + (sv.cbase + c0) * MM, (int64_t)nt * MM, tid, blockDim.x);
+    stage_doubles(lds + FS::NBM * MM, zbuf + (sv.cbase + c0) * M, (int64_t)nt * M, tid, blockDim.x);
+    __syncthreads();
+    if (tid >= 64) return;
+    for (int k = 0; k < nk; ++k) {
+        if (lane < M) xs[(sv.cbase + c0 + k) * M + lane] = v[lane];
+        if (k < nt) lds_step<M>(lds + k * MM, 1, M, v, lane < M ? lds[FS::NBM * MM + k * M + lane] : 0.0, lane);
+    }
 }
 
 }  // namespace tvlp

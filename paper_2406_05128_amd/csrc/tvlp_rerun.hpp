@@ -27,6 +27,7 @@
 #include <type_traits>
 
 #include "tvlp_systolic.hpp"
+#include "tvlp_tiles.hpp"
 
 namespace tvlp {
 
@@ -453,22 +454,51 @@ __device__ __forceinline__ void ring_loop(RR &rr, float *ring, int L, int U, Bod
 template <int M, int CPW, bool DESC, bool FR>
 using RingOf = std::conditional_t<FR, FrameRing<M, CPW, DESC>, RowRing<M, CPW, DESC>>;
 
-template <int M, int G, bool FR = false>
+// Tile ring of the per-sample-row kernels: 4 slots of 8 rows (4 rows for 16
+// chunks per wave, to keep the ring near 24 KB).
+template <int M, int CPW, bool DESC>
+using TileOf = TileRing<M, CPW, DESC, (CPW >= 16 ? 4 : 8), 4>;
+
+// Rows of the coefficient array (= samples of the sequence layout).
+__device__ __forceinline__ int64_t seq_rows(const Seqs &S) {
+    return (S.offsets || S.starts) ? S.N : S.n * S.T;
+}
+
+// Shortest chunk of the wave (0 if a slot is inactive); my_len: the lane's chunk rows.
+template <int CPW, int G>
+__device__ __forceinline__ int wave_min_len(int64_t my_len) {
+    int mn = 0x7fffffff;
+#pragma unroll
+    for (int k = 0; k < CPW; ++k) mn = min(mn, __builtin_amdgcn_readlane((int)my_len, k * G));
+    return mn;
+}
+
+// LDS bytes of a rerun wave's s staging ([cpw][L] floats), rounded to 16 bytes.
+__host__ __device__ constexpr size_t rerun_s_lds_bytes(int cpw, int L) {
+    return ((size_t)cpw * (size_t)L * sizeof(float) + 15) & ~(size_t)15;
+}
+
+template <int M, int G, bool FR = false, bool TILE = false>
 struct RerunLds {
-    static constexpr int BYTES = RingOf<M, 64 / G, false, FR>::FLOATS * 4;
+    static constexpr int BYTES = (TILE ? TileOf<M, 64 / G, false>::FLOATS : RingOf<M, 64 / G, false, FR>::FLOATS) * 4;
 };
 
 // FR: a holds frame-rate rows [B][F][M] and frl is the frame staging area
 // (frame_lds_bytes(64 / G, M, S.nf) bytes of LDS).
-template <int M, int G, bool FR = false>
+// TILE: per-sample rows (not FR, not time-invariant) streamed through the
+// tile ring of tvlp_tiles.hpp instead of the row ring.
+template <int M, int G, bool FR = false, bool TILE = false>
 __device__ __forceinline__ void rerun_chunks(Seqs S, const float *__restrict__ e, const float *__restrict__ a,
                                              const double *__restrict__ xs, float *__restrict__ s,
                                              double *__restrict__ zf, const float *__restrict__ zero,
                                              int64_t nch, int64_t blk, float *ring,
-                                             double *__restrict__ zall = nullptr, unsigned char *frl = nullptr) {
+                                             double *__restrict__ zall = nullptr, unsigned char *frl = nullptr,
+                                             float *sst = nullptr, uint32_t *__restrict__ nonfinite = nullptr) {
     constexpr int CPW = 64 / G;
     constexpr int TPL = (M + G - 1) / G;
+    static_assert(!(TILE && FR), "frame-rate rows are produced in LDS, not tiled");
     using RR = RingOf<M, CPW, false, FR>;
+    using TR = TileOf<M, CPW, false>;
 
     const int lane = threadIdx.x;
     const int slot = lane / G, r = lane % G;
@@ -491,23 +521,17 @@ __device__ __forceinline__ void rerun_chunks(Seqs S, const float *__restrict__ e
         const int k = r * TPL + m;
         hist[m] = (active && k < M && xs) ? xs[gc * M + k] : 0.0;
     }
-    RR rr;
-    if constexpr (FR)
-        rr.init(a, e, zero, lane, base, len, G, 0, b, c * S.L, S, frl);
-    else
-        rr.init(a, e, zero, lane, base, len, G, 0, coef_row(S, b, base), S.ti);
-    const typename RR::template Lanes<TPL> ln(slot, r);
     const int L = S.L;
-    for (int u = 0; u < RR::D; ++u) rr.issue(ring, u);
-    RR::wait_next();  // row 0
     // step u's operands are read from LDS during step u-1
     double av[TPL], ex;
-    RR::load(ring, 0, ln, av, ex);
-    float *so = s ? s + base : nullptr;
+    // With sst ([CPW][L] floats of LDS), s is collected there and written with
+    // coalesced stores after the loop (stores inside the ring loop share vmcnt
+    // with the row DMA and scatter 8 lanes per chunk over the memory pipeline);
+    // without it, s goes straight to memory.
+    float *so = s ? (sst ? sst + slot * L : s + base) : nullptr;
     float yk = 0.f;  // unclamped steps: lane r keeps y of the steps u = r (mod G)
-    ring_loop(rr, ring, L, fast_steps<RR, G, CPW>(len), [&](int u, auto ks, auto fast) {
-        double nav[TPL], nex;
-        RR::load(ring, ks, ln, nav, nex);
+    // one step of Eq. 6 on the group's lanes, with the next step's operands
+    auto step = [&](int u, const double (&nav)[TPL], double nex, auto fast) {
         double part = 0.0;
 #pragma unroll
         for (int m = 0; m < TPL; ++m) part = fma(av[m], hist[m], part);
@@ -532,7 +556,51 @@ __device__ __forceinline__ void rerun_chunks(Seqs S, const float *__restrict__ e
 #pragma unroll
         for (int m = 0; m < TPL; ++m) av[m] = nav[m];
         ex = nex;
-    });
+    };
+    if constexpr (TILE) {
+        TR tr;
+        const int delta = tr.init(a, seq_rows(S), e, seq_rows(S), lane, base, len, G, base);
+        const typename TR::template Lanes<TPL> ln(slot, r, delta);
+        tr.start(ring);
+        TR::load(ring, TR::first(), ln, av, ex, r);
+        tile_loop(tr, ring, L, wave_min_len<CPW, G>(len), [&](int u, auto ks, auto fast) {
+            double nav[TPL], nex;
+            TR::load(ring, ks, ln, nav, nex, r);
+            step(u, nav, nex, fast);
+        });
+    } else {
+        RR rr;
+        if constexpr (FR)
+            rr.init(a, e, zero, lane, base, len, G, 0, b, c * S.L, S, frl);
+        else
+            rr.init(a, e, zero, lane, base, len, G, 0, coef_row(S, b, base), S.ti);
+        const typename RR::template Lanes<TPL> ln(slot, r);
+        for (int u = 0; u < RR::D; ++u) rr.issue(ring, u);
+        RR::wait_next();  // row 0
+        RR::load(ring, 0, ln, av, ex);
+        ring_loop(rr, ring, L, fast_steps<RR, G, CPW>(len), [&](int u, auto ks, auto fast) {
+            double nav[TPL], nex;
+            RR::load(ring, ks, ln, nav, nex);
+            step(u, nav, nex, fast);
+        });
+    }
+    if (s && sst) {
+        // the wave's chunks one after the other, 64 consecutive samples per store;
+        // a chunk holding a non-finite output flags its sequence
+        __syncthreads();
+        for (int k = 0; k < CPW; ++k) {
+            const int64_t kb = __shfl(base, k * G, 64);
+            const int kl = __shfl((int)len, k * G, 64);
+            const int64_t kseq = __shfl(b, k * G, 64);
+            bool bad = false;
+            for (int i = lane; i < kl; i += 64) {
+                const float v = sst[k * L + i];
+                bad |= !__builtin_isfinite(v);
+                s[kb + i] = v;
+            }
+            if (nonfinite && __builtin_amdgcn_ballot_w64(bad) != 0 && lane == 0) atomicOr(nonfinite + kseq, 1u);
+        }
+    }
     if (zall && active) {
 #pragma unroll
         for (int m = 0; m < TPL; ++m) {
@@ -552,15 +620,19 @@ __device__ __forceinline__ void rerun_chunks(Seqs S, const float *__restrict__ e
     }
 }
 
-template <int M, int G, bool FR = false>
+template <int M, int G, bool FR = false, bool TILE = false>
 __global__ __launch_bounds__(64) void k_fwd_rerun2(Seqs S, const float *__restrict__ e,
                                                    const float *__restrict__ a,
                                                    const double *__restrict__ xs,
                                                    float *__restrict__ s, double *__restrict__ zf,
-                                                   const float *__restrict__ zero, int64_t nch) {
-    __shared__ __attribute__((aligned(16))) float ring[RerunLds<M, G, FR>::BYTES / 4];
-    extern __shared__ __attribute__((aligned(16))) unsigned char rerun_dyn[];  // FR: frame staging
-    rerun_chunks<M, G, FR>(S, e, a, xs, s, zf, zero, nch, blockIdx.x, ring, nullptr, rerun_dyn);
+                                                   const float *__restrict__ zero, int64_t nch,
+                                                   uint32_t *__restrict__ nonfinite) {
+    __shared__ __attribute__((aligned(16))) float ring[RerunLds<M, G, FR, TILE>::BYTES / 4];
+    // dynamic LDS: s staging [CPW][L] floats, then (FR) the frame staging area
+    extern __shared__ __attribute__((aligned(16))) unsigned char rerun_dyn[];
+    rerun_chunks<M, G, FR, TILE>(S, e, a, xs, s, zf, zero, nch, blockIdx.x, ring, nullptr,
+                                 rerun_dyn + rerun_s_lds_bytes(64 / G, S.L), reinterpret_cast<float *>(rerun_dyn),
+                                 nonfinite);
 }
 
 // Adjoint rerun of each chunk (push form of Eq. 12, descending), from the
@@ -589,7 +661,8 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
                                                   const double *__restrict__ yend,
                                                   float *__restrict__ ge, float *__restrict__ ga,
                                                   double *__restrict__ tipart,
-                                                  const float *__restrict__ zero, int64_t nch) {
+                                                  const float *__restrict__ zero, int64_t nch,
+                                                  uint32_t *__restrict__ nonfinite) {
     constexpr int CPW = 64 / G;
     constexpr int TPL = (M + G - 1) / G;
     // frame-rate rows: 12 steps in flight keep four blocks of the training shape per CU
@@ -769,43 +842,63 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
         }
     }
 
-    // ---- dL/de(t) = ghat(t), dL/da_i(t) = -ghat(t) s(t-i), chunk by chunk with all lanes
-    for (int k = 0; k < CPW; ++k) {
-        const int kl = (int)__shfl(len, k * G, 64);
-        const int64_t kb = __shfl(base, k * G, 64);
-        const float *sk = ssh_dyn + k * (M + L);
-        const float *gk = gsh_all + k * L;
-        if (ge)
-            for (int t = lane; t < kl; t += 64) ge[kb + t] = gk[t];
-        if (ga) {
-            float *gak = ga + kb * M;
-            if (M % 2 == 0 && (reinterpret_cast<uintptr_t>(ga) & 7) == 0) {
-                // pairs of taps (i, i+1) of one row per lane, float2 stores (8-byte aligned: M even)
-                constexpr int SQ = 128 / M, SR = 128 % M;  // lane stride of 64 pairs in rows and taps
-                const int n2 = kl * (M / 2);
-                int t = (2 * lane) / M, i = 2 * lane - t * M;
-                for (int j = lane; j < n2; j += 64) {
-                    const float gt = -gk[t];
-                    float2 v;
-                    v.x = gt * sk[M + t - 1 - i];
-                    v.y = gt * sk[M + t - 2 - i];
-                    *reinterpret_cast<float2 *>(gak + 2 * j) = v;
-                    t += SQ;
-                    i += SR;
-                    if (i >= M) {
-                        i -= M;
-                        ++t;
+    // ---- dL/de(t) = ghat(t), dL/da_i(t) = -ghat(t) s(t-i), chunk by chunk with all lanes;
+    // with flags requested, a chunk holding a non-finite gradient value flags its sequence
+    auto write_grads = [&](auto checkc) {
+        constexpr bool CHECK = decltype(checkc)::value;
+        for (int k = 0; k < CPW; ++k) {
+            const int kl = (int)__shfl(len, k * G, 64);
+            const int64_t kb = __shfl(base, k * G, 64);
+            const float *sk = ssh_dyn + k * (M + L);
+            const float *gk = gsh_all + k * L;
+            bool bad = false;
+            if (ge || CHECK)
+                for (int t = lane; t < kl; t += 64) {
+                    const float v = gk[t];
+                    if constexpr (CHECK) bad |= !__builtin_isfinite(v);
+                    if (ge) ge[kb + t] = v;
+                }
+            if (ga) {
+                float *gak = ga + kb * M;
+                if (M % 2 == 0 && (reinterpret_cast<uintptr_t>(ga) & 7) == 0) {
+                    // pairs of taps (i, i+1) of one row per lane, float2 stores (8-byte aligned: M even)
+                    constexpr int SQ = 128 / M, SR = 128 % M;  // lane stride of 64 pairs in rows and taps
+                    const int n2 = kl * (M / 2);
+                    int t = (2 * lane) / M, i = 2 * lane - t * M;
+                    for (int j = lane; j < n2; j += 64) {
+                        const float gt = -gk[t];
+                        float2 v;
+                        v.x = gt * sk[M + t - 1 - i];
+                        v.y = gt * sk[M + t - 2 - i];
+                        if constexpr (CHECK) bad |= !__builtin_isfinite(v.x) | !__builtin_isfinite(v.y);
+                        *reinterpret_cast<float2 *>(gak + 2 * j) = v;
+                        t += SQ;
+                        i += SR;
+                        if (i >= M) {
+                            i -= M;
+                            ++t;
+                        }
+                    }
+                } else {
+                    const int n = kl * M;
+                    for (int f = lane; f < n; f += 64) {
+                        const int t = f / M, i = f - t * M;
+                        const float v = -gk[t] * sk[M + t - 1 - i];
+                        if constexpr (CHECK) bad |= !__builtin_isfinite(v);
+                        gak[f] = v;
                     }
                 }
-            } else {
-                const int n = kl * M;
-                for (int f = lane; f < n; f += 64) {
-                    const int t = f / M, i = f - t * M;
-                    gak[f] = -gk[t] * sk[M + t - 1 - i];
-                }
+            }
+            if constexpr (CHECK) {
+                const int64_t kseq = __shfl(b, k * G, 64);
+                if (__builtin_amdgcn_ballot_w64(bad) != 0 && lane == 0) atomicOr(nonfinite + kseq, 1u);
             }
         }
-    }
+    };
+    if (nonfinite)
+        write_grads(std::true_type{});
+    else
+        write_grads(std::false_type{});
 }
 
 // dL/da[b][i] for time-invariant coefficients: the per-chunk shares summed over

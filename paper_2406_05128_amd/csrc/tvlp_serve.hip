@@ -88,7 +88,9 @@ struct Job {
     int64_t off = 0;  // arena offset in samples
     int64_t pos = 0;  // samples already filtered
     hipEvent_t ev_up = nullptr, ev_down = nullptr;
-    Clock::time_point t_submit, t_admit, t_first, t_done;
+    // submitted, admitted (upload issued), first slice launched, last slice
+    // finished on the device, output downloaded
+    Clock::time_point t_submit, t_admit, t_first, t_computed, t_done;
     int status = LP_OK;
 };
 
@@ -217,6 +219,7 @@ void lp_server::run() {
                 samples_done += len;
                 if (j->pos >= j->T) {
                     // output complete: download, then release the arena space
+                    j->t_computed = Clock::now();
                     j->state = JobState::Downloading;
                     slots[s] = nullptr;
                     if (hipMemcpyAsync(j->s_host, s_arena + j->off, (size_t)j->T * sizeof(float),
@@ -352,7 +355,10 @@ int lp_serve_submit(lp_server *srv, int64_t T, const float *e_host, const float 
     return LP_OK;
 }
 
-int lp_serve_poll(lp_server *srv, uint64_t ticket, double *latency_ms_out) {
+}  // extern "C"
+
+namespace {
+int poll_impl(lp_server *srv, uint64_t ticket, double *latency_ms_out, double *device_ms_out) {
     if (!srv) return serve_fail(LP_EINVAL, "server is NULL");
     std::lock_guard<std::mutex> lk(srv->mu);
     auto it = srv->jobs.find(ticket);
@@ -361,6 +367,7 @@ int lp_serve_poll(lp_server *srv, uint64_t ticket, double *latency_ms_out) {
     if (j->state == JobState::Done || j->state == JobState::Failed) {
         const int st = j->status;
         if (latency_ms_out) *latency_ms_out = ms_between(j->t_submit, j->t_done);
+        if (device_ms_out) *device_ms_out = st == LP_OK ? ms_between(j->t_first, j->t_computed) : 0.0;
         (void)hipEventDestroy(j->ev_up);
         (void)hipEventDestroy(j->ev_down);
         srv->jobs.erase(it);
@@ -369,13 +376,20 @@ int lp_serve_poll(lp_server *srv, uint64_t ticket, double *latency_ms_out) {
     }
     return LP_PENDING;
 }
+}  // namespace
 
-int lp_serve_wait(lp_server *srv, uint64_t ticket, double timeout_s, double *latency_ms_out) {
+extern "C" {
+
+int lp_serve_poll(lp_server *srv, uint64_t ticket, double *latency_ms_out) {
+    return poll_impl(srv, ticket, latency_ms_out, nullptr);
+}
+
+int lp_serve_wait(lp_server *srv, uint64_t ticket, double timeout_s, double *latency_ms_out, double *device_ms_out) {
     if (!srv) return serve_fail(LP_EINVAL, "server is NULL");
     const Clock::time_point deadline =
         Clock::now() + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(timeout_s));
     for (;;) {
-        const int rc = lp_serve_poll(srv, ticket, latency_ms_out);
+        const int rc = poll_impl(srv, ticket, latency_ms_out, device_ms_out);
         if (rc != LP_PENDING) return rc;
         std::unique_lock<std::mutex> lk(srv->mu);
         if (srv->cv.wait_until(lk, std::min(deadline, Clock::now() + std::chrono::milliseconds(1))) ==

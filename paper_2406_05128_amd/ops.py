@@ -35,20 +35,62 @@ def _need(t: torch.Tensor, name: str, dtype: torch.dtype, dim: int):
         raise ValueError(f"{name} must be contiguous")
 
 
+def _tag_saved(saved: Optional[torch.Tensor], plan: "Plan", B: int, T: int):
+    """Record on a saved-state buffer the plan, chunk length and shape it was written
+    with: its layout (chunk states and transitions) depends on all of them."""
+    if saved is not None:
+        saved._tvlp_layout = (id(plan), plan.chunk, int(B), int(T))
+
+
+def _check_saved(saved: torch.Tensor, plan: "Plan", B: int, T: int, nbytes: int):
+    if not isinstance(saved, torch.Tensor):
+        raise TypeError("saved must be the tensor returned by the forward")
+    if saved.device.type != "cuda" or (saved.device.index or 0) != (plan.device.index or 0):
+        raise ValueError("saved lives on another device than the plan")
+    if saved.numel() * saved.element_size() < nbytes:
+        raise ValueError(f"saved holds {saved.numel() * saved.element_size()} bytes, the backward of "
+                         f"B={B}, T={T} at chunk {plan.chunk} needs {nbytes}")
+    tag = getattr(saved, "_tvlp_layout", None)
+    if tag is not None and tag != (id(plan), plan.chunk, int(B), int(T)):
+        raise ValueError(f"saved was written by a forward with (plan, chunk, B, T) = {tag[1:]} on "
+                         f"{'this' if tag[0] == id(plan) else 'another'} plan; this backward runs "
+                         f"chunk {plan.chunk}, B={B}, T={T} (the saved layout depends on the chunk length)")
+
+
+def _check_flags(t: Optional[torch.Tensor], B: int):
+    if t is None:
+        return
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.int32 \
+            or t.dim() != 1 or t.shape[0] < B or not t.is_contiguous():
+        raise ValueError(f"nonfinite must be a contiguous int32 GPU tensor of at least {B} elements")
+
+
+def _check_same(t: Optional[torch.Tensor], name: str, shape):
+    if t is None:
+        return
+    _need(t, name, torch.float32, len(shape))
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
 class Plan:
     """Owns an lp_plan (order M, chunk length, device workspace)."""
 
     def __init__(self, M: int, device: Optional[torch.device] = None, chunk: Optional[int] = None,
-                 chained: bool = False):
-        """chained: LP_FLAG_CHAINED_CARRY (carry chunk by chunk, for strongly resonant inputs)."""
+                 chained: bool = False, high_radius: bool = False):
+        """chained: LP_FLAG_CHAINED_CARRY (carry chunk by chunk, for strongly resonant inputs).
+        high_radius: LP_FLAG_HIGH_RADIUS (poles near the unit circle: the chained carry over
+        chunks long enough for its accuracy; the autotuner keeps to such lengths)."""
         lib = _lib.load()
         dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self.device = dev
         self.M = int(M)
-        self.chained = bool(chained)
+        self.high_radius = bool(high_radius)
+        self.chained = bool(chained) or self.high_radius
         h = ctypes.c_void_p()
         _lib.check(lib.lp_plan_create(ctypes.byref(h), dev.index or 0, self.M,
-                                      _lib.LP_FLAG_CHAINED_CARRY if chained else 0))
+                                      (_lib.LP_FLAG_CHAINED_CARRY if chained else 0)
+                                      | (_lib.LP_FLAG_HIGH_RADIUS if high_radius else 0)))
         self._h = h
         if chunk is not None:
             self.set_chunk(chunk)
@@ -87,7 +129,7 @@ class Plan:
         """
         from . import autotune as _at
         key = _at.cache_key(torch.cuda.get_device_name(self.device), self.M, B, T,
-                            "chained" if self.chained else "grouped")
+                            "high-radius" if self.high_radius else ("chained" if self.chained else "grouped"))
         if cache:
             hit = _at.lookup(key)
             if hit is not None:
@@ -140,10 +182,12 @@ class Plan:
     # ------------------------------------------------------------ uniform batches
     def forward(self, e: torch.Tensor, a: torch.Tensor, zi: Optional[torch.Tensor] = None,
                 want_zf: bool = False, save: bool = True, out: Optional[torch.Tensor] = None,
-                saved_out: Optional[torch.Tensor] = None):
+                saved_out: Optional[torch.Tensor] = None, nonfinite: Optional[torch.Tensor] = None):
         """s = LP_a(e).  Returns (s, zf or None, saved or None).
 
         out / saved_out: optional preallocated output and saved-state buffers.
+        nonfinite: optional int32 [B] device tensor; the call sets element b to 1
+        when some output of sequence b is Inf or NaN, else 0.
         """
         _need(e, "e", torch.float32, 2)
         _need(a, "a", torch.float32, 3)
@@ -160,8 +204,10 @@ class Plan:
             saved = saved_out
         else:
             saved = torch.empty(self.saved_bytes(B, T), dtype=torch.uint8, device=e.device) if save else None
+        _check_flags(nonfinite, B)
         _lib.check(_lib.load().lp_forward(self._h, B, T, _ptr(e), _ptr(a), _ptr(zi), _ptr(s), _ptr(zf),
-                                          _ptr(saved), _stream(e.device)))
+                                          _ptr(saved), _ptr(nonfinite), _stream(e.device)))
+        _tag_saved(saved, self, B, T)
         return s, zf, saved
 
     def forward_ti(self, e: torch.Tensor, a: torch.Tensor, zi: Optional[torch.Tensor] = None,
@@ -179,6 +225,7 @@ class Plan:
         saved = torch.empty(self.saved_bytes(B, T), dtype=torch.uint8, device=e.device) if save else None
         _lib.check(_lib.load().lp_forward_ti(self._h, B, T, _ptr(e), _ptr(a), _ptr(zi), _ptr(s), _ptr(zf),
                                              _ptr(saved), _stream(e.device)))
+        _tag_saved(saved, self, B, T)
         return s, zf, saved
 
     def backward_ti(self, g: torch.Tensor, a: torch.Tensor, e: Optional[torch.Tensor], saved: torch.Tensor,
@@ -190,6 +237,11 @@ class Plan:
         B, T = g.shape
         if a.shape != (B, self.M):
             raise ValueError(f"a must have shape {(B, self.M)}, got {tuple(a.shape)}")
+        _check_same(e, "e", (B, T))
+        _check_same(s, "s", (B, T))
+        if zi is not None:
+            _need(zi, "zi", torch.float64, 2)
+        _check_saved(saved, self, B, T, self.saved_bytes(B, T))
         ge = torch.empty_like(g) if need_e else None
         ga = torch.empty_like(a) if need_a else None
         gz = torch.empty((B, self.M), dtype=torch.float64, device=g.device) if need_zi else None
@@ -215,6 +267,7 @@ class Plan:
         saved = torch.empty(self.saved_bytes(B, T), dtype=torch.uint8, device=e.device) if save else None
         _lib.check(_lib.load().lp_forward_frames(self._h, B, T, int(hop), _ptr(e), _ptr(A), _ptr(zi), _ptr(s),
                                                  _ptr(zf), _ptr(saved), _stream(e.device)))
+        _tag_saved(saved, self, B, T)
         return s, zf, saved
 
     def backward_frames(self, g: torch.Tensor, A: torch.Tensor, hop: int, e: Optional[torch.Tensor],
@@ -227,6 +280,11 @@ class Plan:
         F = coef_frames_count(T, hop)
         if A.shape != (B, F, self.M):
             raise ValueError(f"A must have shape {(B, F, self.M)}, got {tuple(A.shape)}")
+        _check_same(e, "e", (B, T))
+        _check_same(s, "s", (B, T))
+        if zi is not None:
+            _need(zi, "zi", torch.float64, 2)
+        _check_saved(saved, self, B, T, self.saved_bytes(B, T))
         ge = torch.empty_like(g) if need_e else None
         gA = torch.empty_like(A) if need_a else None
         gz = torch.empty((B, self.M), dtype=torch.float64, device=g.device) if need_zi else None
@@ -237,16 +295,28 @@ class Plan:
 
     def backward(self, g: torch.Tensor, a: torch.Tensor, e: Optional[torch.Tensor], saved: torch.Tensor,
                  s: Optional[torch.Tensor] = None, zi: Optional[torch.Tensor] = None,
-                 need_e: bool = True, need_a: bool = True, need_zi: bool = False):
-        """Returns (grad_e, grad_a, grad_zi) (None where not requested)."""
+                 need_e: bool = True, need_a: bool = True, need_zi: bool = False,
+                 nonfinite: Optional[torch.Tensor] = None):
+        """Returns (grad_e, grad_a, grad_zi) (None where not requested).  nonfinite:
+        optional int32 [B] device tensor, set to 1 where a sequence's gradients hold
+        Inf or NaN, else 0."""
         _need(g, "g", torch.float32, 2)
         _need(a, "a", torch.float32, 3)
         B, T = g.shape
+        if a.shape != (B, T, self.M):
+            raise ValueError(f"a must have shape {(B, T, self.M)}, got {tuple(a.shape)}")
+        _check_same(e, "e", (B, T))
+        _check_same(s, "s", (B, T))
+        if zi is not None:
+            _need(zi, "zi", torch.float64, 2)
+        _check_saved(saved, self, B, T, self.saved_bytes(B, T))
         ge = torch.empty_like(g) if need_e else None
         ga = torch.empty_like(a) if need_a else None
         gz = torch.empty((B, self.M), dtype=torch.float64, device=g.device) if need_zi else None
+        _check_flags(nonfinite, B)
         _lib.check(_lib.load().lp_backward(self._h, B, T, _ptr(g), _ptr(a), _ptr(e), _ptr(zi), _ptr(s),
-                                           _ptr(saved), _ptr(ge), _ptr(ga), _ptr(gz), _stream(g.device)))
+                                           _ptr(saved), _ptr(ge), _ptr(ga), _ptr(gz), _ptr(nonfinite),
+                                           _stream(g.device)))
         return ge, ga, gz
 
     # ------------------------------------------------------------ packed variable-length batches
@@ -262,12 +332,21 @@ class Plan:
         saved = torch.empty(self.saved_bytes_varlen(B, N), dtype=torch.uint8, device=e.device) if save else None
         _lib.check(_lib.load().lp_forward_varlen(self._h, B, _ptr(offsets), N, _ptr(e), _ptr(a), _ptr(zi),
                                                  _ptr(s), _ptr(zf), _ptr(saved), _stream(e.device)))
+        _tag_saved(saved, self, B, N)
         return s, zf, saved
 
     def backward_varlen(self, g, a, e, offsets, saved, s=None, zi=None, need_e=True, need_a=True,
                         need_zi=False):
+        _need(g, "g", torch.float32, 1)
+        _need(a, "a", torch.float32, 2)
+        _need(offsets, "offsets", torch.int64, 1)
         N = g.shape[0]
         B = offsets.shape[0] - 1
+        if a.shape != (N, self.M):
+            raise ValueError(f"a must have shape {(N, self.M)}, got {tuple(a.shape)}")
+        _check_same(e, "e", (N,))
+        _check_same(s, "s", (N,))
+        _check_saved(saved, self, B, N, self.saved_bytes_varlen(B, N))
         ge = torch.empty_like(g) if need_e else None
         ga = torch.empty_like(a) if need_a else None
         gz = torch.empty((B, self.M), dtype=torch.float64, device=g.device) if need_zi else None

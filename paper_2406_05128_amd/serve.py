@@ -77,13 +77,18 @@ class Server:
         return self._finish(ticket, _lib.load().lp_serve_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(lat)),
                             lat)
 
-    def wait(self, ticket: int, timeout: float = 60.0):
-        """(s, latency_ms); raises TimeoutError if the job is not done in time."""
+    def wait(self, ticket: int, timeout: float = 60.0, device_time: bool = False):
+        """(s, latency_ms), or (s, latency_ms, device_ms) with device_time: the job's
+        time on the device from its first slice to its last; raises TimeoutError if
+        the job is not done in time."""
         lat = ctypes.c_double()
-        rc = _lib.load().lp_serve_wait(self._h, ctypes.c_uint64(ticket), float(timeout), ctypes.byref(lat))
+        dev = ctypes.c_double()
+        rc = _lib.load().lp_serve_wait(self._h, ctypes.c_uint64(ticket), float(timeout), ctypes.byref(lat),
+                                       ctypes.byref(dev))
         if rc == _lib.LP_PENDING:
             raise TimeoutError(f"job {ticket} not done after {timeout} s")
-        return self._finish(ticket, rc, lat)
+        res = self._finish(ticket, rc, lat)
+        return (*res, dev.value) if device_time else res
 
     def stats(self) -> dict:
         v = [ctypes.c_int64() for _ in range(5)]

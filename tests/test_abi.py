@@ -49,7 +49,9 @@ def test_plan_rejects_uncompiled_order():
 def test_null_plan_and_bad_sizes_are_errors():
     lib = _lib.load()
     assert lib.lp_saved_bytes(None, 4, 100) == 0
-    assert lib.lp_forward(None, 1, 1, None, None, None, None, None, None, None) == _lib.LP_EINVAL
+    assert lib.lp_forward(None, 1, 1, None, None, None, None, None, None, None, None) == _lib.LP_EINVAL
+    assert lib.lp_backward(None, 1, 1, None, None, None, None, None, None, None, None, None, None,
+                           None) == _lib.LP_EINVAL
     assert lib.lp_forward_plain(0, 1, 1, None, None, None, None, None, None) == _lib.LP_EINVAL
     assert lib.lp_forward_plain(16, 0, 1, None, None, None, None, None, None) == _lib.LP_EINVAL
     assert lib.lp_forward_plain(16, 1, 1, None, None, None, None, None, None) == _lib.LP_EINVAL
@@ -74,6 +76,6 @@ def test_segments_pair_graph_and_server_argument_errors():
     t = ctypes.c_uint64()
     assert lib.lp_serve_submit(None, 10, None, None, None, ctypes.byref(t)) == _lib.LP_EINVAL
     assert lib.lp_serve_poll(None, 1, None) == _lib.LP_EINVAL
-    assert lib.lp_serve_wait(None, 1, 0.0, None) == _lib.LP_EINVAL
+    assert lib.lp_serve_wait(None, 1, 0.0, None, None) == _lib.LP_EINVAL
     assert lib.lp_serve_stats(None, None, None, None, None, None) == _lib.LP_EINVAL
     assert lib.lp_serve_destroy(None) == _lib.LP_OK

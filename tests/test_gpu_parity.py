@@ -298,6 +298,47 @@ def test_filter_pair_graph_replays(tv):
     graph.close()
 
 
+def test_graph_holds_the_plan_workspace(tv):
+    """A captured graph keeps its plan's workspace address: while the graph exists,
+    calls that would grow (move) the workspace, change the chunk length or destroy
+    the plan are refused and launch nothing; calls that fit still run; after the
+    graph is destroyed everything is allowed again.  (No replay ever touches a
+    freed workspace: the refused calls free nothing.)"""
+    from paper_2406_05128_amd import _lib
+    B, T, M = 2, 4000, 22
+    e2, a2, g = _pair_inputs(B, T, M, seed=54)
+    plan = tv.Plan(M, dev())
+    e2d, a2d, gd = to_dev(e2), to_dev(a2), to_dev(g)
+    y0, s20, sv0 = plan.forward_pair(e2d, a2d)
+    ge0, ga0 = plan.backward_pair(gd, a2d, e2d, sv0)
+    torch.cuda.synchronize()
+    y = torch.empty_like(y0); s2 = torch.empty_like(s20); sv = torch.empty_like(sv0)
+    ge2 = torch.empty_like(ge0); ga2 = torch.empty_like(ga0)
+    graph = tv.PairStepGraph(plan, e2d, a2d, y, s2, sv, gd, ge2, ga2)
+    L0 = plan.chunk
+    big_e = torch.zeros((64, 48000), dtype=torch.float32, device=dev())
+    big_a = torch.zeros((64, 48000, M), dtype=torch.float32, device=dev())
+    with pytest.raises(_lib.TvlpError, match="captured graph"):
+        plan.forward(big_e, big_a)
+    with pytest.raises(_lib.TvlpError, match="captured graph"):
+        plan.set_chunk(L0 + M)
+    with pytest.raises(_lib.TvlpError, match="captured graph"):
+        plan.autotune(2, 4000, reps=1, cache=False)
+    lib = _lib.load()
+    assert lib.lp_plan_destroy(plan.handle) == _lib.LP_EINVAL
+    assert plan.chunk == L0
+    # a call that fits the reserved workspace still runs, and the graph still replays
+    plan.forward(e2d[0], a2d[0])
+    graph.launch()
+    torch.cuda.synchronize()
+    assert torch.equal(y, y0) and torch.equal(ge2, ge0) and torch.equal(ga2, ga0)
+    graph.close()
+    plan.set_chunk(L0 + M)
+    s_big, _, _ = plan.forward(big_e[:4], big_a[:4])
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(s_big).item() == 0
+
+
 def test_autotuned_chunk_is_valid_and_correct(tv, tmp_path, monkeypatch):
     monkeypatch.setenv("TVLP_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
     M = 22
@@ -363,12 +404,44 @@ def test_misaligned_grad_a_matches_aligned(tv):
     st = torch.cuda.current_stream(dev()).cuda_stream
     rc = lib.lp_backward(plan._h, B, T, ctypes.c_void_p(g_d.data_ptr()), ctypes.c_void_p(a_d.data_ptr()),
                          ctypes.c_void_p(e_d.data_ptr()), None, None, ctypes.c_void_p(saved.data_ptr()),
-                         ctypes.c_void_p(ge1.data_ptr()), ctypes.c_void_p(ga1.data_ptr()), None,
+                         ctypes.c_void_p(ge1.data_ptr()), ctypes.c_void_p(ga1.data_ptr()), None, None,
                          ctypes.c_void_p(st))
     assert rc == 0, lib.lp_last_error()
     torch.cuda.synchronize()
     assert torch.equal(ge0, ge1)
     assert torch.equal(ga0.reshape(-1), ga1)
+
+
+def test_nonfinite_flags_only_the_affected_sequences(tv):
+    """Per-sequence non-finite flags of lp_forward / lp_backward: a NaN in one
+    sequence's excitation and an unstable (diverging) coefficient track in another
+    flag exactly those two sequences, in the forward and in the adjoint; every
+    other sequence's outputs are bit-identical to a run without the faulty
+    sequences, and the flags of a clean run are all zero."""
+    B, T, M = 6, 3000, 22
+    e, a, g = workload("train_b64_t48000_m22", gamma=0.98, B=B, T=T)
+    e_bad, a_bad = e.copy(), a.copy()
+    e_bad[1, 1234] = np.nan
+    a_bad[4, 100:, :] = 0.0
+    a_bad[4, 100:, 0] = -1.5  # pole at 1.5 from sample 100 on: s overflows float32 within a few hundred samples
+    plan = tv.Plan(M, dev(), 264)
+    res = {}
+    for name, (ee, aa) in (("clean", (e, a)), ("bad", (e_bad, a_bad))):
+        e_d, a_d, g_d = to_dev(ee), to_dev(aa), to_dev(g)
+        fl_f = torch.full((B,), 7, dtype=torch.int32, device=dev())
+        fl_b = torch.full((B,), 7, dtype=torch.int32, device=dev())
+        s, _, saved = plan.forward(e_d, a_d, nonfinite=fl_f)
+        ge, ga, _ = plan.backward(g_d, a_d, e_d, saved, nonfinite=fl_b)
+        torch.cuda.synchronize()
+        res[name] = (host(s), host(ge), host(ga), fl_f.cpu().numpy(), fl_b.cpu().numpy())
+    s0, ge0, ga0, f0, b0 = res["clean"]
+    s1, ge1, ga1, f1, b1 = res["bad"]
+    assert f0.tolist() == [0] * B and b0.tolist() == [0] * B
+    assert f1.tolist() == [0, 1, 0, 0, 1, 0], f1
+    assert b1.tolist() == [0, 1, 0, 0, 1, 0], b1
+    assert not np.all(np.isfinite(s1[1])) and not np.all(np.isfinite(s1[4]))
+    for b in (0, 2, 3, 5):
+        assert np.array_equal(s1[b], s0[b]) and np.array_equal(ge1[b], ge0[b]) and np.array_equal(ga1[b], ga0[b])
 
 
 def _ti_inputs(B, T, M, seed, radius=0.95):
