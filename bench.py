@@ -119,17 +119,27 @@ def step_bytes(B: int, T: int, M: int) -> float:
     return float(B * T * 4 * (3 * M + 5))
 
 
-def serve_bench(tv, n_req: int, seed: int, slots: int, budget_gib: float, batch: int):
-    """Poisson arrivals (200 req/s, lengths U(12000, 240000), M = 22) through the native server.
+def serve_bench(tv, n_req: int, seed: int, slots: int, budget_gib: float, batch: int,
+                timeout_ms: float = 50.0, small_budget_mb: int = 256):
+    """Serving workload: open-loop Poisson arrivals (200 req/s, lengths U(12000,
+    240000), M = 22, forward only, host-pinned e/a/s) through
 
-    Returns latency percentiles and throughput, plus the same jobs run as
-    padded fixed batches of `batch` in arrival order (host-device copies
-    included on both sides; host-side packing of the padded batches excluded).
+    * the native continuous-batching server with a `budget_gib` arena, and again
+      with a `small_budget_mb` arena (admission by HBM budget under pressure);
+    * a padded fixed-batch baseline fed the same arrival stream: up to `batch`
+      requests, launched when the batch is full or its oldest request has waited
+      `timeout_ms`, padded to the batch's longest request and run as one uniform
+      lp_forward (packing, copies and compute in the request's latency).
+
+    Each run reports p50/p99 of the host latency (arrival to result in host
+    memory) and of the device time (server: a job's first slice to its last;
+    padded: the batch's filter launches), and the useful samples per second.
     """
+    import collections
+
     import numpy as np
     import torch
     from synth import make_coeffs, make_excitation, poisson_requests
-    from paper_2406_05128_amd.serve import latency_percentiles
 
     M = 22
     rng = np.random.default_rng(seed)
@@ -140,64 +150,96 @@ def serve_bench(tv, n_req: int, seed: int, slots: int, budget_gib: float, batch:
     e_pool = torch.from_numpy(make_excitation(rng, 1, pool_T)[0]).pin_memory()
     offs = [int(rng.integers(0, pool_T - int(T) + 1)) for T in lengths]
     outs = [torch.empty(int(T), dtype=torch.float32, pin_memory=True) for T in lengths]
-    budget = int(budget_gib * (1 << 30))
-    with tv.Server(M, budget, max_slots=slots) as srv:
-        # warm the kernels and the scheduler once
-        t = srv.submit(e_pool[:24000], a_pool[:24000])
-        srv.wait(t, 60.0)
-        log(f"serve: {n_req} requests, {slots} slots, {budget_gib} GiB arena")
-        tickets = []
-        t0 = time.perf_counter()
-        for k in range(n_req):
-            delay = float(arrivals[k]) - (time.perf_counter() - t0)
-            if delay > 0:
-                time.sleep(delay)
-            o, T = offs[k], int(lengths[k])
-            tickets.append(srv.submit(e_pool[o:o + T], a_pool[o:o + T], out=outs[k]))
-        lat = [srv.wait(tk, 120.0)[1] for tk in tickets]
-        wall = time.perf_counter() - t0
-        st = srv.stats()
     useful = float(np.sum(lengths))
-    res = latency_percentiles(lat)
-    res = {k: round(v, 3) for k, v in res.items()}
-    res.update({"requests": n_req, "rate_hz": 200.0, "len_range": [12000, 240000], "slots": slots,
-                "arena_GiB": budget_gib, "iterations": st["iterations"],
-                "samples_per_s": round(useful / wall, 1), "offered_samples_per_s": round(useful / float(arrivals[-1]), 1),
-                "wall_s": round(wall, 3)})
 
-    # the same jobs as padded fixed batches (uniform lp_forward over [batch, max T])
-    plan = tv.Plan(M, torch.device("cuda", 0))
+    def pct(x):
+        x = np.asarray(x, dtype=np.float64)
+        return {"p50_ms": round(float(np.percentile(x, 50)), 3), "p99_ms": round(float(np.percentile(x, 99)), 3),
+                "mean_ms": round(float(x.mean()), 3)}
+
+    def continuous(budget_bytes: int, label: str):
+        with tv.Server(M, budget_bytes, max_slots=slots) as srv:
+            t = srv.submit(e_pool[:24000], a_pool[:24000])  # warm the kernels and the scheduler
+            srv.wait(t, 60.0)
+            log(f"serve ({label}): {n_req} requests at 200/s, {slots} slots, {budget_bytes / 2**20:.0f} MiB arena")
+            tickets = []
+            t0 = time.perf_counter()
+            for k in range(n_req):
+                delay = float(arrivals[k]) - (time.perf_counter() - t0)
+                if delay > 0:
+                    time.sleep(delay)
+                o, T = offs[k], int(lengths[k])
+                tickets.append(srv.submit(e_pool[o:o + T], a_pool[o:o + T], out=outs[k]))
+            done = [srv.wait(tk, 120.0, device_time=True) for tk in tickets]
+            wall = time.perf_counter() - t0
+            st = srv.stats()
+        return {"host": pct([d[1] for d in done]), "device": pct([d[2] for d in done]),
+                "arena_MiB": round(budget_bytes / 2**20, 1), "iterations": st["iterations"],
+                "samples_per_s": round(useful / wall, 1), "wall_s": round(wall, 3)}
+
+    res = {"requests": n_req, "rate_hz": 200.0, "len_range": [12000, 240000], "M": M, "slots": slots,
+           "offered_samples_per_s": round(useful / float(arrivals[-1]), 1)}
+    res["continuous"] = continuous(int(budget_gib * (1 << 30)), "large arena")
+    res["continuous_small_budget"] = continuous(small_budget_mb << 20, "small arena")
+
+    # padded fixed batches on the same arrival stream
     dev = torch.device("cuda", 0)
+    plan = tv.Plan(M, dev)
     tmax = int(np.max(lengths))
     e_pad = torch.zeros((batch, tmax), dtype=torch.float32, pin_memory=True)
     a_pad = torch.zeros((batch, tmax, M), dtype=torch.float32, pin_memory=True)
     s_pad = torch.empty((batch, tmax), dtype=torch.float32, pin_memory=True)
     plan.reserve(batch, tmax)
-    busy = 0.0
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # warm-up of the uniform path at the largest shape
+    plan.forward(e_pad.to(dev), a_pad.to(dev), save=False)
+    torch.cuda.synchronize()
+    log(f"serve (padded): batches of {batch}, {timeout_ms} ms timeout")
+    host_lat, dev_lat = [], []
     padded = 0
-    for b0 in range(0, n_req, batch):
-        ids = list(range(b0, min(b0 + batch, n_req)))
-        Tb = int(max(lengths[i] for i in ids))
-        e_pad.zero_()
-        a_pad.zero_()
-        for r, i in enumerate(ids):
-            o, T = offs[i], int(lengths[i])
+    queue = collections.deque()
+    i = 0
+    t0 = time.perf_counter()
+    while i < n_req or queue:
+        now = time.perf_counter() - t0
+        while i < n_req and float(arrivals[i]) <= now:
+            queue.append(i)
+            i += 1
+        if not queue:
+            time.sleep(max(0.0, float(arrivals[i]) - now))
+            continue
+        oldest = float(arrivals[queue[0]])
+        if len(queue) < batch and now - oldest < timeout_ms * 1e-3 and i < n_req:
+            time.sleep(max(0.0, min(float(arrivals[i]), oldest + timeout_ms * 1e-3) - now))
+            continue
+        ids = [queue.popleft() for _ in range(min(batch, len(queue)))]
+        Tb = int(max(lengths[j] for j in ids))
+        nb = len(ids)
+        e_pad[:nb, :Tb].zero_()
+        a_pad[:nb, :Tb].zero_()
+        for r, j in enumerate(ids):
+            o, T = offs[j], int(lengths[j])
             e_pad[r, :T] = e_pool[o:o + T]
             a_pad[r, :T] = a_pool[o:o + T]
-        ev = e_pad[:len(ids), :Tb].contiguous().pin_memory()
-        av = a_pad[:len(ids), :Tb].contiguous().pin_memory()
+        ed = e_pad[:nb, :Tb].to(dev, non_blocking=True)
+        ad = a_pad[:nb, :Tb].to(dev, non_blocking=True)
+        ev0.record()
+        sd, _, _ = plan.forward(ed.contiguous(), ad.contiguous(), save=False)
+        ev1.record()
+        s_pad[:nb, :Tb].copy_(sd, non_blocking=True)
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        ed = ev.to(dev, non_blocking=True)
-        ad = av.to(dev, non_blocking=True)
-        sd, _, _ = plan.forward(ed, ad, save=False)
-        s_pad[:len(ids), :Tb].copy_(sd, non_blocking=True)
-        torch.cuda.synchronize()
-        busy += time.perf_counter() - t1
-        padded += len(ids) * Tb
-    res["padded_fixed_batch"] = {"batch": batch, "samples_per_s": round(useful / busy, 1),
-                                 "padding_efficiency": round(useful / padded, 4),
-                                 "note": "busy time only (batches back to back, no arrival waits)"}
+        t_end = time.perf_counter() - t0
+        for r, j in enumerate(ids):
+            outs[j].copy_(s_pad[r, :int(lengths[j])])
+            host_lat.append(1e3 * (t_end - float(arrivals[j])))
+            dev_lat.append(ev0.elapsed_time(ev1))
+        padded += nb * Tb
+    wall = time.perf_counter() - t0
+    res["padded_fixed_batch"] = {"batch": batch, "timeout_ms": timeout_ms, "host": pct(host_lat),
+                                 "device": pct(dev_lat), "samples_per_s": round(useful / wall, 1),
+                                 "padding_efficiency": round(useful / padded, 4), "wall_s": round(wall, 3)}
+    c = res["continuous"]
+    res["p50_ms"], res["p99_ms"] = c["host"]["p50_ms"], c["host"]["p99_ms"]
     return res
 
 
@@ -579,9 +621,9 @@ def main():
     ap.add_argument("--no-sf", action="store_true", help="skip the source-filter synthesiser section")
     ap.add_argument("--frame-rate-chunk", type=int, default=0,
                     help="chunk length of the frame-rate section (default: a short sweep)")
-    ap.add_argument("--serve-requests", type=int, default=100)
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-slots", type=int, default=64)
-    ap.add_argument("--serve-batch", type=int, default=8)
+    ap.add_argument("--serve-batch", type=int, default=16)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (hardware-counter calibration)")
     args = ap.parse_args()
@@ -771,7 +813,8 @@ def main():
     serve = None
     if not args.no_serve:
         serve = serve_bench(tv, args.serve_requests, 2024, args.serve_slots, 4.0, args.serve_batch)
-        log(f"serve: p50 {serve['p50_ms']} ms, p99 {serve['p99_ms']} ms, {serve['samples_per_s'] / 1e6:.1f} M samples/s")
+        log(f"serve: p50 {serve['p50_ms']} ms, p99 {serve['p99_ms']} ms (continuous batching); padded batches "
+            f"p50 {serve['padded_fixed_batch']['host']['p50_ms']} ms, p99 {serve['padded_fixed_batch']['host']['p99_ms']} ms")
 
     out = {
         "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
