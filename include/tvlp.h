@@ -138,6 +138,27 @@ int lp_plan_status(lp_plan *p);
  * varlen use, a total of N samples in B sequences: pass T = ceil(N / B) + L). */
 int lp_plan_reserve(lp_plan *p, int64_t B, int64_t T);
 
+/*
+ * lp_forward without any device allocation, for callers that cannot allocate:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, kernels and results as lp_forward, except:
+ *   - `saved` is required (lp_saved_bytes(p, B, T) bytes, caller-owned);
+ *   - the workspace (chunk offsets, group maps and carries, the zero block the
+ *     row DMA reads) is the library's static per-device scratch of 16 MiB
+ *     (16 << 20 bytes), looked up and cleared when a plan is created on that
+ *     device, not the plan's own allocation; a call whose workspace exceeds it
+ *     returns LP_EINVAL and launches nothing (64 x 48000 samples at M = 22
+ *     need about 8.3 MB at the default chunk length, 5.4 MB at 418);
+ *   - no timing events are recorded for it.
+ * Every call on one GPU shares that GPU's scratch, which keeps the last call's
+ * contents: calls that overlap on one GPU (on different streams or threads)
+ * race and must be serialised by the caller.  No hipMalloc, hipFree or other
+ * allocating routine is called.
+ */
+int lp_forward_noalloc(lp_plan *p, int64_t B, int64_t T, const float *e, const float *a,
+                       const double *zi, float *s, double *zf, void *saved, uint32_t *nonfinite,
+                       void *stream);
+
 /* Bytes of the `saved` buffer that lp_forward fills for lp_backward: the
  * float64 chunk-entry states and chunk transition matrices (Sec. 3.2 method,
  * chunked form; the backward recomputes s(t) per chunk from them). */

@@ -49,6 +49,7 @@ SIGNATURES = {
     "lp_saved_bytes": (_SZ, [_P, _I64, _I64]),
     "lp_saved_bytes_varlen": (_SZ, [_P, _I64, _I64]),
     "lp_forward": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "lp_forward_noalloc": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P]),
     "lp_backward": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "lp_forward_ti": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P]),
     "lp_backward_ti": (_INT, [_P, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),

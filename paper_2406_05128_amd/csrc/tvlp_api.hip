@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -102,8 +103,15 @@ struct WsLayout {
 // ngf / ngb: group slots of the forward / adjoint scans; nsamp: sample slots
 // of the sequence layout (B*T, or N), for s recomputed by the adjoint;
 // fpart_bytes: the chunks' shares of a frame-rate coefficient gradient.
+// fwd_only: the forward's regions only (the adjoint's q, group maps, recomputed s
+// and frame shares get no space).
 WsLayout ws_layout(int M, int64_t nch, int64_t B, int64_t ngf, int64_t ngb, int64_t nsamp,
-                   size_t fpart_bytes = 0) {
+                   size_t fpart_bytes = 0, bool fwd_only = false) {
+    if (fwd_only) {
+        ngb = 0;
+        nsamp = 0;
+        fpart_bytes = 0;
+    }
     WsLayout w{};
     size_t off = 0;
     const size_t agg = (size_t)(M * M + M) * sizeof(double);
@@ -112,7 +120,7 @@ WsLayout ws_layout(int M, int64_t nch, int64_t B, int64_t ngf, int64_t ngb, int6
     w.xs = off;    off += align_up(bytes_state(M, nch));
     w.phi = off;   off += align_up(bytes_phi(M, nch));
     w.yend = off;  off += align_up(bytes_state(M, nch));  // adjoint: yend; forward: z of every chunk
-    w.q = off;     off += align_up(bytes_state(M, nch));
+    w.q = off;     off += fwd_only ? 0 : align_up(bytes_state(M, nch));
     w.cbase = off; off += align_up((size_t)(B + 1) * sizeof(int64_t));
     w.gbf = off;   off += align_up((size_t)(B + 1) * sizeof(int64_t));
     w.gbb = off;   off += align_up((size_t)(B + 1) * sizeof(int64_t));
@@ -151,6 +159,43 @@ int ensure_ws(lp_plan *p, size_t need, hipStream_t stream) {
     }
     p->ws = ptr;
     p->ws_bytes = need;
+    return LP_OK;
+}
+
+// ---------------------------------------------------------------- static scratch
+// The no-allocation forward (lp_forward_noalloc) takes its workspace from this
+// array instead of the plan's allocation.  Host code must not pass `scratch`
+// itself to a kernel (in host code it names a host-side stand-in): its device
+// address is looked up once per device with hipGetSymbolAddress and kept in
+// g_scratch.
+constexpr size_t kScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices];
+
+__global__ void k_zero_words(uint32_t *p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+}
+
+// Device address of this device's scratch (the current device must be `device`);
+// the first call per device looks it up and clears the zero block and status
+// word at its head (a fill kernel, then a device synchronisation).
+int scratch_of(int device, void **out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (device < 0 || device >= kMaxDevices) return fail(LP_EINVAL, "device %d beyond the scratch table", device);
+    if (!g_scratch[device]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+            return fail(LP_EDEVICE, "hipGetSymbolAddress(scratch) failed on device %d", device);
+        hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, nullptr, (uint32_t *)ptr,
+                           (int)((kStatusOffset + 256) / 4));
+        if (int r = check_hip(hipGetLastError(), "scratch clear launch")) return r;
+        if (int r = check_hip(hipDeviceSynchronize(), "scratch clear")) return r;
+        g_scratch[device] = ptr;
+    }
+    *out = g_scratch[device];
     return LP_OK;
 }
 
@@ -336,10 +381,12 @@ int check_plan(const lp_plan *p) {
 int64_t uniform_nchunks(int64_t B, int64_t T, int L) { return B * ceil_div(T, L); }
 
 // Resolves sequence tables, group counts and workspace regions for one call.
+// ws_ext: a forward-only call into this caller-provided workspace of ws_cap bytes
+// (the static scratch) instead of the plan's own.
 template <class O>
 int prepare(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, const void *saved, hipStream_t st,
             typename O::Bufs &w, const int64_t *starts = nullptr, const int64_t *lens = nullptr,
-            int64_t bound = 0, size_t fpart_bytes = 0) {
+            int64_t bound = 0, size_t fpart_bytes = 0, char *ws_ext = nullptr, size_t ws_cap = 0) {
     const int M = p->M, L = p->L;
     const int cpwf = O::FS::CPW, cpwb = O::RS::CPW;
     int64_t nch, ngf, ngb;
@@ -356,9 +403,15 @@ int prepare(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, const
         ngf = B * ceil_div(C, cpwf);
         ngb = B * ceil_div(C, cpwb);
     }
-    WsLayout lay = ws_layout(M, nch, B, ngf, ngb, tabled ? T_or_N : B * T_or_N, fpart_bytes);
-    if (int r = ensure_ws(p, lay.total, st)) return r;
-    char *ws = (char *)p->ws;
+    WsLayout lay = ws_layout(M, nch, B, ngf, ngb, tabled ? T_or_N : B * T_or_N, fpart_bytes, ws_ext != nullptr);
+    if (ws_ext) {
+        if (lay.total > ws_cap)
+            return fail(LP_EINVAL, "the call needs %zu bytes of scratch; the static scratch holds %zu", lay.total,
+                        ws_cap);
+    } else if (int r = ensure_ws(p, lay.total, st)) {
+        return r;
+    }
+    char *ws = ws_ext ? ws_ext : (char *)p->ws;
     w.nch = nch;
     w.S = Seqs{nullptr, nullptr, nullptr, nullptr, tabled ? 0 : T_or_N, B, L, tabled ? T_or_N : 0, nch, 0};
     w.gf = Groups{nullptr, ngf, cpwf};
@@ -403,7 +456,7 @@ int prepare(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, const
 int forward_impl(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, const float *e, const float *a,
                  const double *zi, float *s, double *zf, void *saved, void *stream,
                  const int64_t *starts = nullptr, const int64_t *lens = nullptr, int64_t bound = 0,
-                 bool ti = false, uint32_t *nonfinite = nullptr) {
+                 bool ti = false, bool noalloc = false, uint32_t *nonfinite = nullptr) {
     if (int r = check_plan(p)) return r;
     if (B < 1) return fail(LP_EINVAL, "B must be >= 1 (got %lld)", (long long)B);
     if (T_or_N < 1) return fail(LP_EINVAL, "T (or N) must be >= 1 (got %lld)", (long long)T_or_N);
@@ -412,11 +465,18 @@ int forward_impl(lp_plan *p, int64_t B, const int64_t *offsets, int64_t T_or_N, 
     if (!dg.ok) return fail(LP_EDEVICE, "cannot select device %d", p->device);
     hipStream_t st = (hipStream_t)stream;
     int rc = LP_OK;
-    Timer tm{p, st};
+    void *sc = nullptr;
+    if (noalloc) {
+        if (!saved) return fail(LP_EINVAL, "the no-allocation forward needs a caller-provided saved buffer");
+        if (int r = scratch_of(p->device, &sc)) return r;
+    }
+    // no timing events on the no-allocation path (event creation may allocate)
+    Timer tm{noalloc ? nullptr : p, st};
     dispatch(p->M, [&](auto ops) {
         using O = decltype(ops);
         typename O::Bufs w;
-        rc = prepare<O>(p, B, offsets, T_or_N, saved, st, w, starts, lens, bound);
+        rc = prepare<O>(p, B, offsets, T_or_N, saved, st, w, starts, lens, bound, 0, (char *)sc,
+                        noalloc ? kScratchBytes : 0);
         w.S.ti = ti ? 1 : 0;
         w.nonfinite = nonfinite;
         if (rc == LP_OK) O::forward(w, e, a, zi, s, zf, st, tm);
@@ -485,6 +545,17 @@ int lp_plan_create(lp_plan **out, int device, int M, int flags) {
     p->L = default_chunk(M);
     if (flags & LP_FLAG_HIGH_RADIUS) dispatch(M, [&](auto ops) { p->L = decltype(ops)::max_chunk(); });
     p->flags = flags;
+    {
+        // the static scratch of the plan's device is looked up (and cleared) here,
+        // ahead of any capture a caller of lp_forward_noalloc may start later
+        DeviceGuard dg(device);
+        void *sc = nullptr;
+        const int r = dg.ok ? scratch_of(device, &sc) : fail(LP_EDEVICE, "cannot select device %d", device);
+        if (r != LP_OK) {
+            delete p;
+            return r;
+        }
+    }
     *out = p;
     return LP_OK;
 }
@@ -604,7 +675,14 @@ size_t lp_saved_bytes_varlen(const lp_plan *p, int64_t B, int64_t N) {
 
 int lp_forward(lp_plan *p, int64_t B, int64_t T, const float *e, const float *a, const double *zi, float *s,
                double *zf, void *saved, uint32_t *nonfinite, void *stream) {
-    return forward_impl(p, B, nullptr, T, e, a, zi, s, zf, saved, stream, nullptr, nullptr, 0, false, nonfinite);
+    return forward_impl(p, B, nullptr, T, e, a, zi, s, zf, saved, stream, nullptr, nullptr, 0, false, false,
+                        nonfinite);
+}
+
+int lp_forward_noalloc(lp_plan *p, int64_t B, int64_t T, const float *e, const float *a, const double *zi, float *s,
+                       double *zf, void *saved, uint32_t *nonfinite, void *stream) {
+    return forward_impl(p, B, nullptr, T, e, a, zi, s, zf, saved, stream, nullptr, nullptr, 0, false, true,
+                        nonfinite);
 }
 
 int lp_backward(lp_plan *p, int64_t B, int64_t T, const float *g, const float *a, const float *e, const double *zi,

@@ -50,6 +50,7 @@ def test_null_plan_and_bad_sizes_are_errors():
     lib = _lib.load()
     assert lib.lp_saved_bytes(None, 4, 100) == 0
     assert lib.lp_forward(None, 1, 1, None, None, None, None, None, None, None, None) == _lib.LP_EINVAL
+    assert lib.lp_forward_noalloc(None, 1, 1, None, None, None, None, None, None, None, None) == _lib.LP_EINVAL
     assert lib.lp_backward(None, 1, 1, None, None, None, None, None, None, None, None, None, None,
                            None) == _lib.LP_EINVAL
     assert lib.lp_forward_plain(0, 1, 1, None, None, None, None, None, None) == _lib.LP_EINVAL
