@@ -548,9 +548,10 @@ def framewise_bench(tv, sets, B: int, T: int, M: int, steps: int, warmup: int, m
 def stress_bench(tv, steps: int):
     """Long high-resonance workload (512 x 240000, M = 32, |k| <= 0.995, gamma 0.995).
 
-    Chained carry over 2048-sample chunks (the accurate configuration for these
-    inputs); reports fwd+adjoint throughput, the error against the float64
-    oracle on 8 sampled sequences, and the autotuner's speed-optimal chunk.
+    A plan made for high pole radii (LP_FLAG_HIGH_RADIUS: chained carry, chunk
+    length autotuned among the lengths long enough for its accuracy); reports
+    fwd+adjoint throughput at the autotuned chunk, and the error against the
+    float64 oracle of each of 8 sampled sequences.
     """
     import numpy as np
     import torch
@@ -563,8 +564,8 @@ def stress_bench(tv, steps: int):
     dev = torch.device("cuda", 0)
     log(f"stress: building inputs B={B} T={T} M={M} on the device")
     e, a, g = stress_inputs(B, T, M, wl.kappa, 0.995, wl.seed, dev)
-    plan = tv.Plan(M, dev, 2048, chained=True)
-    tune = tv.Plan(M, dev, chained=True).autotune(B, T, reps=2, cache=False)
+    plan = tv.Plan(M, dev, high_radius=True)
+    tune = plan.autotune(B, T, reps=2, cache=False)
     saved = torch.empty(plan.saved_bytes(B, T), dtype=torch.uint8, device=dev)
     s = torch.empty_like(e)
 
@@ -584,21 +585,90 @@ def stress_bench(tv, steps: int):
     plan.check_status()
     ms = t0.elapsed_time(t1) / steps
     picks = np.random.default_rng(wl.seed).choice(B, 8, replace=False)
-    worst = {}
+    per_seq = []
     for b in picks:
         eb, ab, gb = (x[b:b + 1].cpu().numpy() for x in (e, a, g))
         s_ref, _ = oracle.lp_forward(eb, ab)
         ge_ref, ga_ref, _ = oracle.lp_backward(gb, ab, s_ref)
+        errs = {}
         for k, x, r in (("s", s[b], s_ref[0]), ("grad_e", ge[b], ge_ref[0]), ("grad_a", ga[b], ga_ref[0])):
             x = x.cpu().numpy().astype(np.float64)
-            err = float(np.sqrt(np.mean((x - r) ** 2)) / max(np.sqrt(np.mean(r ** 2)), 1e-300))
-            worst[k] = max(worst.get(k, 0.0), err)
-    log(f"stress: {ms:.2f} ms/step, worst rms-rel {worst}")
-    return {"workload": wl.name, "carry": "chained", "chunk": 2048, "ms_per_step": round(ms, 3),
+            errs[k] = float(f"{np.sqrt(np.mean((x - r) ** 2)) / max(np.sqrt(np.mean(r ** 2)), 1e-300):.3g}")
+        per_seq.append({"sequence": int(b), **errs})
+    worst = {k: max(p[k] for p in per_seq) for k in ("s", "grad_e", "grad_a")}
+    log(f"stress: {ms:.2f} ms/step at L={plan.chunk}, worst rms-rel {worst}")
+    return {"workload": wl.name, "plan": "high_radius (chained carry)", "chunk": plan.chunk,
+            "chunk_source": "autotuner (lengths >= 1536)", "ms_per_step": round(ms, 3),
             "samples_per_s": B * T / (ms * 1e-3),
-            "error_8_sampled_sequences_rms_rel": {k: float(f"{v:.3g}") for k, v in worst.items()},
-            "autotuned_chunk": tune["chunk"], "autotuned_ms": round(tune["ms"], 3),
-            "note": "autotuned chunk optimises speed only; 2048 is used for accuracy on these inputs"}
+            "autotune_timed": f"{min(B, (1 << 25) // T)} x {T} samples, best {tune['ms']:.3f} ms",
+            "error_rms_rel_worst": worst, "error_rms_rel_per_sequence": per_seq}
+
+
+def pair_bench(tv, steps: int, warmup: int):
+    """Harmonic-plus-noise filter pair (Eq. 1): two LP filters per item, H on a
+    pulse train and C on noise, B = 32 items of T = 96000 samples, M = 22, one
+    upstream gradient dL/dy for y = s_H + s_C.  One step (forward of both
+    filters, their sum, recompute adjoint of both) is captured once in a hipGraph
+    and replayed; samples/s counts 2 B T filtered samples per step.  Per-kernel
+    durations come from an eager run of the same step with per-launch events."""
+    import numpy as np
+    import torch
+    from synth import WORKLOADS, draw_reflection_frames, make_excitation, make_upstream_grad, pulse_train
+    from synth.device import coeffs_from_frames
+
+    wl = WORKLOADS["hpn_pair_b32_t96000_m22"]
+    B, T, M = wl.B, wl.T, wl.M
+    dev = torch.device("cuda", 0)
+    rng = np.random.default_rng(wl.seed)
+    log(f"pair: building inputs B={B} T={T} M={M} (two coefficient draws, pulse train and noise)")
+    a2 = torch.empty((2, B, T, M), dtype=torch.float32, device=dev)
+    for f in range(2):
+        a2[f].copy_(coeffs_from_frames(draw_reflection_frames(rng, B, T, M, wl.kappa, wl.family), T, 1.0, dev))
+    e2d = torch.from_numpy(np.stack([pulse_train(rng, B, T), make_excitation(rng, B, T)])).to(dev)
+    gd = torch.from_numpy(make_upstream_grad(rng, B, T)).to(dev)
+    plan = tv.Plan(M, dev)
+    # the pair runs as 2B sequences through one plan: tune for that shape
+    plan.autotune(2 * B, T, reps=2, cache=False)
+    L = plan.chunk
+    y = torch.empty((B, T), dtype=torch.float32, device=dev)
+    s2 = torch.empty_like(e2d)
+    saved = torch.empty(plan.saved_bytes_pair(B, T), dtype=torch.uint8, device=dev)
+    ge2 = torch.empty_like(e2d)
+    ga2 = torch.empty_like(a2)
+    graph = tv.PairStepGraph(plan, e2d, a2, y, s2, saved, gd, ge2, ga2)
+    for _ in range(warmup):
+        graph.launch()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(steps):
+        graph.launch()
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    graph.close()
+    # per-kernel durations from the eager step (events on the launch stream)
+    plan.set_timing(True)
+    plan.reset_timings()
+    for _ in range(steps):
+        plan.forward_pair(e2d, a2, y=y, s2=s2, saved=saved)
+        plan.backward_pair(gd, a2, e2d, saved)
+    torch.cuda.synchronize()
+    tims = plan.timings()
+    plan.set_timing(False)
+    n = 2 * B * T
+    kernels = {name: {"avg_us": round(1e3 * tms / max(cnt, 1), 2), "launches": cnt}
+               for name, (tms, cnt) in tims.items()}
+    # per filtered sample: e, a read forward and again by the adjoint, grad_e, grad_a
+    # written (3M+3 words); y written and g read once per item, shared by its two
+    # filters (1 word per filtered sample)
+    alg = float(n * 4 * (3 * M + 4))
+    log(f"pair: {ms:.3f} ms/step (graph replay), {n / (ms * 1e-3) / 1e9:.2f} G filtered samples/s")
+    return {"workload": wl.name, "chunk": L, "chunk_source": "autotuner (2B x T)", "ms_per_step": round(ms, 4),
+            "samples_per_s": n / (ms * 1e-3), "filtered_samples_per_step": n,
+            "algorithmic_bytes_per_step": alg, "step_hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "launch": "hipGraph replay of forward + sum + recompute adjoint", "kernels_eager": kernels}
 
 
 def main():
@@ -619,6 +689,7 @@ def main():
     ap.add_argument("--no-framewise", action="store_true", help="skip the frame-wise approximation section")
     ap.add_argument("--no-frame-rate", action="store_true", help="skip the frame-rate coefficient section")
     ap.add_argument("--no-sf", action="store_true", help="skip the source-filter synthesiser section")
+    ap.add_argument("--no-pair", action="store_true", help="skip the harmonic-plus-noise filter pair section")
     ap.add_argument("--frame-rate-chunk", type=int, default=0,
                     help="chunk length of the frame-rate section (default: a short sweep)")
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -810,6 +881,12 @@ def main():
         stress = stress_bench(tv, 3)
         torch.cuda.empty_cache()
 
+    pair = None
+    if not args.no_pair:
+        log("harmonic-plus-noise filter pair (B=32, T=96000, graph replay)")
+        pair = pair_bench(tv, args.steps, args.warmup)
+        torch.cuda.empty_cache()
+
     serve = None
     if not args.no_serve:
         serve = serve_bench(tv, args.serve_requests, 2024, args.serve_slots, 4.0, args.serve_batch)
@@ -831,6 +908,7 @@ def main():
         "cpu_baseline": cpu,
         "serve": serve,
         "stress": stress,
+        "pair": pair,
         "time_invariant": ti,
         "frame_rate": frame_rate,
         "sf_synth": sf,
