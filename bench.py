@@ -734,7 +734,8 @@ def main():
     if args.chunk is None:
         # chunk length picked by the autotuner (fresh measurement, not the cache)
         tune = plan.autotune(B, T, reps=3, cache=False)
-        log(f"autotuned chunk L={tune['chunk']} ({tune['ms']:.3f} ms/step on zero inputs)")
+        log(f"autotuned chunk L={tune['chunk']}, {'chained' if tune['chained'] else 'grouped'} carry "
+            f"({tune['ms']:.3f} ms/step on zero inputs)")
     L = plan.chunk
     plan.reserve(B, T)
     saved = [torch.empty(plan.saved_bytes(B, T), dtype=torch.uint8, device=dev) for _ in sets]
@@ -898,6 +899,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32 io, f64 arithmetic", "data": "synthetic",
         "config": {"workload": wl.name, "B": B, "T": T, "M": M, "chunk": L,
+                   "carry": "chained" if plan.chained else "group maps",
                    "chunk_source": "autotuner" if tune else "--chunk",
                    "inputs": f"reflection-coefficient tracks, 240-sample hop, gamma={args.gamma}",
                    "backward": "recompute s per chunk from saved float64 chunk states"},

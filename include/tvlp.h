@@ -109,14 +109,27 @@ int lp_plan_destroy(lp_plan *p);
 int lp_plan_set_chunk(lp_plan *p, int L);
 int lp_plan_get_chunk(const lp_plan *p);
 
-/* Chunk-length autotuner: times one forward + recompute-adjoint step of a
- * B x T batch (B capped so that the timed batch holds about 32 M samples) for
- * candidate chunk lengths near 64 .. 1024 samples (multiples of M), `reps`
- * timed repetitions each after one warm-up, and keeps the fastest on the plan.
- * Allocates and frees its own zero-filled buffers (timing does not depend on
- * the values) and synchronises the device.  Writes the chosen L and its best
- * step time in ms (either pointer may be NULL).  On error the plan keeps its
- * previous chunk length. */
+/* Carry mode: 1 for the chained carry (LP_FLAG_CHAINED_CARRY), 0 for group
+ * maps.  Setting 0 or 1 fixes the mode for the autotuner; -1 keeps the current
+ * mode and leaves the choice to the autotuner again.  A high-radius plan
+ * accepts only 1; other values give LP_EINVAL.  Both modes use the same
+ * workspace and saved state, so a forward and its adjoint may run in
+ * different modes.  lp_plan_get_carry returns -1 for a NULL plan. */
+int lp_plan_set_carry(lp_plan *p, int mode);
+int lp_plan_get_carry(const lp_plan *p);
+
+/* Chunk-length autotuner (the launch mapping: chunk length L, hence the
+ * number of chunks and of waves per sequence, and the carry mode): times one
+ * forward + recompute-adjoint step of a B x T batch (B capped so that the
+ * timed batch holds about 32 M samples) for candidate chunk lengths near
+ * 64 .. 1024 samples (multiples of M) and, unless the caller fixed the carry
+ * mode (a carry flag at creation, or lp_plan_set_carry), both carry modes;
+ * `reps` timed repetitions each after one warm-up; keeps the fastest on the
+ * plan.  Allocates and frees its own zero-filled buffers (timing does not
+ * depend on the values) and synchronises the device.  Writes the chosen L and
+ * its best step time in ms (either pointer may be NULL; the carry mode is read
+ * back with lp_plan_get_carry).  On error the plan keeps its previous chunk
+ * length and carry mode. */
 int lp_plan_autotune(lp_plan *p, int64_t B, int64_t T, int reps, int *chosen, double *best_ms);
 
 /* Per-kernel timing.  When on, every kernel the plan launches is bracketed by

@@ -40,6 +40,8 @@ SIGNATURES = {
     "lp_plan_destroy": (_INT, [_P]),
     "lp_plan_set_chunk": (_INT, [_P, _INT]),
     "lp_plan_get_chunk": (_INT, [_P]),
+    "lp_plan_set_carry": (_INT, [_P, _INT]),
+    "lp_plan_get_carry": (_INT, [_P]),
     "lp_plan_reserve": (_INT, [_P, _I64, _I64]),
     "lp_plan_autotune": (_INT, [_P, _I64, _I64, _INT, _P, _P]),
     "lp_plan_set_timing": (_INT, [_P, _INT]),

@@ -1,6 +1,7 @@
 """Persistent cache of chunk lengths chosen by the native autotuner (lp_plan_autotune).
 
-One JSON object per file: {"<device>|M=<M>|B=<B>|T=<T>": {"chunk": L, "ms": t}}.
+One JSON object per file: {"<device>|M=<M>|B=<B>|T=<T>[|carry=<constraint>]":
+{"chunk": L, "chained": bool, "ms": t}}.
 Writes go through a temporary file and an atomic rename.
 """
 from __future__ import annotations
@@ -33,7 +34,7 @@ def _read(path: str) -> dict:
 def lookup(key: str) -> Optional[dict]:
     hit = _read(cache_path()).get(key)
     if isinstance(hit, dict) and isinstance(hit.get("chunk"), int) and hit["chunk"] > 0:
-        return {"chunk": hit["chunk"], "ms": float(hit.get("ms", 0.0))}
+        return {"chunk": hit["chunk"], "chained": bool(hit.get("chained", False)), "ms": float(hit.get("ms", 0.0))}
     return None
 
 
@@ -41,7 +42,8 @@ def store(key: str, value: dict) -> None:
     path = cache_path()
     os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
     data = _read(path)
-    data[key] = {"chunk": int(value["chunk"]), "ms": float(value["ms"])}
+    data[key] = {"chunk": int(value["chunk"]), "chained": bool(value.get("chained", False)),
+                 "ms": float(value["ms"])}
     fd, tmp = tempfile.mkstemp(dir=os.path.dirname(path) or ".", suffix=".tmp")
     with os.fdopen(fd, "w") as f:
         json.dump(data, f, indent=1, sort_keys=True)

@@ -545,6 +545,7 @@ int lp_plan_create(lp_plan **out, int device, int M, int flags) {
     p->L = default_chunk(M);
     if (flags & LP_FLAG_HIGH_RADIUS) dispatch(M, [&](auto ops) { p->L = decltype(ops)::max_chunk(); });
     p->flags = flags;
+    p->carry_fixed = (flags & LP_FLAG_CHAINED_CARRY) != 0;
     {
         // the static scratch of the plan's device is looked up (and cleared) here,
         // ahead of any capture a caller of lp_forward_noalloc may start later
@@ -591,6 +592,24 @@ int lp_plan_set_chunk(lp_plan *p, int L) {
 }
 
 int lp_plan_get_chunk(const lp_plan *p) { return p ? p->L : 0; }
+
+int lp_plan_set_carry(lp_plan *p, int mode) {
+    if (int r = check_plan(p)) return r;
+    if (mode < -1 || mode > 1) return fail(LP_EINVAL, "carry mode must be -1, 0 or 1 (got %d)", mode);
+    if (p->flags & LP_FLAG_HIGH_RADIUS) {
+        if (mode != 1) return fail(LP_EINVAL, "a high-radius plan keeps the chained carry");
+        return LP_OK;
+    }
+    if (mode < 0) {  // release: the autotuner chooses again
+        p->carry_fixed = false;
+        return LP_OK;
+    }
+    p->flags = mode ? (p->flags | LP_FLAG_CHAINED_CARRY) : (p->flags & ~LP_FLAG_CHAINED_CARRY);
+    p->carry_fixed = true;
+    return LP_OK;
+}
+
+int lp_plan_get_carry(const lp_plan *p) { return p ? ((p->flags & LP_FLAG_CHAINED_CARRY) ? 1 : 0) : -1; }
 
 int lp_plan_set_timing(lp_plan *p, int on) {
     if (int r = check_plan(p)) return r;
@@ -862,11 +881,18 @@ int lp_plan_autotune(lp_plan *p, int64_t B, int64_t T, int reps, int *chosen, do
         rc = fail(LP_EDEVICE, "autotune stream/event creation failed");
     const bool timing = p->timing;
     p->timing = false;
-    int bestL = oldL;
+    // carry modes: both unless the caller fixed one
+    const int oldflags = p->flags;
+    const int chained_now = (p->flags & LP_FLAG_CHAINED_CARRY) ? 1 : 0;
+    const int modes[2] = {p->carry_fixed ? chained_now : 0, 1};
+    const int nmodes = p->carry_fixed ? 1 : 2;
+    int bestL = oldL, best_mode = chained_now;
     float best = 1e30f;
-    for (int L : cands) {
+    for (int mi = 0; mi < nmodes * (int)cands.size(); ++mi) {
         if (rc != LP_OK) break;
+        const int L = cands[mi % cands.size()], mode = modes[mi / cands.size()];
         p->L = L;
+        p->flags = mode ? (oldflags | LP_FLAG_CHAINED_CARRY) : (oldflags & ~LP_FLAG_CHAINED_CARRY);
         float bestL_ms = 1e30f;
         for (int r = 0; r <= reps && rc == LP_OK; ++r) {  // r = 0 warms up (and sizes the workspace)
             (void)hipEventRecord(e0, st);
@@ -880,10 +906,13 @@ int lp_plan_autotune(lp_plan *p, int64_t B, int64_t T, int reps, int *chosen, do
         if (rc == LP_OK && bestL_ms < best) {
             best = bestL_ms;
             bestL = L;
+            best_mode = mode;
         }
     }
     p->timing = timing;
     p->L = rc == LP_OK ? bestL : oldL;
+    p->flags = rc == LP_OK ? (best_mode ? (oldflags | LP_FLAG_CHAINED_CARRY) : (oldflags & ~LP_FLAG_CHAINED_CARRY))
+                           : oldflags;
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     if (st) (void)hipStreamDestroy(st);

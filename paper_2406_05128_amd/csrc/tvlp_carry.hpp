@@ -17,28 +17,41 @@
 //
 // Matrices are staged through LDS in batches by several waves with many loads
 // in flight; in the chain kernels three waves stage the next batch while the
-// first wave runs the current one.  The carried vector lives in LDS and every
-// matrix row is one lane's dot product.
+// first wave runs the current one.  The carried vector lives in the first
+// wave's registers, one entry per lane; every matrix row is one lane's dot
+// product.
 #pragma once
 
 #include "tvlp_scan.hpp"
 
 namespace tvlp {
 
-// Orders this wave's memory operations for the compiler (a wavefront-scope
-// fence, so values other lanes wrote to LDS are read again, not reused) and
-// keeps the scheduler from moving instructions across.  LDS operations of one
-// wave are executed in order, so no hardware wait is needed between lanes.
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
 // Copies n doubles from global to LDS; thread t of nt cooperating threads.
 // Sixteen loads per thread are issued before their LDS writes, so a batch pays
-// about one memory latency per sixteen rounds instead of one per element.
+// about one memory latency per sixteen rounds instead of one per element; with
+// both addresses 16-byte aligned each load moves two doubles.
 __device__ __forceinline__ void stage_doubles(double *dst, const double *__restrict__ src, int64_t n, int t, int nt) {
     constexpr int U = 16;
+    if (((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15) == 0) {
+        const int64_t n2 = n >> 1;
+        const double2 *s2 = reinterpret_cast<const double2 *>(src);
+        double2 *d2 = reinterpret_cast<double2 *>(dst);
+        for (int64_t q0 = t; q0 < n2; q0 += (int64_t)U * nt) {
+            double2 r[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t q = q0 + (int64_t)u * nt;
+                r[u] = q < n2 ? s2[q] : double2{0.0, 0.0};
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t q = q0 + (int64_t)u * nt;
+                if (q < n2) d2[q] = r[u];
+            }
+        }
+        if ((n & 1) && t == 0) dst[n - 1] = src[n - 1];
+        return;
+    }
     for (int64_t q0 = t; q0 < n; q0 += (int64_t)U * nt) {
         double r[U];
 #pragma unroll
@@ -54,38 +67,42 @@ __device__ __forceinline__ void stage_doubles(double *dst, const double *__restr
     }
 }
 
-// v <- A v + z for the M-vector v in LDS; A[i][j] = A_[i * si + j * sj] in LDS,
-// z held by lane i.  One wave; lane i < M computes row i; every lane's reads
-// of v precede the write of the new v.
+// x_j held by lane j, as a wave-uniform value (two scalar lane reads).
+__device__ __forceinline__ double lane_value(double x, int j) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, j);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), j);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// One step of a carry, x <- A x + z, for the M-vector x held one entry per
+// lane (lane i < M holds x_i and z_i); A[i][j] = A_[i * si + j * sj] in LDS.
+// Lane i reads its row of A (independent of x, so the reads are in flight
+// while x is broadcast), takes every x_j from lane j by a scalar read, and
+// forms its dot product.  Returns the new x_i (lanes >= M: a dummy value).
 template <int M>
-__device__ __forceinline__ void lds_step(const double *A_, int si, int sj, double *v, double z, int lane) {
+__device__ __forceinline__ double reg_step(const double *A_, int si, int sj, double x, double z, int lane) {
     const int i = lane < M ? lane : 0;
+    double r[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) r[j] = A_[i * si + j * sj];
     double acc0 = z, acc1 = 0.0;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-        const double aij = A_[i * si + j * sj];
+        const double xj = lane_value(x, j);
         if (j & 1)
-            acc1 = fma(aij, v[j], acc1);
+            acc1 = fma(r[j], xj, acc1);
         else
-            acc0 = fma(aij, v[j], acc0);
+            acc0 = fma(r[j], xj, acc0);
     }
-    wave_sync();
-    if (lane < M) v[lane] = acc0 + acc1;
-    wave_sync();
-}
-
-// v <- z (lane i < M holds z_i).
-template <int M>
-__device__ __forceinline__ void lds_set(double *v, double z, int lane) {
-    wave_sync();
-    if (lane < M) v[lane] = z;
-    wave_sync();
+    return acc0 + acc1;
 }
 
 template <int M>
 struct CarryShape {
     static constexpr int MM = M * M;
-    static constexpr int THREADS = 256;         // chain and expand kernels: four waves
+    static constexpr int THREADS = 256;         // expand kernels: four waves
+    static constexpr int CHAIN_THREADS = 512;   // chain kernels: one wave computes, seven stage
     static constexpr int BUF_DOUBLES = 8000;    // one chain-kernel staging buffer (62.5 KiB)
     // matrices (each with its offset vector) per chain-kernel batch
     static constexpr int NB = BUF_DOUBLES / (MM + M) > 0 ? BUF_DOUBLES / (MM + M) : 1;
@@ -97,7 +114,7 @@ struct CarryShape {
 // grouped: items are groups (map with its offset; output ginc per group).
 // The last item has no map.
 template <int M>
-__global__ __launch_bounds__(256) void k_fwd_chain(Seqs S, Groups GR, const double *__restrict__ zi,
+__global__ __launch_bounds__(512) void k_fwd_chain(Seqs S, Groups GR, const double *__restrict__ zi,
                                                    const double *__restrict__ phiT,
                                                    const double *__restrict__ zbuf,
                                                    const double *__restrict__ aggbuf, double *__restrict__ ginc,
@@ -105,8 +122,7 @@ __global__ __launch_bounds__(256) void k_fwd_chain(Seqs S, Groups GR, const doub
                                                    uint32_t *__restrict__ nonfinite) {
     using CS = CarryShape<M>;
     constexpr int MM = M * M;
-    __shared__ double lds[2 * CS::BUF_DOUBLES + M];
-    double *v = lds + 2 * CS::BUF_DOUBLES;
+    __shared__ __attribute__((aligned(16))) double lds[2 * CS::BUF_DOUBLES];
     const int64_t b = blockIdx.x;
     if (nonfinite && threadIdx.x == 0) nonfinite[b] = 0u;  // the forward emit sets it
     const SeqView sv = seq_view(S, b);
@@ -127,8 +143,8 @@ __global__ __launch_bounds__(256) void k_fwd_chain(Seqs S, Groups GR, const doub
             stage_doubles(buf, aggbuf + (id0 + k0) * (MM + M), nm * (MM + M), t, nt);
         }
     };
-    if (wv == 0 && lane < M) v[lane] = zi ? zi[b * M + lane] : 0.0;
-    stage(0, tid, CS::THREADS);
+    double x = (wv == 0 && lane < M && zi) ? zi[b * M + lane] : 0.0;
+    stage(0, tid, CS::CHAIN_THREADS);
     __syncthreads();
     for (int64_t bi = 0; bi < nbatch; ++bi) {
         if (wv == 0) {
@@ -136,15 +152,15 @@ __global__ __launch_bounds__(256) void k_fwd_chain(Seqs S, Groups GR, const doub
             const int64_t k0 = bi * CS::NB;
             const int nb = (int)min((int64_t)CS::NB, n - k0);
             for (int k = 0; k < nb; ++k) {
-                if (lane < M) out[(id0 + k0 + k) * M + lane] = v[lane];
+                if (lane < M) out[(id0 + k0 + k) * M + lane] = x;
                 if (k0 + k + 1 < n) {
                     const double *A = chain ? buf + k * MM : buf + k * (MM + M);
                     const double *z = chain ? buf + CS::NB * MM + k * M : A + MM;
-                    lds_step<M>(A, 1, M, v, lane < M ? z[lane] : 0.0, lane);
+                    x = reg_step<M>(A, 1, M, x, z[lane < M ? lane : 0], lane);
                 }
             }
         } else if (bi + 1 < nbatch) {
-            stage(bi + 1, tid - 64, CS::THREADS - 64);
+            stage(bi + 1, tid - 64, CS::CHAIN_THREADS - 64);
         }
         __syncthreads();
     }
@@ -157,15 +173,14 @@ __global__ __launch_bounds__(256) void k_fwd_chain(Seqs S, Groups GR, const doub
 // map with its offset; output ginc per group; group 0 has no map).  Items are
 // visited from the last one down.
 template <int M>
-__global__ __launch_bounds__(256) void k_bwd_chain(Seqs S, Groups GR, const double *__restrict__ phiT,
+__global__ __launch_bounds__(512) void k_bwd_chain(Seqs S, Groups GR, const double *__restrict__ phiT,
                                                    const double *__restrict__ qbuf,
                                                    const double *__restrict__ aggbuf, double *__restrict__ ginc,
                                                    double *__restrict__ yend, double *__restrict__ grad_zi,
                                                    int chain, uint32_t *__restrict__ nonfinite) {
     using CS = CarryShape<M>;
     constexpr int MM = M * M;
-    __shared__ double lds[2 * CS::BUF_DOUBLES + M];
-    double *v = lds + 2 * CS::BUF_DOUBLES;
+    __shared__ __attribute__((aligned(16))) double lds[2 * CS::BUF_DOUBLES];
     const int64_t b = blockIdx.x;
     if (nonfinite && threadIdx.x == 0) nonfinite[b] = 0u;  // the adjoint emit sets it
     const SeqView sv = seq_view(S, b);
@@ -196,8 +211,8 @@ __global__ __launch_bounds__(256) void k_bwd_chain(Seqs S, Groups GR, const doub
             stage_doubles(buf, aggbuf + (id0 + k0) * (MM + M), (int64_t)nb * (MM + M), t, nt);
         }
     };
-    if (wv == 0 && lane < M) v[lane] = 0.0;
-    stage(0, tid, CS::THREADS);
+    double x = 0.0;
+    stage(0, tid, CS::CHAIN_THREADS);
     __syncthreads();
     for (int64_t bi = 0; bi < nbatch; ++bi) {
         if (wv == 0) {
@@ -207,21 +222,21 @@ __global__ __launch_bounds__(256) void k_bwd_chain(Seqs S, Groups GR, const doub
             range(bi, k0, nb);
             for (int k = nb - 1; k >= 0; --k) {
                 const int64_t item = k0 + k;
-                if (lane < M) out[(id0 + item) * M + lane] = v[lane];
+                if (lane < M) out[(id0 + item) * M + lane] = x;
                 if (chain) {
-                    const double q = lane < M ? buf[CS::NB * MM + k * M + lane] : 0.0;
+                    const double q = buf[CS::NB * MM + k * M + (lane < M ? lane : 0)];
                     if (item == n - 1)
-                        lds_set<M>(v, q, lane);
+                        x = q;
                     else
-                        lds_step<M>(buf + k * MM, M, 1, v, q, lane);
+                        x = reg_step<M>(buf + k * MM, M, 1, x, q, lane);
                 } else if (item > 0) {
                     const double *A = buf + k * (MM + M);
-                    lds_step<M>(A, M, 1, v, lane < M ? A[MM + lane] : 0.0, lane);
+                    x = reg_step<M>(A, M, 1, x, A[MM + (lane < M ? lane : 0)], lane);
                 }
             }
-            if (chain && bi + 1 == nbatch && grad_zi && lane < M) grad_zi[b * M + lane] = v[lane];
+            if (chain && bi + 1 == nbatch && grad_zi && lane < M) grad_zi[b * M + lane] = x;
         } else if (bi + 1 < nbatch) {
-            stage(bi + 1, tid - 64, CS::THREADS - 64);
+            stage(bi + 1, tid - 64, CS::CHAIN_THREADS - 64);
         }
         __syncthreads();
     }
@@ -233,8 +248,7 @@ __global__ __launch_bounds__(256) void k_bwd_expand(Seqs S, Groups GR, const dou
                                                     const double *__restrict__ ginc, double *__restrict__ yend,
                                                     double *__restrict__ grad_zi) {
     constexpr int MM = M * M;
-    __shared__ double lds[CPW * (MM + M) + M];
-    double *v = lds + CPW * (MM + M);
+    __shared__ __attribute__((aligned(16))) double lds[CPW * (MM + M)];
     const int64_t gid = blockIdx.x;
     if (gid >= GR.ngroups) return;
     int64_t b, g;
@@ -247,20 +261,20 @@ __global__ __launch_bounds__(256) void k_bwd_expand(Seqs S, Groups GR, const dou
     const bool need_first = (g == 0) && grad_zi;  // y(0) is dL/dzi
     stage_doubles(lds, phiT + (sv.cbase + c0) * MM, (int64_t)nk * MM, tid, blockDim.x);
     stage_doubles(lds + CPW * MM, qbuf + (sv.cbase + c0) * M, (int64_t)nk * M, tid, blockDim.x);
-    if (tid < M) v[tid] = ginc[gid * M + tid];
+    double x = (tid < M) ? ginc[gid * M + tid] : 0.0;
     __syncthreads();
     if (tid >= 64) return;
     for (int k = nk - 1; k >= 0; --k) {
         const int64_t c = c0 + k;
-        if (lane < M) yend[(sv.cbase + c) * M + lane] = v[lane];
+        if (lane < M) yend[(sv.cbase + c) * M + lane] = x;
         if (k == 0 && !need_first) break;  // y at the group start is not needed
-        const double q = lane < M ? lds[CPW * MM + k * M + lane] : 0.0;
+        const double q = lds[CPW * MM + k * M + (lane < M ? lane : 0)];
         if (c == sv.C - 1)  // the sequence's last chunk: y = q
-            lds_set<M>(v, q, lane);
+            x = q;
         else
-            lds_step<M>(lds + k * MM, M, 1, v, q, lane);
+            x = reg_step<M>(lds + k * MM, M, 1, x, q, lane);
     }
-    if (need_first && lane < M) grad_zi[b * M + lane] = v[lane];
+    if (need_first && lane < M) grad_zi[b * M + lane] = x;
 }
 
 // ---------------------------------------------------------------- fused forward carry (grouped mode)
@@ -293,8 +307,7 @@ __global__ __launch_bounds__(256) void k_fwd_carry(Seqs S, Groups GR, const doub
     using FS = FusedCarryShape<M, CPW>;
     constexpr int MM = M * M;
     static_assert(CPW <= FS::NBM, "a group's transitions must fit one staged batch");
-    __shared__ double lds[FS::BUF + M];
-    double *v = lds + FS::BUF;
+    __shared__ __attribute__((aligned(16))) double lds[FS::BUF];
     const int64_t gid = blockIdx.x;
     // the forward emit sets the flags; block gid clears sequence gid's (every
     // launch has at least one group slot per sequence)
@@ -306,7 +319,7 @@ __global__ __launch_bounds__(256) void k_fwd_carry(Seqs S, Groups GR, const doub
     if (g >= groups_of(sv.C, CPW)) return;
     const int tid = threadIdx.x, lane = tid & 63;
     const int64_t gid0 = group_id(S, GR, b, 0);
-    if (tid < M) v[tid] = zi ? zi[b * M + tid] : 0.0;
+    double x = (tid < M && zi) ? zi[b * M + tid] : 0.0;
     // x(g) = P_{g-1} ... P_0 zi + ... : the maps of the groups before g, in batches
     for (int64_t k0 = 0; k0 < g; k0 += FS::NBM) {
         const int nb = (int)min((int64_t)FS::NBM, g - k0);
@@ -316,7 +329,7 @@ __global__ __launch_bounds__(256) void k_fwd_carry(Seqs S, Groups GR, const doub
         if (tid < 64) {
             for (int k = 0; k < nb; ++k) {
                 const double *A = lds + k * (MM + M);  // column-major map, then its offset
-                lds_step<M>(A, 1, M, v, lane < M ? A[MM + lane] : 0.0, lane);
+                x = reg_step<M>(A, 1, M, x, A[MM + (lane < M ? lane : 0)], lane);
             }
         }
     }
@@ -330,8 +343,8 @@ __global__ __launch_bounds__(256) void k_fwd_carry(Seqs S, Groups GR, const doub
     __syncthreads();
     if (tid >= 64) return;
     for (int k = 0; k < nk; ++k) {
-        if (lane < M) xs[(sv.cbase + c0 + k) * M + lane] = v[lane];
-        if (k < nt) lds_step<M>(lds + k * MM, 1, M, v, lane < M ? lds[FS::NBM * MM + k * M + lane] : 0.0, lane);
+        if (lane < M) xs[(sv.cbase + c0 + k) * M + lane] = x;
+        if (k < nt) x = reg_step<M>(lds + k * MM, 1, M, x, lds[FS::NBM * MM + k * M + (lane < M ? lane : 0)], lane);
     }
 }
 

@@ -26,6 +26,9 @@ struct lp_plan {
     int M;
     int L;
     int flags;
+    // the carry mode was fixed by the caller (a flag at creation or
+    // lp_plan_set_carry): the autotuner keeps it
+    bool carry_fixed;
     void *ws;
     size_t ws_bytes;
     bool timing;

@@ -38,7 +38,7 @@ void Ops<M>::forward_t(const Bufs &w, const float *e, const float *a, const doub
     tm.begin("fwd_carry");
     const dim3 ct(CarryShape<M>::THREADS);
     if (chain)
-        hipLaunchKernelGGL((k_fwd_chain<M>), dim3((unsigned)w.S.n), ct, 0, st, w.S, w.gf, zi, w.phiT, w.zbuf,
+        hipLaunchKernelGGL((k_fwd_chain<M>), dim3((unsigned)w.S.n), dim3(CarryShape<M>::CHAIN_THREADS), 0, st, w.S, w.gf, zi, w.phiT, w.zbuf,
                            w.aggf, w.inclf, w.xs, chain, w.nonfinite);
     else  // one block per group: its prefix of group maps, then its chunks
         hipLaunchKernelGGL((k_fwd_carry<M, FS::CPW>), dim3((unsigned)w.gf.ngroups), ct, 0, st, w.S, w.gf, zi,
@@ -82,7 +82,7 @@ void Ops<M>::backward_t(const Bufs &w, const float *g, const float *a, const flo
     tm.end();
     tm.begin("bwd_carry");
     const dim3 ct(CarryShape<M>::THREADS);
-    hipLaunchKernelGGL((k_bwd_chain<M>), dim3((unsigned)w.S.n), ct, 0, st, w.S, w.gb, w.phiT, w.qbuf, w.aggb,
+    hipLaunchKernelGGL((k_bwd_chain<M>), dim3((unsigned)w.S.n), dim3(CarryShape<M>::CHAIN_THREADS), 0, st, w.S, w.gb, w.phiT, w.qbuf, w.aggb,
                        w.inclb, w.yend, gzi, w.chain, w.nonfinite);
     if (!w.chain)
         hipLaunchKernelGGL((k_bwd_expand<M, RS::CPW>), dim3((unsigned)w.gb.ngroups), ct, 0, st, w.S, w.gb, w.phiT,

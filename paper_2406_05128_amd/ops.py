@@ -78,7 +78,8 @@ class Plan:
 
     def __init__(self, M: int, device: Optional[torch.device] = None, chunk: Optional[int] = None,
                  chained: bool = False, high_radius: bool = False):
-        """chained: LP_FLAG_CHAINED_CARRY (carry chunk by chunk, for strongly resonant inputs).
+        """chained: LP_FLAG_CHAINED_CARRY (carry chunk by chunk, for strongly resonant inputs;
+        fixes the carry mode, which the autotuner otherwise picks).
         high_radius: LP_FLAG_HIGH_RADIUS (poles near the unit circle: the chained carry over
         chunks long enough for its accuracy; the autotuner keeps to such lengths)."""
         lib = _lib.load()
@@ -86,7 +87,7 @@ class Plan:
         self.device = dev
         self.M = int(M)
         self.high_radius = bool(high_radius)
-        self.chained = bool(chained) or self.high_radius
+        self._carry_fixed = bool(chained) or self.high_radius
         h = ctypes.c_void_p()
         _lib.check(lib.lp_plan_create(ctypes.byref(h), dev.index or 0, self.M,
                                       (_lib.LP_FLAG_CHAINED_CARRY if chained else 0)
@@ -117,29 +118,45 @@ class Plan:
     def set_chunk(self, L: int):
         _lib.check(_lib.load().lp_plan_set_chunk(self._h, int(L)))
 
+    @property
+    def chained(self) -> bool:
+        """Whether the plan carries chunk by chunk (else through group maps)."""
+        return _lib.load().lp_plan_get_carry(self._h) == 1
+
+    def set_carry(self, chained: bool):
+        """Fix the carry mode (lp_plan_set_carry); the autotuner then keeps it."""
+        _lib.check(_lib.load().lp_plan_set_carry(self._h, 1 if chained else 0))
+        self._carry_fixed = True
+
     def reserve(self, B: int, T: int):
         _lib.check(_lib.load().lp_plan_reserve(self._h, int(B), int(T)))
 
     def autotune(self, B: int, T: int, reps: int = 3, cache: bool = True) -> dict:
-        """Pick the fastest chunk length for a B x T forward + adjoint step (lp_plan_autotune).
+        """Pick the fastest chunk length (and, unless fixed, carry mode) for a B x T
+        forward + adjoint step (lp_plan_autotune).
 
-        Results are cached per (device name, M, B, T) in a JSON file
+        Results are cached per (device name, M, B, T, carry constraint) in a JSON file
         ($TVLP_AUTOTUNE_CACHE, default ~/.cache/tvlp/autotune.json); a cached
-        entry is applied without measuring.  Returns {"chunk", "ms", "cached"}.
+        entry is applied without measuring.  Returns {"chunk", "chained", "ms", "cached"}.
         """
         from . import autotune as _at
-        key = _at.cache_key(torch.cuda.get_device_name(self.device), self.M, B, T,
-                            "high-radius" if self.high_radius else ("chained" if self.chained else "grouped"))
+        constraint = ("high-radius" if self.high_radius
+                      else (("chained" if self.chained else "grouped") if self._carry_fixed else "free"))
+        key = _at.cache_key(torch.cuda.get_device_name(self.device), self.M, B, T, constraint)
         if cache:
             hit = _at.lookup(key)
             if hit is not None:
                 self.set_chunk(hit["chunk"])
-                return {**hit, "cached": True}
+                if not self._carry_fixed:
+                    # apply the cached mode and leave the choice free for later tuning
+                    _lib.check(_lib.load().lp_plan_set_carry(self._h, 1 if hit["chained"] else 0))
+                    _lib.check(_lib.load().lp_plan_set_carry(self._h, -1))
+                return {**hit, "chained": self.chained, "cached": True}
         L = ctypes.c_int()
         ms = ctypes.c_double()
         _lib.check(_lib.load().lp_plan_autotune(self._h, int(B), int(T), int(reps), ctypes.byref(L),
                                                 ctypes.byref(ms)))
-        res = {"chunk": int(L.value), "ms": float(ms.value)}
+        res = {"chunk": int(L.value), "chained": self.chained, "ms": float(ms.value)}
         if cache:
             _at.store(key, res)
         return {**res, "cached": False}

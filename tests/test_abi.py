@@ -58,6 +58,8 @@ def test_null_plan_and_bad_sizes_are_errors():
     assert lib.lp_forward_plain(16, 1, 1, None, None, None, None, None, None) == _lib.LP_EINVAL
     assert lib.lp_backward_plain(16, 1, 1, None, None, None, None, None, None, None, None) == _lib.LP_EINVAL
     assert lib.lp_plan_destroy(None) == _lib.LP_OK
+    assert lib.lp_plan_set_carry(None, 1) == _lib.LP_EINVAL
+    assert lib.lp_plan_get_carry(None) == -1
 
 
 def test_segments_pair_graph_and_server_argument_errors():

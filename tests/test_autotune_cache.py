@@ -10,11 +10,13 @@ def test_cache_roundtrip(tmp_path, monkeypatch):
     k1 = at.cache_key("AMD Instinct MI355X", 22, 64, 48000)
     k2 = at.cache_key("AMD Instinct MI355X", 16, 4, 16000)
     assert at.lookup(k1) is None
-    at.store(k1, {"chunk": 264, "ms": 0.9})
+    at.store(k1, {"chunk": 264, "chained": True, "ms": 0.9})
     at.store(k2, {"chunk": 128, "ms": 0.05})
-    assert at.lookup(k1) == {"chunk": 264, "ms": 0.9}
-    assert at.lookup(k2) == {"chunk": 128, "ms": 0.05}
+    assert at.lookup(k1) == {"chunk": 264, "chained": True, "ms": 0.9}
+    assert at.lookup(k2) == {"chunk": 128, "chained": False, "ms": 0.05}
     assert set(json.loads(path.read_text())) == {k1, k2}
+    # the carry constraint is part of the key
+    assert at.cache_key("d", 22, 64, 48000, "free") != at.cache_key("d", 22, 64, 48000)
 
 
 def test_corrupt_or_invalid_entries_are_ignored(tmp_path, monkeypatch):

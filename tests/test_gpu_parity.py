@@ -346,10 +346,16 @@ def test_autotuned_chunk_is_valid_and_correct(tv, tmp_path, monkeypatch):
     assert not res["cached"] and res["ms"] > 0
     L = res["chunk"]
     assert L % M == 0 and M <= L <= 2048 and plan.chunk == L
-    again = tv.Plan(M, dev()).autotune(8, 5000)
-    assert again["cached"] and again["chunk"] == L
+    assert res["chained"] == plan.chained
+    again_plan = tv.Plan(M, dev())
+    again = again_plan.autotune(8, 5000)
+    assert again["cached"] and again["chunk"] == L and again_plan.chained == res["chained"]
     e, a, g = inputs(3, 3001, M, seed=21)
-    check_all(tv, e, a, g, chunk=L)
+    check_all(tv, e, a, g, chunk=L, chained=res["chained"])
+    # a fixed carry mode is kept by the tuner
+    fixed = tv.Plan(M, dev())
+    fixed.set_carry(False)
+    assert fixed.autotune(8, 5000, reps=1, cache=False)["chained"] is False and not fixed.chained
 
 
 @pytest.mark.parametrize("B,T,M,L", [(3, 5000, 22, 66), (2, 9001, 32, 64), (4, 3000, 16, 32), (3, 2000, 4, 8)])
