@@ -69,12 +69,21 @@ void Ops<M>::backward_t(const Bufs &w, const float *g, const float *a, const flo
     const bool emit = ge || ga;
     const float *s_use = s_in ? s_in : w.sbuf;
     const size_t dynr = FR ? frame_lds_bytes(RS::CPW, M, w.S.nf) : 0;
+    // per-sample rows (not frame-rate, not time-invariant): tiled row streams
+    const bool tile = !FR && !w.S.ti;
     tm.begin("bwd_scan");
     if (emit && !s_in) {
         const int64_t nrun = ceil_div(w.nch, RS::CPW);
-        hipLaunchKernelGGL((k_bwd_front<M, RS::G, RS::R, FR>), dim3((unsigned)(w.gb.ngroups + nrun)), dim3(64),
-                           dynr, st, w.S, w.gb, g, a, w.phiT, w.qbuf, w.aggb, w.zero, w.chain, e, w.xs, w.sbuf,
-                           w.nch);
+        const dim3 grid((unsigned)(w.gb.ngroups + nrun));
+        if (tile)
+            hipLaunchKernelGGL((k_bwd_front<M, RS::G, RS::R, FR, !FR>), grid, dim3(64), dynr, st, w.S, w.gb, g, a,
+                               w.phiT, w.qbuf, w.aggb, w.zero, w.chain, e, w.xs, w.sbuf, w.nch);
+        else
+            hipLaunchKernelGGL((k_bwd_front<M, RS::G, RS::R, FR>), grid, dim3(64), dynr, st, w.S, w.gb, g, a,
+                               w.phiT, w.qbuf, w.aggb, w.zero, w.chain, e, w.xs, w.sbuf, w.nch);
+    } else if (tile) {
+        hipLaunchKernelGGL((k_bwd_local<M, RS::G, RS::R, FR, !FR>), dim3((unsigned)w.gb.ngroups), dim3(64), dynr,
+                           st, w.S, w.gb, g, a, w.phiT, w.qbuf, w.aggb, w.zero, w.chain);
     } else {
         hipLaunchKernelGGL((k_bwd_local<M, RS::G, RS::R, FR>), dim3((unsigned)w.gb.ngroups), dim3(64), dynr, st,
                            w.S, w.gb, g, a, w.phiT, w.qbuf, w.aggb, w.zero, w.chain);

@@ -454,10 +454,14 @@ __device__ __forceinline__ void ring_loop(RR &rr, float *ring, int L, int U, Bod
 template <int M, int CPW, bool DESC, bool FR>
 using RingOf = std::conditional_t<FR, FrameRing<M, CPW, DESC>, RowRing<M, CPW, DESC>>;
 
-// Tile ring of the per-sample-row kernels: 4 slots of 8 rows (4 rows for 16
-// chunks per wave, to keep the ring near 24 KB).
-template <int M, int CPW, bool DESC>
-using TileOf = TileRing<M, CPW, DESC, (CPW >= 16 ? 4 : 8), 4>;
+// Tile ring of the per-sample-row kernels: NT slots of 8 rows (4 rows for 16
+// chunks per wave, to keep the ring near 24 KB at 4 slots).
+template <int M, int CPW, bool DESC, int NT = 4>
+using TileOf = TileRing<M, CPW, DESC, (CPW >= 16 ? 4 : 8), NT>;
+
+// Tile slots of the adjoint's front launch, whose two kinds of waves share
+// every SIMD (about 18 KB of LDS per wave at 3 slots, so that eight fit a CU).
+constexpr int FrontTiles = 3;
 
 // Rows of the coefficient array (= samples of the sequence layout).
 __device__ __forceinline__ int64_t seq_rows(const Seqs &S) {
@@ -478,16 +482,17 @@ __host__ __device__ constexpr size_t rerun_s_lds_bytes(int cpw, int L) {
     return ((size_t)cpw * (size_t)L * sizeof(float) + 15) & ~(size_t)15;
 }
 
-template <int M, int G, bool FR = false, bool TILE = false>
+template <int M, int G, bool FR = false, bool TILE = false, int NT = 4>
 struct RerunLds {
-    static constexpr int BYTES = (TILE ? TileOf<M, 64 / G, false>::FLOATS : RingOf<M, 64 / G, false, FR>::FLOATS) * 4;
+    static constexpr int BYTES =
+        (TILE ? TileOf<M, 64 / G, false, NT>::FLOATS : RingOf<M, 64 / G, false, FR>::FLOATS) * 4;
 };
 
 // FR: a holds frame-rate rows [B][F][M] and frl is the frame staging area
 // (frame_lds_bytes(64 / G, M, S.nf) bytes of LDS).
 // TILE: per-sample rows (not FR, not time-invariant) streamed through the
 // tile ring of tvlp_tiles.hpp instead of the row ring.
-template <int M, int G, bool FR = false, bool TILE = false>
+template <int M, int G, bool FR = false, bool TILE = false, int NT = 4>
 __device__ __forceinline__ void rerun_chunks(Seqs S, const float *__restrict__ e, const float *__restrict__ a,
                                              const double *__restrict__ xs, float *__restrict__ s,
                                              double *__restrict__ zf, const float *__restrict__ zero,
@@ -498,7 +503,10 @@ __device__ __forceinline__ void rerun_chunks(Seqs S, const float *__restrict__ e
     constexpr int TPL = (M + G - 1) / G;
     static_assert(!(TILE && FR), "frame-rate rows are produced in LDS, not tiled");
     using RR = RingOf<M, CPW, false, FR>;
-    using TR = TileOf<M, CPW, false>;
+    using TR = TileOf<M, CPW, false, NT>;
+    // unclamped tiles store G consecutive outputs per chunk at a time: a tile
+    // must end on such a group's boundary
+    static_assert(!TILE || TR::ROWS % G == 0, "tile rows must be a multiple of the lanes per chunk");
 
     const int lane = threadIdx.x;
     const int slot = lane / G, r = lane % G;

@@ -406,25 +406,31 @@ __global__ __launch_bounds__(64) void k_fwd_local(
 
 // ---------------------------------------------------------------- adjoint scan
 
-template <int M, int G, int R, bool FR = false>
+// TILE: per-sample rows (not frame-rate, not time-invariant) streamed through
+// a descending tile ring of FrontTiles slots (tvlp_tiles.hpp) instead of the
+// row ring.
+template <int M, int G, int R, bool FR = false, bool TILE = false>
 struct BwdScanShape {
     static constexpr int CPW = 64 / G;
     using RD = RingOf<M, CPW, true, FR>;
-    static constexpr int RING_BYTES = RD::FLOATS * 4;
+    using TD = TileOf<M, CPW, true, FrontTiles>;
+    static constexpr int RING_BYTES = (TILE ? TD::FLOATS : RD::FLOATS) * 4;
     static constexpr int MAT_BYTES = (3 * M * M + 4 * M + CPW * M) * 8;
     static constexpr int LDS_BYTES = RING_BYTES > MAT_BYTES ? RING_BYTES : MAT_BYTES;
 };
 
 // One wave handles adjoint group tid_; lds_raw: SH::LDS_BYTES bytes of LDS;
 // FR: a holds frame-rate rows and frl is the frame staging area.
-template <int M, int G, int R, bool FR = false>
+template <int M, int G, int R, bool FR = false, bool TILE = false>
 __device__ __forceinline__ void bwd_local_group(Seqs S, Groups GR, const float *__restrict__ g_in,
                                                 const float *__restrict__ a, const double *__restrict__ phiT,
                                                 double *__restrict__ qbuf, double *__restrict__ aggbuf,
                                                 const float *__restrict__ zero, int chain, int64_t tid_,
                                                 unsigned char *lds_raw, unsigned char *frl = nullptr) {
-    using SH = BwdScanShape<M, G, R, FR>;
+    static_assert(!(TILE && FR), "frame-rate rows are produced in LDS, not tiled");
+    using SH = BwdScanShape<M, G, R, FR, TILE>;
     using RD = typename SH::RD;
+    using TD = typename SH::TD;
     constexpr int CPW = SH::CPW;
     constexpr int TPL = (M + G - 1) / G;
     constexpr int MM = M * M;
@@ -461,7 +467,51 @@ __device__ __forceinline__ void bwd_local_group(Seqs S, Groups GR, const float *
     double P[TPL], P0 = 0.0;
 #pragma unroll
     for (int m = 0; m < TPL; ++m) P[m] = 0.0;
-    {
+    // one descending step of the chunk's adjoint with row u's taps av and
+    // upstream gradient gx
+    auto step = [&](int u, const double (&av)[TPL], double gx, auto fast) {
+        const double gh = gx + P0;
+        double np[TPL];
+#pragma unroll
+        for (int m = 0; m < TPL; ++m) np[m] = fma(-av[m], gh, P[m]);
+        const double down = dpp_f64<DPP_ROW_SHL1>(np[0]);
+        const double b0 = group_bcast0<G>(np[0], r);
+        if constexpr (decltype(fast)::value) {
+            // unclamped steps end before the chunk's first sample
+            P0 = b0;
+#pragma unroll
+            for (int m = 0; m + 1 < TPL; ++m) P[m] = np[m + 1];
+            P[TPL - 1] = (r == G - 1) ? 0.0 : down;
+        } else {
+            // a step inside the chunk shifts the pendings one tap down; the
+            // chunk's first sample (u = len - 1) keeps the un-shifted p(-i)
+            const bool shift = u + 1 < len, last = u + 1 == len;
+            P0 = shift ? b0 : P0;
+#pragma unroll
+            for (int m = 0; m + 1 < TPL; ++m) P[m] = shift ? np[m + 1] : (last ? np[m] : P[m]);
+            P[TPL - 1] = shift ? ((r == G - 1) ? 0.0 : down) : (last ? np[TPL - 1] : P[TPL - 1]);
+        }
+    };
+    if constexpr (TILE) {
+        // the shared upstream gradient of a stacked pair has half the rows
+        const int64_t grows = S.gshare > 0 ? (int64_t)S.gshare * S.T : seq_rows(S);
+        TD td;
+        const int delta = td.init(a, seq_rows(S), g_in, grows, lane, base, len, G, base + gshare_offset(S, b));
+        const typename TD::template Lanes<TPL> ln(slot, r, delta);
+        td.start(ring);
+        double av[TPL], gx;
+        TD::load(ring, TD::first(), ln, av, gx, r);
+        // an unclamped tile must end before every chunk's first sample (u = len - 1,
+        // the one step that does not shift)
+        tile_loop(td, ring, L, wave_min_len<CPW, G>(len) - 1, [&](int u, auto ks, auto fast) {
+            double nav[TPL], ngx;
+            TD::load(ring, ks, ln, nav, ngx, r);
+            step(u, av, gx, fast);
+#pragma unroll
+            for (int m = 0; m < TPL; ++m) av[m] = nav[m];
+            gx = ngx;
+        });
+    } else {
         RD rd;
         if constexpr (FR)
             rd.init(a, g_in, zero, lane, base, len, G, gshare_offset(S, b), b, c * L, S, frl);
@@ -475,27 +525,7 @@ __device__ __forceinline__ void bwd_local_group(Seqs S, Groups GR, const float *
         ring_loop(rd, ring, L, fast_steps<RD, G, CPW>(len), [&](int u, auto ks, auto fast) {
             double nav[TPL], ngx;
             RD::load(ring, ks, ln, nav, ngx);
-            const double gh = gx + P0;
-            double np[TPL];
-#pragma unroll
-            for (int m = 0; m < TPL; ++m) np[m] = fma(-av[m], gh, P[m]);
-            const double down = dpp_f64<DPP_ROW_SHL1>(np[0]);
-            const double b0 = group_bcast0<G>(np[0], r);
-            if constexpr (decltype(fast)::value) {
-                // unclamped steps end before the chunk's first sample
-                P0 = b0;
-#pragma unroll
-                for (int m = 0; m + 1 < TPL; ++m) P[m] = np[m + 1];
-                P[TPL - 1] = (r == G - 1) ? 0.0 : down;
-            } else {
-                // a step inside the chunk shifts the pendings one tap down; the
-                // chunk's first sample (u = len - 1) keeps the un-shifted p(-i)
-                const bool shift = u + 1 < len, last = u + 1 == len;
-                P0 = shift ? b0 : P0;
-#pragma unroll
-                for (int m = 0; m + 1 < TPL; ++m) P[m] = shift ? np[m + 1] : (last ? np[m] : P[m]);
-                P[TPL - 1] = shift ? ((r == G - 1) ? 0.0 : down) : (last ? np[TPL - 1] : P[TPL - 1]);
-            }
+            step(u, av, gx, fast);
 #pragma unroll
             for (int m = 0; m < TPL; ++m) av[m] = nav[m];
             gx = ngx;
@@ -569,28 +599,29 @@ __device__ __forceinline__ void bwd_local_group(Seqs S, Groups GR, const float *
     }
 }
 
-template <int M, int G, int R, bool FR = false>
+template <int M, int G, int R, bool FR = false, bool TILE = false>
 __global__ __launch_bounds__(64) void k_bwd_local(Seqs S, Groups GR, const float *__restrict__ g_in,
                                                   const float *__restrict__ a, const double *__restrict__ phiT,
                                                   double *__restrict__ qbuf, double *__restrict__ aggbuf,
                                                   const float *__restrict__ zero, int chain) {
-    __shared__ __attribute__((aligned(16))) unsigned char lds_raw[BwdScanShape<M, G, R, FR>::LDS_BYTES];
+    __shared__ __attribute__((aligned(16))) unsigned char lds_raw[BwdScanShape<M, G, R, FR, TILE>::LDS_BYTES];
     extern __shared__ __attribute__((aligned(16))) unsigned char bwd_dyn[];  // FR: frame staging
-    bwd_local_group<M, G, R, FR>(S, GR, g_in, a, phiT, qbuf, aggbuf, zero, chain, blockIdx.x, lds_raw, bwd_dyn);
+    bwd_local_group<M, G, R, FR, TILE>(S, GR, g_in, a, phiT, qbuf, aggbuf, zero, chain, blockIdx.x, lds_raw,
+                                       bwd_dyn);
 }
 
 // The adjoint's local scan together with the recompute of s from the saved
 // chunk entry states (into s_out), in one launch: neither needs the other, and
 // interleaving their blocks gives every SIMD two independent waves whose
 // latencies overlap.  Blocks alternate (scan, rerun) while both kinds remain.
-template <int M, int G, int R, bool FR = false>
+template <int M, int G, int R, bool FR = false, bool TILE = false>
 __global__ __launch_bounds__(64) void k_bwd_front(Seqs S, Groups GR, const float *__restrict__ g_in,
                                                   const float *__restrict__ a, const double *__restrict__ phiT,
                                                   double *__restrict__ qbuf, double *__restrict__ aggbuf,
                                                   const float *__restrict__ zero, int chain,
                                                   const float *__restrict__ e, const double *__restrict__ xs,
                                                   float *__restrict__ s_out, int64_t nch) {
-    constexpr int B1 = BwdScanShape<M, G, R, FR>::LDS_BYTES, B2 = RerunLds<M, G, FR>::BYTES;
+    constexpr int B1 = BwdScanShape<M, G, R, FR, TILE>::LDS_BYTES, B2 = RerunLds<M, G, FR, TILE, FrontTiles>::BYTES;
     __shared__ __attribute__((aligned(16))) unsigned char lds_raw[B1 > B2 ? B1 : B2];
     extern __shared__ __attribute__((aligned(16))) unsigned char front_dyn[];  // FR: frame staging
     const int64_t nscan = GR.ngroups, nrun = (nch + 64 / G - 1) / (64 / G);
@@ -606,10 +637,11 @@ __global__ __launch_bounds__(64) void k_bwd_front(Seqs S, Groups GR, const float
         j = i - both;
     }
     if (scan)
-        bwd_local_group<M, G, R, FR>(S, GR, g_in, a, phiT, qbuf, aggbuf, zero, chain, j, lds_raw, front_dyn);
+        bwd_local_group<M, G, R, FR, TILE>(S, GR, g_in, a, phiT, qbuf, aggbuf, zero, chain, j, lds_raw,
+                                           front_dyn);
     else
-        rerun_chunks<M, G, FR>(S, e, a, xs, s_out, nullptr, zero, nch, j, reinterpret_cast<float *>(lds_raw),
-                               nullptr, front_dyn);
+        rerun_chunks<M, G, FR, TILE, FrontTiles>(S, e, a, xs, s_out, nullptr, zero, nch, j,
+                                                 reinterpret_cast<float *>(lds_raw), nullptr, front_dyn);
 }
 
 }  // namespace tvlp
