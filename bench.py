@@ -29,19 +29,16 @@ FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published
 
 
 # HBM bytes per launch (rocprofv3 FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, factors from a
-# plain 256 MiB device copy) for the training workload, per chunk length; valid only for the
-# kernel sources (hash below) they were measured with, otherwise reported as null.
+# plain 256 MiB device copy) for the training workload with the chained carry, per chunk
+# length; valid only for the kernel sources (hash below) they were measured with and for
+# the chained carry, otherwise reported as null.
 TRAFFIC = {
-    "sources_sha256": "127812db53712b4a9119f38e3bd876996e445d8c3bb13608c4b29273648e7af4",
+    "sources_sha256": "b64e7e34f1a21933ddd6baf9a053d71e00ad609a585197e937a33a83f3038bd2",
+    "carry": "chained",
     "bytes_by_chunk": {
-        374: {"fwd_scan": 327982899, "fwd_emit": 299558614, "bwd_scan": 627690776, "bwd_emit": 583198674},
-        396: {"fwd_scan": 324850734, "fwd_emit": 298709595, "bwd_scan": 623030045, "bwd_emit": 582624792},
-        418: {"fwd_scan": 320327088, "fwd_emit": 298773793, "bwd_scan": 621017877, "bwd_emit": 582576859},
-        440: {"fwd_scan": 319243873, "fwd_emit": 297689586, "bwd_scan": 614620203, "bwd_emit": 581690705},
-        462: {"fwd_scan": 315345204, "fwd_emit": 298295835, "bwd_scan": 614618057, "bwd_emit": 581878974},
-        484: {"fwd_scan": 315631650, "fwd_emit": 297848573, "bwd_scan": 611931242, "bwd_emit": 581712205},
-        506: {"fwd_scan": 311666920, "fwd_emit": 297911086, "bwd_scan": 610780350, "bwd_emit": 581765378},
-        528: {"fwd_scan": 309611240, "fwd_emit": 296567596, "bwd_scan": 605887926, "bwd_emit": 580391213},
+        396: {"fwd_scan": 320787251, "fwd_emit": 320271283, "bwd_scan": 627125023, "bwd_emit": 582682818},
+        418: {"fwd_scan": 316245576, "fwd_emit": 319039986, "bwd_scan": 625359305, "bwd_emit": 582620044},
+        440: {"fwd_scan": 315759055, "fwd_emit": 314715509, "bwd_scan": 612960507, "bwd_emit": 581742636},
     },
 }
 
@@ -59,8 +56,8 @@ def kernel_sources_sha256() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str, chunk: int):
-    if kernel_sources_sha256() != TRAFFIC["sources_sha256"]:
+def measured_traffic(kernel: str, chunk: int, chained: bool = True):
+    if kernel_sources_sha256() != TRAFFIC["sources_sha256"] or chained != (TRAFFIC["carry"] == "chained"):
         return None
     return TRAFFIC["bytes_by_chunk"].get(chunk, {}).get(kernel)
 
@@ -679,6 +676,8 @@ def main():
     ap.add_argument("--gamma", type=float, default=1.0,
                     help="bandwidth expansion of the coefficient tracks (1 = literal recipe)")
     ap.add_argument("--chunk", type=int, default=None)
+    ap.add_argument("--carry", choices=("auto", "chained", "grouped"), default="auto",
+                    help="carry mode of the training plan (auto: the autotuner's choice, or group maps with --chunk)")
     ap.add_argument("--no-sequential", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seq-steps", type=int, default=2)
@@ -730,6 +729,8 @@ def main():
     torch.cuda.synchronize()
 
     plan = tv.Plan(M, dev, args.chunk)
+    if args.carry != "auto":
+        plan.set_carry(args.carry == "chained")
     tune = None
     if args.chunk is None:
         # chunk length picked by the autotuner (fresh measurement, not the cache)
@@ -788,7 +789,7 @@ def main():
         d = kernels[dominant]
         by = kernel_bytes(dominant, B, T, M, L)
         ach = by / (d["avg_us"] * 1e-6) / 1e9
-        traffic = measured_traffic(dominant, L)
+        traffic = measured_traffic(dominant, L, plan.chained)
         roofline = {"kernel": dominant, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "algorithmic_bytes": by,
