@@ -306,20 +306,19 @@ __global__ __launch_bounds__(64) void k_fwd_local(
                 __builtin_amdgcn_s_waitcnt(waitcnt_vm(SH::DMA_N * (SH::D - 1)));  // row t+1 has landed
                 float nrv[M], nex;
                 load_row(SH::CONST_SLOTS ? (K + 1) % SH::NS : (t + 1) % SH::NS, K, nrv, nex);
-                double acc[CPL][2];
+                // one chain per column (CPL independent chains cover the FMA
+                // latency), oldest tap first so that the newest output enters last
+                double acc[CPL];
 #pragma unroll
-                for (int m = 0; m < CPL; ++m) {
-                    acc[m][0] = (m == 0 && sub == 0) ? (double)ex : 0.0;
-                    acc[m][1] = 0.0;
-                }
+                for (int m = 0; m < CPL; ++m) acc[m] = (m == 0 && sub == 0) ? (double)ex : 0.0;
 #pragma unroll
-                for (int i = 1; i <= M; ++i) {
+                for (int i = M; i >= 1; --i) {
                     const double ai = (double)rv[i - 1];
 #pragma unroll
-                    for (int m = 0; m < CPL; ++m) acc[m][i & 1] = fma(-ai, h[m][wrap<M>(K - i)], acc[m][i & 1]);
+                    for (int m = 0; m < CPL; ++m) acc[m] = fma(-ai, h[m][wrap<M>(K - i)], acc[m]);
                 }
 #pragma unroll
-                for (int m = 0; m < CPL; ++m) h[m][K] = acc[m][0] + acc[m][1];
+                for (int m = 0; m < CPL; ++m) h[m][K] = acc[m];
 #pragma unroll
                 for (int i = 0; i < M; ++i) rv[i] = nrv[i];
                 ex = nex;
