@@ -601,6 +601,7 @@ __device__ __forceinline__ void rerun_chunks(Seqs S, const float *__restrict__ e
             const int kl = __shfl((int)len, k * G, 64);
             const int64_t kseq = __shfl(b, k * G, 64);
             bool bad = false;
+#pragma unroll 8
             for (int i = lane; i < kl; i += 64) {
                 const float v = sst[k * L + i];
                 bad |= !__builtin_isfinite(v);
@@ -701,7 +702,24 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
     const typename RD::template Lanes<TPL> ln(slot, r);
     const int U = fast_steps<RD, G, CPW>(len);
     for (int k = r; k < M; k += G) ssh[M - 1 - k] = active ? (float)xs[gc * M + k] : 0.f;
-    for (int t = r; t < L; t += G) ssh[M + t] = (active && t < len) ? s_in[base + t] : 0.f;
+    {
+        // sixteen loads per lane in flight before their LDS writes (one at a time,
+        // every load of the chunk's s waited on its own memory latency)
+        constexpr int U = 16;
+        for (int t0 = r; t0 < L; t0 += U * G) {
+            float v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = t0 + u * G;
+                v[u] = (active && t < len) ? s_in[base + t] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = t0 + u * G;
+                if (t < L) ssh[M + t] = v[u];
+            }
+        }
+    }
     __syncthreads();
 
     // ---- descending adjoint pass
@@ -861,6 +879,7 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
             const float *gk = gsh_all + k * L;
             bool bad = false;
             if (ge || CHECK)
+#pragma unroll 8
                 for (int t = lane; t < kl; t += 64) {
                     const float v = gk[t];
                     if constexpr (CHECK) bad |= !__builtin_isfinite(v);
@@ -869,23 +888,35 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
             if (ga) {
                 float *gak = ga + kb * M;
                 if (M % 2 == 0 && (reinterpret_cast<uintptr_t>(ga) & 7) == 0) {
-                    // pairs of taps (i, i+1) of one row per lane, float2 stores (8-byte aligned: M even)
-                    constexpr int SQ = 128 / M, SR = 128 % M;  // lane stride of 64 pairs in rows and taps
+                    // pairs of taps (i, i+1) of one row per lane, float2 stores (8-byte aligned: M even);
+                    // rounds of four pairs per lane, whose LDS reads are all issued before the
+                    // first product (a pair at a time waited for its reads on every store)
                     const int n2 = kl * (M / 2);
-                    int t = (2 * lane) / M, i = 2 * lane - t * M;
-                    for (int j = lane; j < n2; j += 64) {
-                        const float gt = -gk[t];
+                    auto pair = [&](int j, float &gt, float &s0, float &s1) {
+                        const int f = 2 * j, t = f / M, i = f - t * M;
+                        gt = -gk[t];
+                        s0 = sk[M + t - 1 - i];
+                        s1 = sk[M + t - 2 - i];
+                    };
+                    auto put = [&](int j, float gt, float s0, float s1) {
                         float2 v;
-                        v.x = gt * sk[M + t - 1 - i];
-                        v.y = gt * sk[M + t - 2 - i];
+                        v.x = gt * s0;
+                        v.y = gt * s1;
                         if constexpr (CHECK) bad |= !__builtin_isfinite(v.x) | !__builtin_isfinite(v.y);
                         *reinterpret_cast<float2 *>(gak + 2 * j) = v;
-                        t += SQ;
-                        i += SR;
-                        if (i >= M) {
-                            i -= M;
-                            ++t;
-                        }
+                    };
+                    int j = lane;
+                    for (; j + 192 < n2; j += 256) {
+                        float gt[4], s0[4], s1[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) pair(j + 64 * u, gt[u], s0[u], s1[u]);
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) put(j + 64 * u, gt[u], s0[u], s1[u]);
+                    }
+                    for (; j < n2; j += 64) {
+                        float gt, s0, s1;
+                        pair(j, gt, s0, s1);
+                        put(j, gt, s0, s1);
                     }
                 } else {
                     const int n = kl * M;
