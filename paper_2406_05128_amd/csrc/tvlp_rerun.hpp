@@ -701,26 +701,43 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
     float *gsh = gsh_all + slot * L;
     const typename RD::template Lanes<TPL> ln(slot, r);
     const int U = fast_steps<RD, G, CPW>(len);
-    for (int k = r; k < M; k += G) ssh[M - 1 - k] = active ? (float)xs[gc * M + k] : 0.f;
-    {
-        // sixteen loads per lane in flight before their LDS writes (one at a time,
-        // every load of the chunk's s waited on its own memory latency)
-        constexpr int U = 16;
-        for (int t0 = r; t0 < L; t0 += U * G) {
-            float v[U];
+    // s of the chunk and its M predecessors into LDS; called once the row ring's
+    // first rows are in flight, so both wait on the same memory latencies (the
+    // descending pass does not read these rows; the barrier after it publishes them)
+    auto load_s = [&]() {
+        {
+            // the chunk's entry state (M words over G lanes), all loads in flight together
+            float xv[(M + G - 1) / G];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int t = t0 + u * G;
-                v[u] = (active && t < len) ? s_in[base + t] : 0.f;
+            for (int q = 0; q < (M + G - 1) / G; ++q) {
+                const int k = r + G * q;
+                xv[q] = (active && k < M) ? (float)xs[gc * M + k] : 0.f;
             }
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int t = t0 + u * G;
-                if (t < L) ssh[M + t] = v[u];
+            for (int q = 0; q < (M + G - 1) / G; ++q) {
+                const int k = r + G * q;
+                if (k < M) ssh[M - 1 - k] = xv[q];
             }
         }
-    }
-    __syncthreads();
+        {
+            // sixteen loads per lane in flight before their LDS writes (one at a time,
+            // every load of the chunk's s waited on its own memory latency)
+            constexpr int U = 16;
+            for (int t0 = r; t0 < L; t0 += U * G) {
+                float v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int t = t0 + u * G;
+                    v[u] = (active && t < len) ? s_in[base + t] : 0.f;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int t = t0 + u * G;
+                    if (t < L) ssh[M + t] = v[u];
+                }
+            }
+        }
+    };
 
     // ---- descending adjoint pass
     double P[TPL], P0 = 0.0;
@@ -741,6 +758,7 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
     else
         rd.init(a, g, zero, lane, base, len, G, goff, coef_row(S, b, base), S.ti);
     for (int u = 0; u < RD::D; ++u) rd.issue(ring, u);
+    load_s();
     RD::wait_next();  // row 0 (sample len - 1)
     double av[TPL], gx;
     RD::load(ring, 0, ln, av, gx);
