@@ -33,12 +33,12 @@ FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published
 # length; valid only for the kernel sources (hash below) they were measured with and for
 # the chained carry, otherwise reported as null.
 TRAFFIC = {
-    "sources_sha256": "b64e7e34f1a21933ddd6baf9a053d71e00ad609a585197e937a33a83f3038bd2",
+    "sources_sha256": "1468b336fc72df8f3187fd7e438597f413d7b2fe75b2b73dbb80c3f37880f715",
     "carry": "chained",
     "bytes_by_chunk": {
-        396: {"fwd_scan": 320787251, "fwd_emit": 320271283, "bwd_scan": 627125023, "bwd_emit": 582682818},
-        418: {"fwd_scan": 316245576, "fwd_emit": 319039986, "bwd_scan": 625359305, "bwd_emit": 582620044},
-        440: {"fwd_scan": 315759055, "fwd_emit": 314715509, "bwd_scan": 612960507, "bwd_emit": 581742636},
+        396: {"fwd_scan": 320760092, "fwd_emit": 320341183, "bwd_scan": 627216940, "bwd_emit": 582737934},
+        418: {"fwd_scan": 316274053, "fwd_emit": 319094361, "bwd_scan": 625382039, "bwd_emit": 582673740},
+        440: {"fwd_scan": 315788178, "fwd_emit": 314745349, "bwd_scan": 612967582, "bwd_emit": 581686186},
     },
 }
 
