@@ -125,8 +125,11 @@ int lp_plan_get_carry(const lp_plan *p);
  * 64 .. 1024 samples (multiples of M) and, unless the caller fixed the carry
  * mode (a carry flag at creation, or lp_plan_set_carry), both carry modes;
  * `reps` timed repetitions each after one warm-up; keeps the fastest on the
- * plan.  Allocates and frees its own zero-filled buffers (timing does not
- * depend on the values) and synchronises the device.  Writes the chosen L and
+ * plan.  Allocates and frees its own buffers, filled with deterministic
+ * stand-in data (e and g uniform in [-1, 1), coefficients of a stable filter
+ * below 0.9/M in magnitude: the kernels' time depends on the values through
+ * their power draw, so zeros would favour the wrong candidates), and
+ * synchronises the device.  Writes the chosen L and
  * its best step time in ms (either pointer may be NULL; the carry mode is read
  * back with lp_plan_get_carry).  On error the plan keeps its previous chunk
  * length and carry mode. */

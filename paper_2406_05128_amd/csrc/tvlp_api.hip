@@ -322,7 +322,24 @@ __global__ __launch_bounds__(256) void k_pair_sum(float *__restrict__ y, const f
         const float4 v = *reinterpret_cast<const float4 *>(s2 + n + i0);
         *reinterpret_cast<float4 *>(y + i0) = make_float4(u.x + v.x, u.y + v.y, u.z + v.z, u.w + v.w);
     } else {
-        for (int64_t i = i0; i < n; ++i) y[i] = s2[i] + s2[n + i];
+        const int64_t i1 = i0 + 4 < n ? i0 + 4 : n;
+        for (int64_t i = i0; i < i1; ++i) y[i] = s2[i] + s2[n + i];
+    }
+}
+
+// Deterministic stand-in values for the autotuner's timed runs: x[i] = scale * u
+// with u in [-1, 1) from a 32-bit integer mix of (i, seed) (xorshift-multiply
+// rounds).  The kernels' time depends on the values they see (their power draw
+// and hence the clock), so the candidates are timed on data rather than zeros.
+__global__ __launch_bounds__(256) void k_tune_fill(float *__restrict__ x, int64_t n, float scale, uint32_t seed) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t h = (uint32_t)i ^ (uint32_t)(i >> 32) * 0x9e3779b9u ^ seed;
+        h ^= h >> 16;
+        h *= 0x7feb352du;
+        h ^= h >> 15;
+        h *= 0x846ca68bu;
+        h ^= h >> 16;
+        x[i] = scale * ((float)(h >> 8) * (1.0f / 8388608.0f) - 1.0f);
     }
 }
 
@@ -870,10 +887,16 @@ int lp_plan_autotune(lp_plan *p, int64_t B, int64_t T, int reps, int *chosen, do
     const size_t floats = n * (size_t)(2 * M + 4);  // e, g, s, ge, a, ga
     const size_t bytes = floats * sizeof(float) + saved_bytes;
     if (hipMalloc(&buf, bytes) != hipSuccess) return fail(LP_ENOMEM, "autotune buffers (%zu bytes)", bytes);
-    // timing does not depend on the values: zero inputs
     int rc = check_hip(hipMemset(buf, 0, floats * sizeof(float)), "autotune memset");
     float *e = buf, *g = e + n, *s = g + n, *ge = s + n, *a = ge + n, *ga = a + n * M;
     void *saved = ga + n * M;
+    // e and g uniform in [-1, 1); coefficients below 0.9 / M in magnitude (a stable
+    // filter: their absolute sum stays below 0.9)
+    if (rc == LP_OK) {
+        hipLaunchKernelGGL(k_tune_fill, dim3(1024), dim3(256), 0, nullptr, e, (int64_t)(2 * n), 1.0f, 1u);
+        hipLaunchKernelGGL(k_tune_fill, dim3(1024), dim3(256), 0, nullptr, a, (int64_t)(n * M), 0.9f / M, 2u);
+        rc = check_hip(hipStreamSynchronize(nullptr), "autotune input fill");
+    }
     hipStream_t st = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (rc == LP_OK && (hipStreamCreate(&st) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||

@@ -1,5 +1,9 @@
 // Carries across chunks (gfx950).
 //
+// Group maps.  k_compose forms, for every group of consecutive chunks, the
+// product of its chunks' affine maps (forward P_g, r_g; adjoint Psi_g, w_g),
+// from the transitions and offsets the local scans stored.
+//
 // Forward.  The group maps x(g+1) = P_g x(g) + r_g, applied from x(0) = zi,
 // give every group's entry state; the group's chunk transitions x(c+1) =
 // Phi_c x(c) + z_c then give every chunk's entry state x_c (the state the
@@ -16,7 +20,7 @@
 // write the per-chunk vectors themselves.
 //
 // Matrices are staged through LDS in batches by several waves with many loads
-// in flight; in the chain kernels three waves stage the next batch while the
+// in flight; in the chain kernels seven waves stage the next batch while the
 // first wave runs the current one.  The carried vector lives in the first
 // wave's registers, one entry per lane; every matrix row is one lane's dot
 // product.
@@ -107,6 +111,180 @@ struct CarryShape {
     // matrices (each with its offset vector) per chain-kernel batch
     static constexpr int NB = BUF_DOUBLES / (MM + M) > 0 ? BUF_DOUBLES / (MM + M) : 1;
 };
+
+// ---------------------------------------------------------------- group maps
+//
+// A chunk's affine map is held as an M x (M+1) augmented matrix [A | v]
+// (column-major, the offset v as column M, the implicit last row (0 ... 0 1)),
+// so that one matrix product composes both parts: [A | v] [B | u] =
+// [A B | A u + v].  Forward factors [Phi_c | z_c] (x(c+1) = Phi_c x(c) + z_c),
+// multiplied later-on-the-left: [P_g | r_g] = F_{n-1} ... F_0.  Adjoint
+// factors [Phi_c^T | q_c] (y(c) = Phi_c^T y(c+1) + q_c; Phi^T = 0 for the
+// sequence's last chunk), earlier-on-the-left: [Psi_g | w_g] = F_0 ... F_{n-1}.
+// The factors are multiplied as a binary tree (neighbour pairs, then pairs of
+// pairs), one product per wave, so a group of n chunks takes ceil(log2 n)
+// dependent products instead of n - 1.
+
+template <int M>
+struct ComposeShape {
+    static constexpr int AUG = M * (M + 1);  // doubles per augmented matrix
+    static constexpr int THREADS = 256;
+    static constexpr int WAVES = THREADS / 64;
+    // a wave's lanes as an 8 x 8 grid; lane (rt, ct) forms the outputs in rows
+    // rt + 8r (r < RB) and columns ct + 8c (c < CB)
+    static constexpr int RB = (M + 7) / 8;
+    static constexpr int CB = (M + 1 + 7) / 8;
+};
+
+// C = X Y for augmented matrices in LDS, as a sum of M outer products; one
+// wave, lane (rt, ct)'s outputs into registers.  Rows and columns past the
+// matrix read a valid element and are never stored.
+template <int M>
+__device__ __forceinline__ void aug_product(const double *X, const double *Y,
+                                            double (&acc)[ComposeShape<M>::RB][ComposeShape<M>::CB], int lane) {
+    using CS = ComposeShape<M>;
+    const int rt = lane >> 3, ct = lane & 7;
+    int row[CS::RB], col[CS::CB];
+#pragma unroll
+    for (int r = 0; r < CS::RB; ++r) row[r] = min(rt + 8 * r, M - 1);
+#pragma unroll
+    for (int c = 0; c < CS::CB; ++c) col[c] = min(ct + 8 * c, M);
+#pragma unroll
+    for (int r = 0; r < CS::RB; ++r) {
+        const double xo = X[M * M + row[r]];  // offset column: C[:, M] = X Y[:, M] + X[:, M]
+#pragma unroll
+        for (int c = 0; c < CS::CB; ++c) acc[r][c] = (col[c] == M) ? xo : 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        double xv[CS::RB], yv[CS::CB];
+#pragma unroll
+        for (int r = 0; r < CS::RB; ++r) xv[r] = X[m * M + row[r]];
+#pragma unroll
+        for (int c = 0; c < CS::CB; ++c) yv[c] = Y[col[c] * M + m];
+#pragma unroll
+        for (int r = 0; r < CS::RB; ++r)
+#pragma unroll
+            for (int c = 0; c < CS::CB; ++c) acc[r][c] = fma(xv[r], yv[c], acc[r][c]);
+    }
+}
+
+template <int M>
+__device__ __forceinline__ void aug_store(double *C, const double (&acc)[ComposeShape<M>::RB][ComposeShape<M>::CB],
+                                          int lane) {
+    using CS = ComposeShape<M>;
+    const int rt = lane >> 3, ct = lane & 7;
+#pragma unroll
+    for (int r = 0; r < CS::RB; ++r)
+#pragma unroll
+        for (int c = 0; c < CS::CB; ++c) {
+            const int i = rt + 8 * r, j = ct + 8 * c;
+            if (i < M && j <= M) C[j * M + i] = acc[r][c];
+        }
+}
+
+// LDS of k_compose: the group's factors, multiplied in place.
+template <int M>
+constexpr size_t compose_lds_bytes(int cpw) { return (size_t)cpw * ComposeShape<M>::AUG * sizeof(double); }
+
+// One block per group: forward (BWD false) [P_g | r_g] for every group but each
+// sequence's last, written as aggbuf[gid] = P (column-major) then r; adjoint
+// (BWD true) [Psi_g | w_g] for every group but each sequence's first, written as
+// Psi (row-major) then w.  vec is zbuf (forward) or qbuf (adjoint).  Dynamic
+// LDS: compose_lds_bytes<M>(CPW).
+template <int M, int CPW, bool BWD>
+__global__ __launch_bounds__(256) void k_compose(Seqs S, Groups GR, const double *__restrict__ phiT,
+                                                 const double *__restrict__ vec, double *__restrict__ aggbuf) {
+    using CS = ComposeShape<M>;
+    constexpr int MM = M * M, AUG = CS::AUG;
+    extern __shared__ __attribute__((aligned(16))) double fa[];  // [CPW][AUG]
+    const int64_t gid = blockIdx.x;
+    if (gid >= GR.ngroups) return;
+    int64_t b, g;
+    group_at(S, GR, gid, b, g);
+    const SeqView sv = seq_view(S, b);
+    const int64_t ng = groups_of(sv.C, CPW);
+    if (g >= ng) return;
+    if (BWD ? g == 0 : g == ng - 1) return;  // no map needed
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t c0 = g * CPW;
+    const int n = (int)min((int64_t)CPW, sv.C - c0);
+    const int64_t cb = sv.cbase + c0;
+    // the factors: matrix part, then offsets; every load of a thread is issued
+    // before its LDS writes (one memory latency for the whole staging)
+    constexpr int NL = (CPW * MM + CS::THREADS - 1) / CS::THREADS;
+    constexpr int NV = (CPW * M + CS::THREADS - 1) / CS::THREADS;
+    double v[NL], u[NV];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+        const int idx = tid + q * CS::THREADS;
+        v[q] = 0.0;
+        // adjoint: the sequence's last chunk has no transition (Phi^T = 0)
+        if (idx < n * MM && (!BWD || c0 + idx / MM < sv.C - 1)) v[q] = phiT[cb * MM + idx];
+    }
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        const int idx = tid + q * CS::THREADS;
+        u[q] = idx < n * M ? vec[cb * M + idx] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+        const int idx = tid + q * CS::THREADS;
+        if (idx < n * MM) {
+            const int k = idx / MM, r = idx - k * MM;
+            if (!BWD) {
+                fa[k * AUG + r] = v[q];
+            } else {
+                // phiT holds Phi column-major, i.e. Phi^T row-major: element
+                // r = (i, j) of Phi^T goes to column j, row i
+                const int i = r / M, j = r - i * M;
+                fa[k * AUG + j * M + i] = v[q];
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        const int idx = tid + q * CS::THREADS;
+        if (idx < n * M) {
+            const int k = idx / M;
+            fa[k * AUG + MM + (idx - k * M)] = u[q];
+        }
+    }
+    __syncthreads();
+    // level by level, in place: product p of a level (factors 2p, 2p+1) goes to
+    // slot p once every product of its round has read its factors; slot p is
+    // below every factor a later round reads
+    int cnt = n;
+    while (cnt > 1) {
+        const int np = cnt / 2;
+        for (int p0 = 0; p0 < np; p0 += CS::WAVES) {
+            const int p = p0 + wv;
+            double out[CS::RB][CS::CB];
+            if (p < np) {
+                const double *lo = fa + 2 * p * AUG, *hi = lo + AUG;
+                aug_product<M>(BWD ? lo : hi, BWD ? hi : lo, out, lane);
+            }
+            __syncthreads();
+            if (p < np) aug_store<M>(fa + p * AUG, out, lane);
+            __syncthreads();
+        }
+        if (cnt & 1) {  // the odd factor moves up unchanged (slot np < cnt - 1)
+            for (int idx = tid; idx < AUG; idx += CS::THREADS) fa[np * AUG + idx] = fa[(cnt - 1) * AUG + idx];
+            __syncthreads();
+        }
+        cnt = np + (cnt & 1);
+    }
+    double *ag = aggbuf + gid * (MM + M);
+    for (int idx = tid; idx < MM; idx += CS::THREADS) {
+        if (!BWD) {
+            ag[idx] = fa[idx];
+        } else {  // row-major Psi: element idx = (i, j) from column j, row i
+            const int i = idx / M, j = idx - i * M;
+            ag[idx] = fa[j * M + i];
+        }
+    }
+    for (int idx = tid; idx < M; idx += CS::THREADS) ag[MM + idx] = fa[MM + idx];
+}
 
 // ---------------------------------------------------------------- forward
 

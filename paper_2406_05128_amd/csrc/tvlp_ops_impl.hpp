@@ -32,7 +32,7 @@ void Ops<M>::forward_t(const Bufs &w, const float *e, const float *a, const doub
         }
     } else {
         hipLaunchKernelGGL((k_fwd_local<M, FS::LPC, FS::CPL, FS::R, FR>), dim3((unsigned)w.gf.ngroups), dim3(64),
-                           dynf, st, w.S, w.gf, e, a, w.phiT, w.zbuf, w.aggf, w.chain);
+                           dynf, st, w.S, w.gf, e, a, w.phiT, w.zbuf);
     }
     tm.end();
     tm.begin("fwd_carry");
@@ -40,9 +40,13 @@ void Ops<M>::forward_t(const Bufs &w, const float *e, const float *a, const doub
     if (chain)
         hipLaunchKernelGGL((k_fwd_chain<M>), dim3((unsigned)w.S.n), dim3(CarryShape<M>::CHAIN_THREADS), 0, st, w.S, w.gf, zi, w.phiT, w.zbuf,
                            w.aggf, w.inclf, w.xs, chain, w.nonfinite);
-    else  // one block per group: its prefix of group maps, then its chunks
+    else {  // group maps, then one block per group: its prefix of group maps, then its chunks
+        hipLaunchKernelGGL((k_compose<M, FS::CPW, false>), dim3((unsigned)w.gf.ngroups),
+                           dim3(ComposeShape<M>::THREADS), compose_lds_bytes<M>(FS::CPW), st, w.S, w.gf, w.phiT,
+                           w.zbuf, w.aggf);
         hipLaunchKernelGGL((k_fwd_carry<M, FS::CPW>), dim3((unsigned)w.gf.ngroups), ct, 0, st, w.S, w.gf, zi,
                            w.phiT, w.zbuf, w.aggf, w.xs, w.nonfinite);
+    }
     tm.end();
     tm.begin("fwd_emit");
     if (!FR && !ti)  // per-sample rows: tiled row stream
@@ -77,20 +81,24 @@ void Ops<M>::backward_t(const Bufs &w, const float *g, const float *a, const flo
         const dim3 grid((unsigned)(w.gb.ngroups + nrun));
         if (tile)
             hipLaunchKernelGGL((k_bwd_front<M, RS::G, RS::R, FR, !FR>), grid, dim3(64), dynr, st, w.S, w.gb, g, a,
-                               w.phiT, w.qbuf, w.aggb, w.zero, w.chain, e, w.xs, w.sbuf, w.nch);
+                               w.qbuf, w.zero, e, w.xs, w.sbuf, w.nch);
         else
             hipLaunchKernelGGL((k_bwd_front<M, RS::G, RS::R, FR>), grid, dim3(64), dynr, st, w.S, w.gb, g, a,
-                               w.phiT, w.qbuf, w.aggb, w.zero, w.chain, e, w.xs, w.sbuf, w.nch);
+                               w.qbuf, w.zero, e, w.xs, w.sbuf, w.nch);
     } else if (tile) {
         hipLaunchKernelGGL((k_bwd_local<M, RS::G, RS::R, FR, !FR>), dim3((unsigned)w.gb.ngroups), dim3(64), dynr,
-                           st, w.S, w.gb, g, a, w.phiT, w.qbuf, w.aggb, w.zero, w.chain);
+                           st, w.S, w.gb, g, a, w.qbuf, w.zero);
     } else {
         hipLaunchKernelGGL((k_bwd_local<M, RS::G, RS::R, FR>), dim3((unsigned)w.gb.ngroups), dim3(64), dynr, st,
-                           w.S, w.gb, g, a, w.phiT, w.qbuf, w.aggb, w.zero, w.chain);
+                           w.S, w.gb, g, a, w.qbuf, w.zero);
     }
     tm.end();
     tm.begin("bwd_carry");
     const dim3 ct(CarryShape<M>::THREADS);
+    if (!w.chain)  // the groups' reverse maps
+        hipLaunchKernelGGL((k_compose<M, RS::CPW, true>), dim3((unsigned)w.gb.ngroups),
+                           dim3(ComposeShape<M>::THREADS), compose_lds_bytes<M>(RS::CPW), st, w.S, w.gb, w.phiT,
+                           w.qbuf, w.aggb);
     hipLaunchKernelGGL((k_bwd_chain<M>), dim3((unsigned)w.S.n), dim3(CarryShape<M>::CHAIN_THREADS), 0, st, w.S, w.gb, w.phiT, w.qbuf, w.aggb,
                        w.inclb, w.yend, gzi, w.chain, w.nonfinite);
     if (!w.chain)

@@ -3,16 +3,14 @@
 // Forward (k_fwd_local).  A wave owns a group of CPW consecutive chunks of one
 // sequence.  It computes each chunk's transition (Phi_c, z_c) with the basis
 // pass (LPC lanes per chunk, CPL float64 columns per lane, coefficient rows
-// staged through LDS), stores Phi_c (column-major) and z_c, and composes the
-// group's affine map x(c0 + CPW) = P_G x(c0) + r_G in LDS.
+// staged through LDS) and stores Phi_c (column-major) and z_c.
 //
 // Adjoint (k_bwd_local).  The mirror image: per chunk the zero-terminal
-// adjoint response q_c (systolic push form of Eq. 12), stored, and the group's
-// reverse map y(c0) = Psi_G y(c0 + nk) + w_G with Psi_G the product of the
-// Phi_c^T.
+// adjoint response q_c (systolic push form of Eq. 12), stored.
 //
-// No wave waits on another; the carries across groups and the per-chunk
-// states are computed afterwards by the carry kernels (tvlp_carry.hpp).
+// No wave waits on another; group maps (grouped carry), the carries across
+// chunks and the per-chunk states are computed afterwards by the carry
+// kernels (tvlp_carry.hpp).
 #pragma once
 
 #include "tvlp_rerun.hpp"
@@ -152,8 +150,7 @@ struct FwdScanShape {
     static constexpr int STRIDE = ((RM + 1) / 2) * 2 + 2;  // floats per chunk slab
     // chunk slabs, per-row scalars, and a 2-float dummy target for masked writes
     static constexpr int SLAB_BYTES = (CPW * STRIDE + CPW * R + 2) * 4;
-    static constexpr int MAT_BYTES = (3 * M * M + 4 * M) * 8;
-    static constexpr int LDS_BYTES = RING_BYTES > MAT_BYTES ? RING_BYTES : MAT_BYTES;
+    static constexpr int LDS_BYTES = RING_BYTES;
 };
 
 // s_waitcnt immediate that waits for vmcnt <= n only (gfx9 encoding).
@@ -164,18 +161,12 @@ constexpr int waitcnt_vm(int n) { return (n & 0xF) | (0x7 << 4) | (0xF << 8) | (
 template <int M, int LPC, int CPL, int R, bool FR = false>
 __global__ __launch_bounds__(64) void k_fwd_local(
     Seqs S, Groups GR, const float *__restrict__ e, const float *__restrict__ a, double *__restrict__ phiT,
-    double *__restrict__ zbuf, double *__restrict__ aggbuf, int chain) {
+    double *__restrict__ zbuf) {
     using SH = FwdScanShape<M, LPC, CPL, R, FR>;
     constexpr int CPW = SH::CPW;
-    constexpr int MM = M * M;
     static_assert(M % R == 0, "slab rows must divide M");
     __shared__ __attribute__((aligned(16))) unsigned char lds_raw[SH::LDS_BYTES];
     extern __shared__ __attribute__((aligned(16))) unsigned char fwd_dyn[];
-    double *PT = reinterpret_cast<double *>(lds_raw);  // aggregate, column-major
-    double *FT = PT + MM;                              // current chunk's Phi, column-major
-    double *QT = FT + MM;                              // product scratch
-    double *vr = QT + MM;                              // aggregate offset
-    double *vz = vr + M;                               // chunk offset
 
     const int lane = threadIdx.x;
     const int64_t gid = blockIdx.x;
@@ -340,7 +331,7 @@ __global__ __launch_bounds__(64) void k_fwd_local(
             }
         }
         for (; t0 < L; t0 += M) block(std::false_type{});
-        __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));  // drain the look-ahead before the ring is reused
+        __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));  // no look-ahead DMA outlives the wave
         // Phi_c column-major to global (column j-1 = response to unit state s(cL-j)),
         // z_c (zero-state response, column 0) alongside
         if (act) {
@@ -357,50 +348,6 @@ __global__ __launch_bounds__(64) void k_fwd_local(
             }
         }
     }
-    __syncthreads();
-
-    // Writes chunk k's Phi (column-major) and z into FT / vz.
-    auto stage_chunk = [&](int k) {
-        if (slot == k) {
-#pragma unroll
-            for (int m = 0; m < CPL; ++m) {
-                const int col = sub * CPL + m;
-                if (col == 0) {
-#pragma unroll
-                    for (int q = 0; q < M; ++q) vz[q] = h[m][M - 1 - q];
-                } else if (col <= M) {
-#pragma unroll
-                    for (int q = 0; q < M; ++q) FT[(col - 1) * M + q] = h[m][M - 1 - q];
-                }
-            }
-        }
-        __syncthreads();
-    };
-
-    const bool last_group = (c0 + CPW >= v.C);
-    // ---- compose the group's map over its transition-carrying chunks (not in
-    // chained mode, where every carry is a matrix-vector product)
-    if (!last_group && !chain) {
-        // nbasis == CPW here
-        stage_chunk(0);
-        for (int q = lane; q < MM; q += 64) PT[q] = FT[q];
-        if (lane < M) vr[lane] = vz[lane];
-        __syncthreads();
-        for (int k = 1; k < nbasis; ++k) {
-            stage_chunk(k);
-            matmul_cm<M>(FT, PT, QT, lane);
-            double rn = 0.0;
-            if (lane < M) rn = matvec_cm<M>(FT, vr, vz[lane], lane);
-            __syncthreads();
-            for (int q = lane; q < MM; q += 64) PT[q] = QT[q];
-            if (lane < M) vr[lane] = rn;
-            __syncthreads();
-        }
-        // the group's map x(c0 + CPW) = P x(c0) + r (column-major matrix, then offset)
-        double *ag = aggbuf + gid * (MM + M);
-        for (int q = lane; q < MM; q += 64) ag[q] = PT[q];
-        if (lane < M) ag[MM + lane] = vr[lane];
-    }
 }
 
 // ---------------------------------------------------------------- adjoint scan
@@ -414,17 +361,15 @@ struct BwdScanShape {
     using RD = RingOf<M, CPW, true, FR>;
     using TD = TileOf<M, CPW, true, FrontTiles>;
     static constexpr int RING_BYTES = (TILE ? TD::FLOATS : RD::FLOATS) * 4;
-    static constexpr int MAT_BYTES = (3 * M * M + 4 * M + CPW * M) * 8;
-    static constexpr int LDS_BYTES = RING_BYTES > MAT_BYTES ? RING_BYTES : MAT_BYTES;
+    static constexpr int LDS_BYTES = RING_BYTES;
 };
 
 // One wave handles adjoint group tid_; lds_raw: SH::LDS_BYTES bytes of LDS;
 // FR: a holds frame-rate rows and frl is the frame staging area.
 template <int M, int G, int R, bool FR = false, bool TILE = false>
 __device__ __forceinline__ void bwd_local_group(Seqs S, Groups GR, const float *__restrict__ g_in,
-                                                const float *__restrict__ a, const double *__restrict__ phiT,
-                                                double *__restrict__ qbuf, double *__restrict__ aggbuf,
-                                                const float *__restrict__ zero, int chain, int64_t tid_,
+                                                const float *__restrict__ a, double *__restrict__ qbuf,
+                                                const float *__restrict__ zero, int64_t tid_,
                                                 unsigned char *lds_raw, unsigned char *frl = nullptr) {
     static_assert(!(TILE && FR), "frame-rate rows are produced in LDS, not tiled");
     using SH = BwdScanShape<M, G, R, FR, TILE>;
@@ -432,16 +377,7 @@ __device__ __forceinline__ void bwd_local_group(Seqs S, Groups GR, const float *
     using TD = typename SH::TD;
     constexpr int CPW = SH::CPW;
     constexpr int TPL = (M + G - 1) / G;
-    constexpr int MM = M * M;
     float *ring = reinterpret_cast<float *>(lds_raw);
-    double *PS = reinterpret_cast<double *>(lds_raw);  // aggregate Psi, row-major
-    double *FT = PS + MM;                              // Phi_k^T row-major (= Phi_k column-major)
-    double *QT = FT + MM;
-    double *vw = QT + MM;
-    double *vy = vw + M;
-    double *vt = vy + M;
-    double *vq = vt + M;  // [CPW][M] q of each chunk (filled after the slab phase)
-    (void)vt;
 
     const int lane = threadIdx.x;
     if (tid_ >= GR.ngroups) return;
@@ -453,7 +389,6 @@ __device__ __forceinline__ void bwd_local_group(Seqs S, Groups GR, const float *
     const int64_t ng = groups_of(v.C, CPW);
     if (gr >= ng) return;  // slot beyond the real group count
     const int64_t g = ng - 1 - gr;
-    const int64_t gid = group_id(S, GR, b, g);
     const int64_t c0 = g * CPW;
     const int nk = (int)min((int64_t)CPW, v.C - c0);
 
@@ -530,83 +465,23 @@ __device__ __forceinline__ void bwd_local_group(Seqs S, Groups GR, const float *
             gx = ngx;
         });
     }
-    __syncthreads();
-    // q_c[i-1] = p(-i): lane slot (tap i) -> LDS and global
+    // q_c[i-1] = p(-i): lane slot (tap i)
     if (act) {
 #pragma unroll
         for (int m = 0; m < TPL; ++m) {
             const int i = r * TPL + m + 1;
-            if (i <= M) {
-                vq[slot * M + (i - 1)] = P[m];
-                qbuf[(v.cbase + c) * M + (i - 1)] = P[m];
-            }
+            if (i <= M) qbuf[(v.cbase + c) * M + (i - 1)] = P[m];
         }
-    }
-    __syncthreads();
-
-    // Phi_{c0+k}^T (row-major) goes through registers: the next chunk's matrix
-    // is fetched while the current one is used, then committed to FT.
-    constexpr int PF = (MM + 63) / 64;
-    double pre[PF];
-    auto fetch_phi = [&](int k) {
-        const double *src = phiT + (v.cbase + c0 + k) * MM;
-#pragma unroll
-        for (int q = 0; q < PF; ++q) {
-            const int idx = lane + 64 * q;
-            pre[q] = src[idx < MM ? idx : 0];
-        }
-    };
-    auto commit_phi = [&]() {
-#pragma unroll
-        for (int q = 0; q < PF; ++q) {
-            const int idx = lane + 64 * q;
-            if (idx < MM) FT[idx] = pre[q];
-        }
-        __syncthreads();
-    };
-
-    // ---- reverse map of the group: y(c0) = Psi y(c0+nk) + w (not in chained mode)
-    if (g > 0 && !chain) {
-        // start from the group's last chunk
-        const int kl = nk - 1;
-        const bool kl_has_phi = (c0 + kl) < v.C - 1;
-        if (kl_has_phi) {
-            fetch_phi(kl);
-            commit_phi();
-            for (int q = lane; q < MM; q += 64) PS[q] = FT[q];
-        } else {
-            for (int q = lane; q < MM; q += 64) PS[q] = 0.0;
-        }
-        if (lane < M) vw[lane] = vq[kl * M + lane];
-        if (kl > 0) fetch_phi(kl - 1);
-        __syncthreads();
-        for (int k = kl - 1; k >= 0; --k) {
-            commit_phi();
-            if (k > 0) fetch_phi(k - 1);
-            matmul_rm<M>(FT, PS, QT, lane);
-            double wn = 0.0;
-            if (lane < M) wn = matvec_rm<M>(FT, vw, vq[k * M + lane], lane);
-            __syncthreads();
-            for (int q = lane; q < MM; q += 64) PS[q] = QT[q];
-            if (lane < M) vw[lane] = wn;
-            __syncthreads();
-        }
-        // the group's reverse map y(c0) = Psi y(c0 + nk) + w (row-major matrix, then offset)
-        double *ag = aggbuf + gid * (MM + M);
-        for (int q = lane; q < MM; q += 64) ag[q] = PS[q];
-        if (lane < M) ag[MM + lane] = vw[lane];
     }
 }
 
 template <int M, int G, int R, bool FR = false, bool TILE = false>
 __global__ __launch_bounds__(64) void k_bwd_local(Seqs S, Groups GR, const float *__restrict__ g_in,
-                                                  const float *__restrict__ a, const double *__restrict__ phiT,
-                                                  double *__restrict__ qbuf, double *__restrict__ aggbuf,
-                                                  const float *__restrict__ zero, int chain) {
+                                                  const float *__restrict__ a, double *__restrict__ qbuf,
+                                                  const float *__restrict__ zero) {
     __shared__ __attribute__((aligned(16))) unsigned char lds_raw[BwdScanShape<M, G, R, FR, TILE>::LDS_BYTES];
     extern __shared__ __attribute__((aligned(16))) unsigned char bwd_dyn[];  // FR: frame staging
-    bwd_local_group<M, G, R, FR, TILE>(S, GR, g_in, a, phiT, qbuf, aggbuf, zero, chain, blockIdx.x, lds_raw,
-                                       bwd_dyn);
+    bwd_local_group<M, G, R, FR, TILE>(S, GR, g_in, a, qbuf, zero, blockIdx.x, lds_raw, bwd_dyn);
 }
 
 // The adjoint's local scan together with the recompute of s from the saved
@@ -615,9 +490,8 @@ __global__ __launch_bounds__(64) void k_bwd_local(Seqs S, Groups GR, const float
 // latencies overlap.  Blocks alternate (scan, rerun) while both kinds remain.
 template <int M, int G, int R, bool FR = false, bool TILE = false>
 __global__ __launch_bounds__(64) void k_bwd_front(Seqs S, Groups GR, const float *__restrict__ g_in,
-                                                  const float *__restrict__ a, const double *__restrict__ phiT,
-                                                  double *__restrict__ qbuf, double *__restrict__ aggbuf,
-                                                  const float *__restrict__ zero, int chain,
+                                                  const float *__restrict__ a, double *__restrict__ qbuf,
+                                                  const float *__restrict__ zero,
                                                   const float *__restrict__ e, const double *__restrict__ xs,
                                                   float *__restrict__ s_out, int64_t nch) {
     constexpr int B1 = BwdScanShape<M, G, R, FR, TILE>::LDS_BYTES, B2 = RerunLds<M, G, FR, TILE, FrontTiles>::BYTES;
@@ -636,8 +510,7 @@ __global__ __launch_bounds__(64) void k_bwd_front(Seqs S, Groups GR, const float
         j = i - both;
     }
     if (scan)
-        bwd_local_group<M, G, R, FR, TILE>(S, GR, g_in, a, phiT, qbuf, aggbuf, zero, chain, j, lds_raw,
-                                           front_dyn);
+        bwd_local_group<M, G, R, FR, TILE>(S, GR, g_in, a, qbuf, zero, j, lds_raw, front_dyn);
     else
         rerun_chunks<M, G, FR, TILE, FrontTiles>(S, e, a, xs, s_out, nullptr, zero, nch, j,
                                                  reinterpret_cast<float *>(lds_raw), nullptr, front_dyn);
