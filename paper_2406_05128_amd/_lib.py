@@ -138,6 +138,22 @@ def check_sf(code: int) -> int:
     return code
 
 
+_BUILD_ID = None
+
+
+def build_id() -> str:
+    """Short content hash of the libtvlp.so file this process loads."""
+    global _BUILD_ID
+    if _BUILD_ID is None:
+        import hashlib
+        h = hashlib.sha256()
+        with open(LIB_PATH, "rb") as f:
+            for block in iter(lambda: f.read(1 << 20), b""):
+                h.update(block)
+        _BUILD_ID = h.hexdigest()[:16]
+    return _BUILD_ID
+
+
 def version() -> str:
     return load().lp_version().decode()
 

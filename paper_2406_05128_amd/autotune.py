@@ -1,7 +1,8 @@
 """Persistent cache of chunk lengths chosen by the native autotuner (lp_plan_autotune).
 
-One JSON object per file: {"<device>|M=<M>|B=<B>|T=<T>[|carry=<constraint>]":
-{"chunk": L, "chained": bool, "ms": t}}.
+One JSON object per file: {"<device>|M=<M>|B=<B>|T=<T>[|carry=<constraint>][|lib=<id>]":
+{"chunk": L, "chained": bool, "ms": t}}.  The library id names the build the
+choice was measured with, so a rebuilt library (other kernels) tunes afresh.
 Writes go through a temporary file and an atomic rename.
 """
 from __future__ import annotations
@@ -17,9 +18,11 @@ def cache_path() -> str:
                           os.path.join(os.path.expanduser("~"), ".cache", "tvlp", "autotune.json"))
 
 
-def cache_key(device_name: str, M: int, B: int, T: int, carry: str = "grouped") -> str:
+def cache_key(device_name: str, M: int, B: int, T: int, carry: str = "grouped", lib: str = "") -> str:
     key = f"{device_name}|M={int(M)}|B={int(B)}|T={int(T)}"
-    return key if carry == "grouped" else f"{key}|carry={carry}"
+    if carry != "grouped":
+        key = f"{key}|carry={carry}"
+    return f"{key}|lib={lib}" if lib else key
 
 
 def _read(path: str) -> dict:

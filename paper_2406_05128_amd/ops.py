@@ -135,14 +135,14 @@ class Plan:
         """Pick the fastest chunk length (and, unless fixed, carry mode) for a B x T
         forward + adjoint step (lp_plan_autotune).
 
-        Results are cached per (device name, M, B, T, carry constraint) in a JSON file
+        Results are cached per (device name, M, B, T, carry constraint, library build) in a JSON file
         ($TVLP_AUTOTUNE_CACHE, default ~/.cache/tvlp/autotune.json); a cached
         entry is applied without measuring.  Returns {"chunk", "chained", "ms", "cached"}.
         """
         from . import autotune as _at
         constraint = ("high-radius" if self.high_radius
                       else (("chained" if self.chained else "grouped") if self._carry_fixed else "free"))
-        key = _at.cache_key(torch.cuda.get_device_name(self.device), self.M, B, T, constraint)
+        key = _at.cache_key(torch.cuda.get_device_name(self.device), self.M, B, T, constraint, _lib.build_id())
         if cache:
             hit = _at.lookup(key)
             if hit is not None:

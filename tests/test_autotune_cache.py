@@ -15,8 +15,17 @@ def test_cache_roundtrip(tmp_path, monkeypatch):
     assert at.lookup(k1) == {"chunk": 264, "chained": True, "ms": 0.9}
     assert at.lookup(k2) == {"chunk": 128, "chained": False, "ms": 0.05}
     assert set(json.loads(path.read_text())) == {k1, k2}
-    # the carry constraint is part of the key
+    # the carry constraint and the library build are part of the key
     assert at.cache_key("d", 22, 64, 48000, "free") != at.cache_key("d", 22, 64, 48000)
+    assert at.cache_key("d", 22, 64, 48000, lib="a") != at.cache_key("d", 22, 64, 48000, lib="b")
+    assert at.cache_key("d", 22, 64, 48000, lib="a").endswith("|lib=a")
+
+
+def test_build_id_names_the_library_file():
+    from paper_2406_05128_amd import _lib
+    bid = _lib.build_id()
+    assert len(bid) == 16 and int(bid, 16) >= 0
+    assert _lib.build_id() == bid
 
 
 def test_corrupt_or_invalid_entries_are_ignored(tmp_path, monkeypatch):
