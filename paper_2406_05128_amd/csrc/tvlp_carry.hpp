@@ -323,6 +323,7 @@ __global__ __launch_bounds__(512) void k_fwd_chain(Seqs S, Groups GR, const doub
     };
     double x = (wv == 0 && lane < M && zi) ? zi[b * M + lane] : 0.0;
     stage(0, tid, CS::CHAIN_THREADS);
+    if (wv == 0) __builtin_amdgcn_s_setprio(2);  // the serial wave issues ahead of the staging waves
     __syncthreads();
     for (int64_t bi = 0; bi < nbatch; ++bi) {
         if (wv == 0) {
@@ -391,6 +392,7 @@ __global__ __launch_bounds__(512) void k_bwd_chain(Seqs S, Groups GR, const doub
     };
     double x = 0.0;
     stage(0, tid, CS::CHAIN_THREADS);
+    if (wv == 0) __builtin_amdgcn_s_setprio(2);  // the serial wave issues ahead of the staging waves
     __syncthreads();
     for (int64_t bi = 0; bi < nbatch; ++bi) {
         if (wv == 0) {

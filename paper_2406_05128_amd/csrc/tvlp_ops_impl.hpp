@@ -32,7 +32,7 @@ void Ops<M>::forward_t(const Bufs &w, const float *e, const float *a, const doub
         }
     } else {
         hipLaunchKernelGGL((k_fwd_local<M, FS::LPC, FS::CPL, FS::R, FR>), dim3((unsigned)w.gf.ngroups), dim3(64),
-                           dynf, st, w.S, w.gf, e, a, w.phiT, w.zbuf);
+                           dynf, st, w.S, w.gf, e, a, w.phiT, w.zbuf, w.zero);
     }
     tm.end();
     tm.begin("fwd_carry");

@@ -161,7 +161,7 @@ constexpr int waitcnt_vm(int n) { return (n & 0xF) | (0x7 << 4) | (0xF << 8) | (
 template <int M, int LPC, int CPL, int R, bool FR = false>
 __global__ __launch_bounds__(64) void k_fwd_local(
     Seqs S, Groups GR, const float *__restrict__ e, const float *__restrict__ a, double *__restrict__ phiT,
-    double *__restrict__ zbuf) {
+    double *__restrict__ zbuf, const float *__restrict__ zero) {
     using SH = FwdScanShape<M, LPC, CPL, R, FR>;
     constexpr int CPW = SH::CPW;
     static_assert(M % R == 0, "slab rows must divide M");
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(64) void k_fwd_local(
 #pragma unroll
         for (int i = 0; i < SH::DMA_N; ++i) {
             const int j = 64 * i + lane;
-            const float *p = e;  // valid dummy for unused slots
+            const float *p = zero;  // unused slot words stay zero
             int st = 0;
             if constexpr (FR) {
                 if (lane < CPW && lane < nbasis) {  // excitation of chunk `lane`
@@ -267,13 +267,18 @@ __global__ __launch_bounds__(64) void k_fwd_local(
         };
         // row t's coefficients and excitation (ring slot slotn; FR: produced row
         // rk), read during step t-1
+        // the excitation word a lane reads: its chunk's for the zero-state column
+        // (sub 0), else a slot word that is always zero (ZW), so that the
+        // column's start needs no select
+        constexpr bool ZW = FR ? (CPW < 64) : (SH::ROWF < SLOTF);
+        const int exo = (ZW && sub != 0) ? (FR ? CPW : SH::ROWF) : SH::XOFF + (slot < CPW ? slot : 0);
         auto load_row = [&](int slotn, int rk, float (&rv)[M], float &ex) {
             const float *slotp = ring + slotn * SLOTF;
             const float *row = FR ? rows + rk * SH::CW + (slot < CPW ? slot : 0) * M
                                   : slotp + (slot < CPW ? slot : 0) * M;
 #pragma unroll
             for (int i = 0; i < M; ++i) rv[i] = row[i];
-            ex = slotp[SH::XOFF + (slot < CPW ? slot : 0)];
+            ex = slotp[exo];
         };
         for (int t = 0; t < SH::D; ++t) issue(t, t % SH::NS);
         __builtin_amdgcn_s_waitcnt(waitcnt_vm(SH::DMA_N * (SH::D - 1)));  // row 0 has landed
@@ -301,7 +306,7 @@ __global__ __launch_bounds__(64) void k_fwd_local(
                 // latency), oldest tap first so that the newest output enters last
                 double acc[CPL];
 #pragma unroll
-                for (int m = 0; m < CPL; ++m) acc[m] = (m == 0 && sub == 0) ? (double)ex : 0.0;
+                for (int m = 0; m < CPL; ++m) acc[m] = m == 0 && (ZW || sub == 0) ? (double)ex : 0.0;
 #pragma unroll
                 for (int i = M; i >= 1; --i) {
                     const double ai = (double)rv[i - 1];
