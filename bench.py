@@ -34,12 +34,12 @@ FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published
 # in both carry modes (the carry mode only changes the carry kernels between them).  Valid
 # only for the kernel sources (hash below) they were measured with, otherwise null.
 TRAFFIC = {
-    "sources_sha256": "eaf284128d8329076b63c1b0c859f0abe76dc441229eebff0cb752bd1742a6bc",
+    "sources_sha256": "b8f9e3e7f75b301c444f5daf9becc916b090ec2637f0fd68b7ede98278ac55d5",
     "measured_with_carry": "chained",
     "bytes_by_chunk": {
-        396: {"fwd_scan": 319438208, "fwd_emit": 320342582, "bwd_scan": 626960870, "bwd_emit": 582729837},
-        418: {"fwd_scan": 315231539, "fwd_emit": 319103965, "bwd_scan": 625157684, "bwd_emit": 582695877},
-        440: {"fwd_scan": 314843686, "fwd_emit": 314744540, "bwd_scan": 612837655, "bwd_emit": 581679478},
+        396: {"fwd_scan": 319471639, "fwd_emit": 320338984, "bwd_scan": 627078447, "bwd_emit": 582765179},
+        418: {"fwd_scan": 315444595, "fwd_emit": 319099050, "bwd_scan": 625062136, "bwd_emit": 582684787},
+        440: {"fwd_scan": 314951411, "fwd_emit": 314752677, "bwd_scan": 612901999, "bwd_emit": 581694525},
     },
 }
 
