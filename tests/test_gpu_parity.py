@@ -178,6 +178,16 @@ def test_training_shape_full_size(tv):
     print("train_b64_t48000_m22 gated:", errs)
 
 
+@pytest.mark.parametrize("chained", [False, True])
+def test_training_shape_bench_launch(tv, chained):
+    """The bench's launch configuration at the training shape (L=418, which the
+    autotuner picks there, in either carry mode): every sequence vs the oracle,
+    gated inputs."""
+    e, a, g = workload("train_b64_t48000_m22", gamma=0.98)
+    errs = check_all(tv, e, a, g, chunk=418, chained=chained)
+    print("train_b64_t48000_m22 L=418", "chained" if chained else "group maps", errs)
+
+
 def test_training_shape_literal_inputs_reported(tv):
     """Literal (gamma = 1) inputs: error reported, not gated (poles up to ~0.9999)."""
     e, a, g = workload("train_b64_t48000_m22", gamma=1.0, B=8)
