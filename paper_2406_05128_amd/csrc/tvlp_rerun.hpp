@@ -823,6 +823,7 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
             while (tb != NONE) {
                 float nd = (float)n;
                 const int t_start = t;
+#pragma unroll 8
                 for (; t < tb; ++t) {
                     const float gt = gsh[t];
                     const float gn = gt * nd;
@@ -869,6 +870,7 @@ __global__ __launch_bounds__(64) void k_adj_emit2(Seqs S, const float *__restric
         double acc[TPL];
 #pragma unroll
         for (int m = 0; m < TPL; ++m) acc[m] = 0.0;
+#pragma unroll 8
         for (int t = 0; t < (int)len; ++t) {
             const double gt = (double)gsh[t];
 #pragma unroll
