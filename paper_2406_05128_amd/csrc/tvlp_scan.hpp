@@ -237,7 +237,7 @@ __global__ __launch_bounds__(64) void k_fwd_local(
         const float *rows = ring + SH::NS * SLOTF;
         FrameCoefs<M, CPW, false> fc;
         auto produce_block = [&]() {
-#pragma unroll 1
+#pragma unroll 2
             for (int k = 0; k < M; ++k) fc.produce(rows_l + k * SH::CW);
         };
         if constexpr (FR) {
