@@ -34,12 +34,12 @@ FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published
 # in both carry modes (the carry mode only changes the carry kernels between them).  Valid
 # only for the kernel sources (hash below) they were measured with, otherwise null.
 TRAFFIC = {
-    "sources_sha256": "b8f9e3e7f75b301c444f5daf9becc916b090ec2637f0fd68b7ede98278ac55d5",
+    "sources_sha256": "7bbcf0e667e9fa44b03685a8364a6dce77d618230907880bae0c86b906655021",
     "measured_with_carry": "chained",
     "bytes_by_chunk": {
-        396: {"fwd_scan": 319471639, "fwd_emit": 320338984, "bwd_scan": 627078447, "bwd_emit": 582765179},
-        418: {"fwd_scan": 315444595, "fwd_emit": 319099050, "bwd_scan": 625062136, "bwd_emit": 582684787},
-        440: {"fwd_scan": 314951411, "fwd_emit": 314752677, "bwd_scan": 612901999, "bwd_emit": 581694525},
+        396: {"fwd_scan": 319319651, "fwd_emit": 320341857, "bwd_scan": 627108829, "bwd_emit": 582755662},
+        418: {"fwd_scan": 315205443, "fwd_emit": 319096997, "bwd_scan": 625207172, "bwd_emit": 582656058},
+        440: {"fwd_scan": 315031803, "fwd_emit": 314747676, "bwd_scan": 612763442, "bwd_emit": 581678855},
     },
 }
 
