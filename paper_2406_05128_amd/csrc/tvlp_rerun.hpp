@@ -231,18 +231,32 @@ struct FrameCoefs {
             inf[slot] = fi;
         }
         __syncthreads();
+        // every load of a round is issued before its LDS writes (one memory
+        // latency per round of eight words per lane instead of one per word)
         const int n_all = CPW * nfr * M;
-        for (int idx = lane; idx < n_all; idx += 64) {
-            const int k = idx / (nfr * M);
-            const int rem = idx - k * nfr * M;
-            const int qq = rem / M, f = rem - qq * M;
-            const FrameInfo fi = inf[k];
-            float v = 0.f;
-            if (fi.len > 0) {
-                const int64_t q = min(fi.q0 + qq, S.F - 1);
-                v = A[fi.arow + q * M + f];
+        constexpr int U = 8;
+        for (int idx0 = lane; idx0 < n_all; idx0 += 64 * U) {
+            float v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int idx = idx0 + 64 * u;
+                v[u] = 0.f;
+                if (idx < n_all) {
+                    const int k = idx / (nfr * M);
+                    const int rem = idx - k * nfr * M;
+                    const int qq = rem / M, f = rem - qq * M;
+                    const FrameInfo fi = inf[k];
+                    if (fi.len > 0) {
+                        const int64_t q = min(fi.q0 + qq, S.F - 1);
+                        v[u] = A[fi.arow + q * M + f];
+                    }
+                }
             }
-            st[idx] = v;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int idx = idx0 + 64 * u;
+                if (idx < n_all) st[idx] = v[u];
+            }
         }
         __syncthreads();
         rows = st;
