@@ -34,12 +34,12 @@ FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published
 # in both carry modes (the carry mode only changes the carry kernels between them).  Valid
 # only for the kernel sources (hash below) they were measured with, otherwise null.
 TRAFFIC = {
-    "sources_sha256": "7bbcf0e667e9fa44b03685a8364a6dce77d618230907880bae0c86b906655021",
+    "sources_sha256": "e99cf2c7041347679ae1333fe7dcd2eee1640d750be883a827ce9f4f7bd6f2f1",
     "measured_with_carry": "chained",
     "bytes_by_chunk": {
-        396: {"fwd_scan": 319319651, "fwd_emit": 320341857, "bwd_scan": 627108829, "bwd_emit": 582755662},
-        418: {"fwd_scan": 315205443, "fwd_emit": 319096997, "bwd_scan": 625207172, "bwd_emit": 582656058},
-        440: {"fwd_scan": 315031803, "fwd_emit": 314747676, "bwd_scan": 612763442, "bwd_emit": 581678855},
+        396: {"fwd_scan": 319647619, "fwd_emit": 320340091, "bwd_scan": 626953308, "bwd_emit": 582718385},
+        418: {"fwd_scan": 315348773, "fwd_emit": 319095591, "bwd_scan": 625222386, "bwd_emit": 582657398},
+        440: {"fwd_scan": 315060035, "fwd_emit": 314747454, "bwd_scan": 612846050, "bwd_emit": 581660965},
     },
 }
 
