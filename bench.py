@@ -778,9 +778,12 @@ def main():
     for name, (ms, n) in tims.items():
         avg_us = 1e3 * ms / max(n, 1)
         by = kernel_bytes(name, B, T, M, L)
+        tr = measured_traffic(name, L)  # HBM bytes per launch from the counters, or None
         kernels[name] = {"avg_us": round(avg_us, 2), "launches": n,
                          "alg_bytes": by or None,
-                         "alg_GBps": round(by / (avg_us * 1e-6) / 1e9, 1) if by else None}
+                         "alg_GBps": round(by / (avg_us * 1e-6) / 1e9, 1) if by else None,
+                         "traffic": tr,
+                         "traffic_GBps": round(tr / (avg_us * 1e-6) / 1e9, 1) if tr else None}
     # the path is bound by HBM (a scan with no dense contraction): the roofline names the
     # kernel with the longest average launch, against the HBM peak, with its share of the
     # step's algorithmic bytes
