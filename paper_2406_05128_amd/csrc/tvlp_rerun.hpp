@@ -1060,8 +1060,18 @@ __global__ __launch_bounds__(256) void k_ti_phi(Seqs S, const float *__restrict_
         if (n & 1) mul_into(R, P);
         if (n > 1) mul_into(P, P);
     }
+    // every transition slot gets the same matrix: each thread keeps its entries
+    // in registers and writes them chunk by chunk (coalesced across threads)
     double *dst = phiT + v.cbase * MM;
-    for (int64_t q = tid; q < nt * MM; q += nth) dst[q] = R[q % MM];
+    for (int q = tid; q < MM; q += nth) {
+        const double r = R[q];
+        int64_t c = 0;
+        for (; c + 4 <= nt; c += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) dst[(c + u) * MM + q] = r;
+        }
+        for (; c < nt; ++c) dst[c * MM + q] = r;
+    }
 }
 
 // Zero-state offsets z_c of every chunk (time-invariant forward): the rerun from
