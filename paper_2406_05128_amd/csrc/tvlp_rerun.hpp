@@ -1047,10 +1047,17 @@ __global__ __launch_bounds__(256) void k_ti_phi(Seqs S, const float *__restrict_
     auto mul_into = [&](double *X, const double *Y) {  // X <- X Y
         for (int q = tid; q < MM; q += nth) {
             const int j = q / M, k = q % M;
-            double acc = 0.0;
-#pragma unroll 2
-            for (int i = 0; i < M; ++i) acc = fma(X[i * M + k], Y[j * M + i], acc);
-            Q[q] = acc;
+            // fully unrolled, two partial sums: the LDS reads of the row and
+            // column are issued together rather than one dependent pair per tap
+            double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                if (i & 1)
+                    acc1 = fma(X[i * M + k], Y[j * M + i], acc1);
+                else
+                    acc0 = fma(X[i * M + k], Y[j * M + i], acc0);
+            }
+            Q[q] = acc0 + acc1;
         }
         __syncthreads();
         for (int q = tid; q < MM; q += nth) X[q] = Q[q];
