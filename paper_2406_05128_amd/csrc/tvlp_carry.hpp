@@ -286,6 +286,20 @@ __global__ __launch_bounds__(256) void k_compose(Seqs S, Groups GR, const double
     for (int idx = tid; idx < M; idx += CS::THREADS) ag[MM + idx] = fa[MM + idx];
 }
 
+// One chunk per sequence (uniform batches with T <= L, such as frames filtered
+// one by one): no chunk carries a transition, so the carries reduce to the
+// state at the only chunk's boundary, st[b] = zi[b] (forward entry state) or
+// zero (adjoint terminal state, zi null), and to clearing the per-sequence
+// flags that the emits set, as the carry kernels do.  n sequences of M values.
+template <int M>
+__global__ __launch_bounds__(256) void k_single_chunk_states(int64_t n, const double *__restrict__ zi,
+                                                             double *__restrict__ st,
+                                                             uint32_t *__restrict__ nonfinite) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < n * M) st[idx] = zi ? zi[idx] : 0.0;
+    if (nonfinite && idx < n) nonfinite[idx] = 0u;
+}
+
 // ---------------------------------------------------------------- forward
 
 // Chained: items are chunks (matrix Phi_c, offset z_c; output xs per chunk);

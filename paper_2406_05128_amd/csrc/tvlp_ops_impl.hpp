@@ -5,6 +5,10 @@
 
 namespace tvlp_host {
 
+// Uniform batches whose sequences fit one chunk (T <= L): no chunk carries a
+// transition and the carries reduce to k_single_chunk_states.
+inline bool single_chunk(const Seqs &S) { return !S.offsets && !S.starts && S.T <= S.L; }
+
 template <int M>
 void Ops<M>::forward(const Bufs &w, const float *e, const float *a, const double *zi, float *s, double *zf,
                     hipStream_t st, Timer &tm) {
@@ -23,31 +27,39 @@ void Ops<M>::forward_t(const Bufs &w, const float *e, const float *a, const doub
     const size_t dynf = FR ? frame_lds_bytes(FS::CPW, M, w.S.nf) : 0;
     // the forward rerun stages s in LDS ahead of the FR frame staging
     const size_t dynr = (FR ? frame_lds_bytes(RS::CPW, M, w.S.nf) : 0) + rerun_s_lds_bytes(RS::CPW, w.S.L);
-    tm.begin("fwd_scan");
-    if (ti) {
-        if (w.S.T > w.S.L) {  // some chunk carries a transition (uniform batches)
-            hipLaunchKernelGGL((k_ti_zs<M, RS::G>), dim3((unsigned)ceil_div(w.nch, RS::CPW)), dim3(64), 0, st,
-                               w.S, e, a, w.zbuf, w.zero, w.nch);
-            hipLaunchKernelGGL((k_ti_phi<M>), dim3((unsigned)w.S.n), dim3(256), 0, st, w.S, a, w.phiT);
-        }
+    if (single_chunk(w.S)) {
+        // no transitions: each sequence's only chunk starts from zi (or zero)
+        tm.begin("fwd_carry");
+        hipLaunchKernelGGL((k_single_chunk_states<M>), dim3((unsigned)ceil_div(w.S.n * M, 256)), dim3(256), 0, st,
+                           w.S.n, zi, w.xs, w.nonfinite);
+        tm.end();
     } else {
-        hipLaunchKernelGGL((k_fwd_local<M, FS::LPC, FS::CPL, FS::R, FR>), dim3((unsigned)w.gf.ngroups), dim3(64),
-                           dynf, st, w.S, w.gf, e, a, w.phiT, w.zbuf, w.zero);
+        tm.begin("fwd_scan");
+        if (ti) {
+            if (w.S.T > w.S.L) {  // some chunk carries a transition (uniform batches)
+                hipLaunchKernelGGL((k_ti_zs<M, RS::G>), dim3((unsigned)ceil_div(w.nch, RS::CPW)), dim3(64), 0, st,
+                                   w.S, e, a, w.zbuf, w.zero, w.nch);
+                hipLaunchKernelGGL((k_ti_phi<M>), dim3((unsigned)w.S.n), dim3(256), 0, st, w.S, a, w.phiT);
+            }
+        } else {
+            hipLaunchKernelGGL((k_fwd_local<M, FS::LPC, FS::CPL, FS::R, FR>), dim3((unsigned)w.gf.ngroups), dim3(64),
+                               dynf, st, w.S, w.gf, e, a, w.phiT, w.zbuf, w.zero);
+        }
+        tm.end();
+        tm.begin("fwd_carry");
+        const dim3 ct(CarryShape<M>::THREADS);
+        if (chain)
+            hipLaunchKernelGGL((k_fwd_chain<M>), dim3((unsigned)w.S.n), dim3(CarryShape<M>::CHAIN_THREADS), 0, st,
+                               w.S, w.gf, zi, w.phiT, w.zbuf, w.aggf, w.inclf, w.xs, chain, w.nonfinite);
+        else {  // group maps, then one block per group: its prefix of group maps, then its chunks
+            hipLaunchKernelGGL((k_compose<M, FS::CPW, false>), dim3((unsigned)w.gf.ngroups),
+                               dim3(ComposeShape<M>::THREADS), compose_lds_bytes<M>(FS::CPW), st, w.S, w.gf, w.phiT,
+                               w.zbuf, w.aggf);
+            hipLaunchKernelGGL((k_fwd_carry<M, FS::CPW>), dim3((unsigned)w.gf.ngroups), ct, 0, st, w.S, w.gf, zi,
+                               w.phiT, w.zbuf, w.aggf, w.xs, w.nonfinite);
+        }
+        tm.end();
     }
-    tm.end();
-    tm.begin("fwd_carry");
-    const dim3 ct(CarryShape<M>::THREADS);
-    if (chain)
-        hipLaunchKernelGGL((k_fwd_chain<M>), dim3((unsigned)w.S.n), dim3(CarryShape<M>::CHAIN_THREADS), 0, st, w.S, w.gf, zi, w.phiT, w.zbuf,
-                           w.aggf, w.inclf, w.xs, chain, w.nonfinite);
-    else {  // group maps, then one block per group: its prefix of group maps, then its chunks
-        hipLaunchKernelGGL((k_compose<M, FS::CPW, false>), dim3((unsigned)w.gf.ngroups),
-                           dim3(ComposeShape<M>::THREADS), compose_lds_bytes<M>(FS::CPW), st, w.S, w.gf, w.phiT,
-                           w.zbuf, w.aggf);
-        hipLaunchKernelGGL((k_fwd_carry<M, FS::CPW>), dim3((unsigned)w.gf.ngroups), ct, 0, st, w.S, w.gf, zi,
-                           w.phiT, w.zbuf, w.aggf, w.xs, w.nonfinite);
-    }
-    tm.end();
     tm.begin("fwd_emit");
     if (!FR && !ti)  // per-sample rows: tiled row stream
         hipLaunchKernelGGL((k_fwd_rerun2<M, RS::G, false, true>), dim3((unsigned)ceil_div(w.nch, RS::CPW)),
@@ -75,36 +87,45 @@ void Ops<M>::backward_t(const Bufs &w, const float *g, const float *a, const flo
     const size_t dynr = FR ? frame_lds_bytes(RS::CPW, M, w.S.nf) : 0;
     // per-sample rows (not frame-rate, not time-invariant): tiled row streams
     const bool tile = !FR && !w.S.ti;
-    tm.begin("bwd_scan");
-    if (emit && !s_in) {
-        const int64_t nrun = ceil_div(w.nch, RS::CPW);
-        const dim3 grid((unsigned)(w.gb.ngroups + nrun));
-        if (tile)
-            hipLaunchKernelGGL((k_bwd_front<M, RS::G, RS::R, FR, !FR>), grid, dim3(64), dynr, st, w.S, w.gb, g, a,
-                               w.qbuf, w.zero, e, w.xs, w.sbuf, w.nch);
-        else
-            hipLaunchKernelGGL((k_bwd_front<M, RS::G, RS::R, FR>), grid, dim3(64), dynr, st, w.S, w.gb, g, a,
-                               w.qbuf, w.zero, e, w.xs, w.sbuf, w.nch);
-    } else if (tile) {
-        hipLaunchKernelGGL((k_bwd_local<M, RS::G, RS::R, FR, !FR>), dim3((unsigned)w.gb.ngroups), dim3(64), dynr,
-                           st, w.S, w.gb, g, a, w.qbuf, w.zero);
+    if (emit && s_in && !gzi && single_chunk(w.S)) {
+        // one chunk per sequence with s given: the adjoint starts every chunk
+        // from the zero terminal state, and no local scan or carry is needed
+        tm.begin("bwd_carry");
+        hipLaunchKernelGGL((k_single_chunk_states<M>), dim3((unsigned)ceil_div(w.S.n * M, 256)), dim3(256), 0, st,
+                           w.S.n, (const double *)nullptr, w.yend, w.nonfinite);
+        tm.end();
     } else {
-        hipLaunchKernelGGL((k_bwd_local<M, RS::G, RS::R, FR>), dim3((unsigned)w.gb.ngroups), dim3(64), dynr, st,
-                           w.S, w.gb, g, a, w.qbuf, w.zero);
+        tm.begin("bwd_scan");
+        if (emit && !s_in) {
+            const int64_t nrun = ceil_div(w.nch, RS::CPW);
+            const dim3 grid((unsigned)(w.gb.ngroups + nrun));
+            if (tile)
+                hipLaunchKernelGGL((k_bwd_front<M, RS::G, RS::R, FR, !FR>), grid, dim3(64), dynr, st, w.S, w.gb, g, a,
+                                   w.qbuf, w.zero, e, w.xs, w.sbuf, w.nch);
+            else
+                hipLaunchKernelGGL((k_bwd_front<M, RS::G, RS::R, FR>), grid, dim3(64), dynr, st, w.S, w.gb, g, a,
+                                   w.qbuf, w.zero, e, w.xs, w.sbuf, w.nch);
+        } else if (tile) {
+            hipLaunchKernelGGL((k_bwd_local<M, RS::G, RS::R, FR, !FR>), dim3((unsigned)w.gb.ngroups), dim3(64), dynr,
+                               st, w.S, w.gb, g, a, w.qbuf, w.zero);
+        } else {
+            hipLaunchKernelGGL((k_bwd_local<M, RS::G, RS::R, FR>), dim3((unsigned)w.gb.ngroups), dim3(64), dynr, st,
+                               w.S, w.gb, g, a, w.qbuf, w.zero);
+        }
+        tm.end();
+        tm.begin("bwd_carry");
+        const dim3 ct(CarryShape<M>::THREADS);
+        if (!w.chain)  // the groups' reverse maps
+            hipLaunchKernelGGL((k_compose<M, RS::CPW, true>), dim3((unsigned)w.gb.ngroups),
+                               dim3(ComposeShape<M>::THREADS), compose_lds_bytes<M>(RS::CPW), st, w.S, w.gb, w.phiT,
+                               w.qbuf, w.aggb);
+        hipLaunchKernelGGL((k_bwd_chain<M>), dim3((unsigned)w.S.n), dim3(CarryShape<M>::CHAIN_THREADS), 0, st, w.S,
+                           w.gb, w.phiT, w.qbuf, w.aggb, w.inclb, w.yend, gzi, w.chain, w.nonfinite);
+        if (!w.chain)
+            hipLaunchKernelGGL((k_bwd_expand<M, RS::CPW>), dim3((unsigned)w.gb.ngroups), ct, 0, st, w.S, w.gb, w.phiT,
+                               w.qbuf, w.inclb, w.yend, gzi);
+        tm.end();
     }
-    tm.end();
-    tm.begin("bwd_carry");
-    const dim3 ct(CarryShape<M>::THREADS);
-    if (!w.chain)  // the groups' reverse maps
-        hipLaunchKernelGGL((k_compose<M, RS::CPW, true>), dim3((unsigned)w.gb.ngroups),
-                           dim3(ComposeShape<M>::THREADS), compose_lds_bytes<M>(RS::CPW), st, w.S, w.gb, w.phiT,
-                           w.qbuf, w.aggb);
-    hipLaunchKernelGGL((k_bwd_chain<M>), dim3((unsigned)w.S.n), dim3(CarryShape<M>::CHAIN_THREADS), 0, st, w.S, w.gb, w.phiT, w.qbuf, w.aggb,
-                       w.inclb, w.yend, gzi, w.chain, w.nonfinite);
-    if (!w.chain)
-        hipLaunchKernelGGL((k_bwd_expand<M, RS::CPW>), dim3((unsigned)w.gb.ngroups), ct, 0, st, w.S, w.gb, w.phiT,
-                           w.qbuf, w.inclb, w.yend, gzi);
-    tm.end();
     if (emit && FR) {
         const unsigned grid = (unsigned)ceil_div(w.nch, RS::CPW);
         const size_t dyn = emit_frame_lds_offset(RS::CPW, M, w.S.L) + dynr;
