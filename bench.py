@@ -34,12 +34,12 @@ FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published
 # in both carry modes (the carry mode only changes the carry kernels between them).  Valid
 # only for the kernel sources (hash below) they were measured with, otherwise null.
 TRAFFIC = {
-    "sources_sha256": "e99cf2c7041347679ae1333fe7dcd2eee1640d750be883a827ce9f4f7bd6f2f1",
+    "sources_sha256": "522e01cfdb5a0425a555d2ae6d2e4f4c24c18c2bbc068847a57c081a0ba01ad0",
     "measured_with_carry": "chained",
     "bytes_by_chunk": {
-        396: {"fwd_scan": 319647619, "fwd_emit": 320340091, "bwd_scan": 626953308, "bwd_emit": 582718385},
-        418: {"fwd_scan": 315348773, "fwd_emit": 319095591, "bwd_scan": 625222386, "bwd_emit": 582657398},
-        440: {"fwd_scan": 315060035, "fwd_emit": 314747454, "bwd_scan": 612846050, "bwd_emit": 581660965},
+        396: {"fwd_scan": 319921149, "fwd_emit": 320335761, "bwd_scan": 627060226, "bwd_emit": 582735419},
+        418: {"fwd_scan": 315712383, "fwd_emit": 319086666, "bwd_scan": 625226587, "bwd_emit": 582676001},
+        440: {"fwd_scan": 315259482, "fwd_emit": 314733194, "bwd_scan": 612818027, "bwd_emit": 581682165},
     },
 }
 
