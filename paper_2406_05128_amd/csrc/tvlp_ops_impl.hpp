@@ -9,6 +9,29 @@ namespace tvlp_host {
 // transition and the carries reduce to k_single_chunk_states.
 inline bool single_chunk(const Seqs &S) { return !S.offsets && !S.starts && S.T <= S.L; }
 
+// Compute units of the current device, cached per device (a launch heuristic
+// only: 256 on MI355X, the value assumed when the query fails).
+inline int device_cus() {
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cache[dev]) {
+        int n = 0;
+        cache[dev] = (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+                         ? n
+                         : 256;
+    }
+    return cache[dev];
+}
+
+// Rounds in which a grid of one-wave blocks runs when LDS (160 KB per CU on
+// gfx950) is what limits the waves per CU.
+inline int64_t lds_rounds(int64_t waves, size_t lds_per_wave) {
+    const int64_t per_cu = std::max<int64_t>(1, (int64_t)((160 * 1024) / std::max<size_t>(lds_per_wave, 1)));
+    const int64_t slots = per_cu * device_cus();
+    return (waves + slots - 1) / slots;
+}
+
 template <int M>
 void Ops<M>::forward(const Bufs &w, const float *e, const float *a, const double *zi, float *s, double *zf,
                     hipStream_t st, Timer &tm) {
@@ -25,8 +48,14 @@ void Ops<M>::forward_t(const Bufs &w, const float *e, const float *a, const doub
     const bool ti = !FR && w.S.ti;
     const int chain = ti ? 1 : w.chain;
     const size_t dynf = FR ? frame_lds_bytes(FS::CPW, M, w.S.nf) : 0;
-    // the forward rerun stages s in LDS ahead of the FR frame staging
-    const size_t dynr = (FR ? frame_lds_bytes(RS::CPW, M, w.S.nf) : 0) + rerun_s_lds_bytes(RS::CPW, w.S.L);
+    // the forward rerun stages s in LDS (ahead of the FR frame staging) for
+    // coalesced stores, unless the staging area would add a round of waves
+    const int64_t rwaves = ceil_div(w.nch, RS::CPW);
+    const size_t rfix = (FR ? frame_lds_bytes(RS::CPW, M, w.S.nf) : 0) +
+                        ((!FR && !ti) ? RerunLds<M, RS::G, false, true>::BYTES : RerunLds<M, RS::G, FR>::BYTES);
+    const size_t sstage = rerun_s_lds_bytes(RS::CPW, w.S.L);
+    const int stage_s = lds_rounds(rwaves, rfix + sstage) <= lds_rounds(rwaves, rfix) ? 1 : 0;
+    const size_t dynr = (FR ? frame_lds_bytes(RS::CPW, M, w.S.nf) : 0) + (stage_s ? sstage : 0);
     if (single_chunk(w.S)) {
         // no transitions: each sequence's only chunk starts from zi (or zero)
         tm.begin("fwd_carry");
@@ -63,10 +92,10 @@ void Ops<M>::forward_t(const Bufs &w, const float *e, const float *a, const doub
     tm.begin("fwd_emit");
     if (!FR && !ti)  // per-sample rows: tiled row stream
         hipLaunchKernelGGL((k_fwd_rerun2<M, RS::G, false, true>), dim3((unsigned)ceil_div(w.nch, RS::CPW)),
-                           dim3(64), dynr, st, w.S, e, a, w.xs, s, zf, w.zero, w.nch, w.nonfinite);
+                           dim3(64), dynr, st, w.S, e, a, w.xs, s, zf, w.zero, w.nch, w.nonfinite, stage_s);
     else
         hipLaunchKernelGGL((k_fwd_rerun2<M, RS::G, FR>), dim3((unsigned)ceil_div(w.nch, RS::CPW)), dim3(64), dynr,
-                           st, w.S, e, a, w.xs, s, zf, w.zero, w.nch, w.nonfinite);
+                           st, w.S, e, a, w.xs, s, zf, w.zero, w.nch, w.nonfinite, stage_s);
     tm.end();
 }
 

@@ -649,13 +649,15 @@ __global__ __launch_bounds__(64) void k_fwd_rerun2(Seqs S, const float *__restri
                                                    const double *__restrict__ xs,
                                                    float *__restrict__ s, double *__restrict__ zf,
                                                    const float *__restrict__ zero, int64_t nch,
-                                                   uint32_t *__restrict__ nonfinite) {
+                                                   uint32_t *__restrict__ nonfinite, int stage_s) {
     __shared__ __attribute__((aligned(16))) float ring[RerunLds<M, G, FR, TILE>::BYTES / 4];
-    // dynamic LDS: s staging [CPW][L] floats, then (FR) the frame staging area
+    // dynamic LDS: with stage_s the s staging area [CPW][L] floats (s written with
+    // coalesced stores after the loop, else as it is produced), then (FR) the
+    // frame staging area
     extern __shared__ __attribute__((aligned(16))) unsigned char rerun_dyn[];
     rerun_chunks<M, G, FR, TILE>(S, e, a, xs, s, zf, zero, nch, blockIdx.x, ring, nullptr,
-                                 rerun_dyn + rerun_s_lds_bytes(64 / G, S.L), reinterpret_cast<float *>(rerun_dyn),
-                                 nonfinite);
+                                 rerun_dyn + (stage_s ? rerun_s_lds_bytes(64 / G, S.L) : 0),
+                                 stage_s ? reinterpret_cast<float *>(rerun_dyn) : nullptr, nonfinite);
 }
 
 // Adjoint rerun of each chunk (push form of Eq. 12, descending), from the
