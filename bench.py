@@ -34,12 +34,12 @@ FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published
 # in both carry modes (the carry mode only changes the carry kernels between them).  Valid
 # only for the kernel sources (hash below) they were measured with, otherwise null.
 TRAFFIC = {
-    "sources_sha256": "522e01cfdb5a0425a555d2ae6d2e4f4c24c18c2bbc068847a57c081a0ba01ad0",
+    "sources_sha256": "0518989db867124d6318499a219066429b1230d358cb15d2f5e5c18762ecf01c",
     "measured_with_carry": "chained",
     "bytes_by_chunk": {
-        396: {"fwd_scan": 319921149, "fwd_emit": 320335761, "bwd_scan": 627060226, "bwd_emit": 582735419},
-        418: {"fwd_scan": 315712383, "fwd_emit": 319086666, "bwd_scan": 625226587, "bwd_emit": 582676001},
-        440: {"fwd_scan": 315259482, "fwd_emit": 314733194, "bwd_scan": 612818027, "bwd_emit": 581682165},
+        396: {"fwd_scan": 319674597, "fwd_emit": 320343252, "bwd_scan": 627050543, "bwd_emit": 582741050},
+        418: {"fwd_scan": 315566905, "fwd_emit": 319093989, "bwd_scan": 625221550, "bwd_emit": 582673912},
+        440: {"fwd_scan": 315229279, "fwd_emit": 314743010, "bwd_scan": 612850460, "bwd_emit": 581682640},
     },
 }
 
